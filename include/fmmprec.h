@@ -1,0 +1,177 @@
+/*
+ * fmmprec.h -- C ABI of the MI355X (gfx950) FMM-preconditioned Poisson solver.
+ *
+ * Method: Ibeid, Yokota, Pestana, Keyes, "Fast Multipole Preconditioners for
+ * Sparse Matrices Arising from Elliptic Equations" (arXiv:1308.3339).
+ *   - The linear system A x = b of Sec. 2.1 (eq. axb), here the 5-point
+ *     finite-difference Laplacian on the unit square with Dirichlet data.
+ *   - Only the action of the preconditioner P^{-1} is needed (Sec. 3.1), and
+ *     it is applied from the right.
+ *   - P^{-1} is the FMM-BEM preconditioner of Sec. 3.3 (Fig. 1): a volume
+ *     potential u_i = sum_j f_j G_ij (Sec. 5.1, eq. volume_integral) evaluated
+ *     by the FMM of Sec. 5, corrected by a boundary-element solve for zero
+ *     Dirichlet data (Sec. 4.1, eqs. ubound and uinter).
+ *   - Setup once, apply every iteration (Sec. 7.1: PCSetUp / PCApply).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers (hipMalloc'd or torch CUDA tensors)
+ *     unless stated otherwise.  `stream` is a hipStream_t passed as void*
+ *     (NULL = the default stream).
+ *   - Grid arrays are row-major n x n: node (i, j), i, j = 0..n-1, lives at
+ *     index j*n + i and at the point ((i+1)h, (j+1)h), h = 1/(n+1).
+ *   - Ring arrays hold the 4n Dirichlet nodes next to the grid (corners
+ *     excluded), counter-clockwise: bottom ((k+1)h, 0), right (1, (k+1)h),
+ *     top ((n-k)h, 1), left (0, (n-k)h); node s*n + k for side s, k = 0..n-1.
+ *   - nrhs > 1 means nrhs arrays stored back to back (stride n*n, or N).
+ *   - Ownership: the caller owns all input/output buffers and keeps them
+ *     alive until the stream work is done; the plan owns every workspace
+ *     (expansions, tables, boundary inverse, Krylov basis) and
+ *     fmm_destroy() frees it.
+ *   - fmm_apply / fmm_precond_apply / fmm_stencil_apply are asynchronous and
+ *     ordered on `stream`.  precond_gmres_solve synchronises `stream` before
+ *     it returns (its result struct lives on the host).
+ *   - A plan may be used by one stream at a time (calls that overlap on two
+ *     streams race on the plan's workspace).
+ *   - Errors are status codes; nothing is thrown across the ABI.  After a
+ *     negative status the outputs are undefined and fmm_last_error() holds a
+ *     message.
+ */
+#ifndef FMMPREC_H
+#define FMMPREC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan fmm_plan; /* opaque, library-owned */
+
+enum {
+    FMM_OK = 0,
+    FMM_NOT_CONVERGED = 1,  /* maxit spent; u holds the last iterate     */
+    FMM_ERR_ARG = -1,       /* an argument failed validation            */
+    FMM_ERR_DEVICE = -2,    /* a HIP call failed                        */
+    FMM_ERR_ALLOC = -3,     /* device or host allocation failed         */
+    FMM_ERR_NUMERIC = -4,   /* NaN/Inf met (right-hand side or Arnoldi) */
+    FMM_ERR_UNSUPPORTED = -5 /* valid request this build does not serve  */
+};
+
+typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
+
+typedef enum { FMM_FP64 = 0 } fmm_precision;
+
+/* The problem the plan is built for.
+ *   GRID:   n = interior points per side, n = 8 * 2^L (L >= 0); x, y unused.
+ *           The quadtree root is the square [h/2, 1-h/2]^2, whose leaves are
+ *           the 8 x 8 blocks of the grid.
+ *   POINTS: n = number of points N >= 1; x, y = DEVICE arrays of N
+ *           coordinates inside the root square [x0, x0+side] x [y0, y0+side]
+ *           (side > 0).  They are read during fmm_setup only.  The tree has
+ *           L = ceil(log4(N/64)) levels (at least 0); a point belongs to leaf
+ *           min(max(floor((x - x0)/side * 2^L), 0), 2^L - 1) per axis. */
+typedef struct {
+    int32_t kind;   /* fmm_kind */
+    int64_t n;
+    const double *x;
+    const double *y;
+    double x0, y0, side;
+} fmm_problem;
+
+/* FMM parameters.
+ *   p        number of expansion coefficients, M_0..M_{p-1} (Sec. 5.3), 2..20.
+ *   leaf     points per leaf side squared; must be 64 (8 x 8 grid blocks).
+ *   prec     fmm_precision; FMM_FP64 only.
+ *   bem      GRID: 1 = boundary correction on (Sec. 4), 0 = free-space
+ *            volume potential only.  Ignored for POINTS.
+ *   self_eps GRID: the singular self term is G_self = -(1/2pi) log(self_eps h)
+ *            (Sec. 4.2 smoothing read as a self-cell value); 0 selects the
+ *            default exp(-gamma)/(2 sqrt 2) = 0.1985..., which matches the
+ *            5-point lattice Green's function at short range. */
+typedef struct {
+    int32_t p;
+    int32_t leaf;
+    int32_t prec;
+    int32_t bem;
+    double self_eps;
+} fmm_params;
+
+/* Krylov parameters: tol > 0 (relative true residual ||b - Ax||/||b||),
+ * restart in [1, 32], maxit >= 1 (total inner iterations). */
+typedef struct {
+    double tol;
+    int32_t restart;
+    int32_t maxit;
+} gmres_params;
+
+/* HOST struct filled by precond_gmres_solve. */
+typedef struct {
+    int32_t iters;        /* inner iterations (= preconditioner applications) */
+    int32_t restarts;     /* completed restart cycles                         */
+    double est_rel_res;   /* Givens estimate at the last inner iteration      */
+    double true_rel_res;  /* ||b - A x|| / ||b|| recomputed at exit           */
+} gmres_result;
+
+/* Builds a plan (PCSetUp, Sec. 7.1): tree, operator tables, workspace and,
+ * for GRID with bem=1, the inverse of the boundary collocation matrix.
+ * `problem` and `params` are HOST pointers.  Synchronises `stream`.
+ * Returns FMM_OK and *out, or an error with *out = NULL. */
+int fmm_setup(const fmm_problem *problem, const fmm_params *params, void *stream,
+              fmm_plan **out);
+
+/* Volume potential by FMM (Sec. 5.1 eq. volume_integral, Sec. 5.3):
+ *   GRID:   u_i = sum_j q_j G(x_i - x_j) over the n*n nodes with
+ *           G = -(1/2pi) log r and the self term q_i G_self.
+ *   POINTS: u_i = sum_{j != i} q_j G(x_i - x_j) in the caller's point order.
+ * q and u hold nrhs arrays of n*n (GRID) or N (POINTS) doubles; u must not
+ * alias q. */
+int fmm_apply(fmm_plan *plan, const double *q, double *u, int nrhs, void *stream);
+
+/* z = P^{-1} r (PCApply, Sec. 3.3 Fig. 1), GRID plans only:
+ *   q = h^2 r (midpoint rule for the volume integral of Sec. 4.1),
+ *   phi = FMM volume potential of q at the interior and ring nodes,
+ *   bem=1: sigma = -S^{-1} phi_ring (collocation, Sec. 4.3) and
+ *          z = phi + sum_l h sigma_l G(x - y_l) by a second FMM pass;
+ *   bem=0: z = phi.
+ * r and z hold nrhs grids; z must not alias r. */
+int fmm_precond_apply(fmm_plan *plan, const double *r, double *z, int nrhs, void *stream);
+
+/* As fmm_precond_apply for one right-hand side, also returning the ring
+ * potential phi_ring (4n) and the boundary density sigma (4n) in ring order
+ * (sigma is left untouched when bem=0).  Either extra pointer may be NULL. */
+int fmm_precond_stages(fmm_plan *plan, const double *r, double *z, double *phi_ring,
+                       double *sigma, void *stream);
+
+/* w = A v, the 5-point Laplacian with zero Dirichlet data (Sec. 2.1):
+ * (Av)_ij = (4 v_ij - v_{i-1,j} - v_{i+1,j} - v_{i,j-1} - v_{i,j+1}) / h^2.
+ * GRID plans only; nrhs grids; w must not alias v. */
+int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void *stream);
+
+/* Solves A u = b with right-preconditioned FGMRES(restart) and P^{-1} of
+ * fmm_precond_apply (GRID plans only):
+ *   b = f + (boundary values g at the neighbouring ring nodes) / h^2,
+ *   f: n*n grid (device); g: 4n ring values (device) or NULL for zero data;
+ *   u: on entry the initial guess x0, on exit the solution;
+ *   stop when ||b - A u|| / ||b|| <= tol (Givens estimate, then confirmed
+ *   with an explicit residual; restart from the current u otherwise).
+ * Returns FMM_OK, FMM_NOT_CONVERGED (maxit spent; u = last iterate and *res
+ * valid) or an error.  `prm` and `res` are HOST pointers; prm may be NULL
+ * (tol 1e-8, restart 30, maxit 600); res may be NULL. */
+int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
+                        const gmres_params *prm, gmres_result *res, void *stream);
+
+/* Frees the plan and everything it owns.  NULL is accepted. */
+int fmm_destroy(fmm_plan *plan);
+
+/* Message for the last error on this plan (or of the last failed fmm_setup
+ * when plan is NULL).  The string is owned by the library. */
+const char *fmm_last_error(const fmm_plan *plan);
+
+/* Library version string, e.g. "fmmprec 0.1 gfx950". */
+const char *fmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMPREC_H */

@@ -1,0 +1,226 @@
+"""ctypes binding of libfmmprec.so.  The functions keep the C names; Plan is a
+thin owner of an fmm_plan*.  Device arrays are torch float64 CUDA tensors
+(contiguous); the stream is torch's current stream unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libfmmprec.so"
+
+FMM_OK, FMM_NOT_CONVERGED = 0, 1
+FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_ALLOC, FMM_ERR_NUMERIC, FMM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
+FMM_GRID, FMM_POINTS = 0, 1
+FMM_FP64 = 0
+
+# every symbol include/fmmprec.h declares
+exported_symbols = (
+    "fmm_setup", "fmm_apply", "fmm_precond_apply", "fmm_precond_stages", "fmm_stencil_apply",
+    "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version",
+)
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fmmprec error %d: %s" % (code, msg))
+        self.code = code
+
+
+class fmm_problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("side", ctypes.c_double)]
+
+
+class fmm_params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("bem", ctypes.c_int32), ("self_eps", ctypes.c_double)]
+
+
+class gmres_params(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+
+
+class gmres_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("est_rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(_PKG, _LIBNAME)
+
+
+def load_library():
+    """Load the in-tree libfmmprec.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise FmmError(FMM_ERR_DEVICE, "%s is not built (run paper_1308_3339_amd.build)" % path)
+    L = ctypes.CDLL(path)
+    vp, dp, i32 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int
+    L.fmm_setup.argtypes = [ctypes.POINTER(fmm_problem), ctypes.POINTER(fmm_params), vp,
+                            ctypes.POINTER(vp)]
+    L.fmm_setup.restype = i32
+    L.fmm_apply.argtypes = [vp, dp, dp, i32, vp]
+    L.fmm_apply.restype = i32
+    L.fmm_precond_apply.argtypes = [vp, dp, dp, i32, vp]
+    L.fmm_precond_apply.restype = i32
+    L.fmm_precond_stages.argtypes = [vp, dp, dp, dp, dp, vp]
+    L.fmm_precond_stages.restype = i32
+    L.fmm_stencil_apply.argtypes = [vp, dp, dp, i32, vp]
+    L.fmm_stencil_apply.restype = i32
+    L.precond_gmres_solve.argtypes = [vp, dp, dp, dp, ctypes.POINTER(gmres_params),
+                                      ctypes.POINTER(gmres_result), vp]
+    L.precond_gmres_solve.restype = i32
+    L.fmm_destroy.argtypes = [vp]
+    L.fmm_destroy.restype = i32
+    L.fmm_last_error.argtypes = [vp]
+    L.fmm_last_error.restype = ctypes.c_char_p
+    L.fmm_version.argtypes = []
+    L.fmm_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, name, numel=None):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must live on the GPU" % name)
+    if t.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s has %d elements, needs %d" % (name, t.numel(), numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(code, plan_ptr):
+    if code < 0:
+        msg = load_library().fmm_last_error(plan_ptr)
+        raise FmmError(code, msg.decode() if msg else "")
+    return code
+
+
+def fmm_version():
+    return load_library().fmm_version().decode()
+
+
+def fmm_last_error(plan=None):
+    p = plan._ptr if isinstance(plan, Plan) else plan
+    return load_library().fmm_last_error(p).decode()
+
+
+def fmm_setup(kind=FMM_GRID, n=64, p=10, bem=1, self_eps=0.0, x=None, y=None,
+              x0=0.0, y0=0.0, side=1.0, leaf=64, prec=FMM_FP64, stream=None):
+    L = load_library()
+    prob = fmm_problem(kind, n, None, None, x0, y0, side)
+    if kind == FMM_POINTS:
+        prob.x = _dptr(x, "x", n).value
+        prob.y = _dptr(y, "y", n).value
+    prm = fmm_params(p, leaf, prec, bem, self_eps)
+    out = ctypes.c_void_p()
+    code = L.fmm_setup(ctypes.byref(prob), ctypes.byref(prm), _stream(stream), ctypes.byref(out))
+    _check(code, None)
+    return Plan(out, kind, n, p, bem)
+
+
+def fmm_apply(plan, q, u, nrhs=1, stream=None):
+    N = plan.npts
+    code = load_library().fmm_apply(plan._ptr, _dptr(q, "q", N * nrhs), _dptr(u, "u", N * nrhs),
+                                    nrhs, _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def fmm_precond_apply(plan, r, z, nrhs=1, stream=None):
+    N = plan.npts
+    code = load_library().fmm_precond_apply(plan._ptr, _dptr(r, "r", N * nrhs),
+                                            _dptr(z, "z", N * nrhs), nrhs, _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def fmm_precond_stages(plan, r, z, phi_ring=None, sigma=None, stream=None):
+    N, m = plan.npts, 4 * plan.n
+    code = load_library().fmm_precond_stages(plan._ptr, _dptr(r, "r", N), _dptr(z, "z", N),
+                                             _dptr(phi_ring, "phi_ring", m),
+                                             _dptr(sigma, "sigma", m), _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def fmm_stencil_apply(plan, v, w, nrhs=1, stream=None):
+    N = plan.npts
+    code = load_library().fmm_stencil_apply(plan._ptr, _dptr(v, "v", N * nrhs),
+                                            _dptr(w, "w", N * nrhs), nrhs, _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, stream=None):
+    N = plan.npts
+    prm = gmres_params(tol, restart, maxit)
+    res = gmres_result()
+    code = load_library().precond_gmres_solve(plan._ptr, _dptr(f, "f", N),
+                                              _dptr(g, "g", 4 * plan.n), _dptr(u, "u", N),
+                                              ctypes.byref(prm), ctypes.byref(res),
+                                              _stream(stream))
+    _check(code, plan._ptr)
+    return {"status": code, "converged": code == FMM_OK, "iters": res.iters,
+            "restarts": res.restarts, "est_rel_res": res.est_rel_res,
+            "true_rel_res": res.true_rel_res}
+
+
+def fmm_destroy(plan):
+    if isinstance(plan, Plan):
+        plan.close()
+        return FMM_OK
+    return load_library().fmm_destroy(plan)
+
+
+class Plan:
+    """Owner of an fmm_plan*; methods mirror the C entry points."""
+
+    def __init__(self, ptr, kind, n, p, bem):
+        self._ptr = ptr
+        self.kind, self.n, self.p, self.bem = kind, n, p, bem
+        self.npts = n * n if kind == FMM_GRID else n
+
+    apply = fmm_apply
+    precond_apply = fmm_precond_apply
+    precond_stages = fmm_precond_stages
+    stencil_apply = fmm_stencil_apply
+    solve = precond_gmres_solve
+
+    def close(self):
+        if self._ptr is not None and self._ptr.value:
+            load_library().fmm_destroy(self._ptr)
+        self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,373 @@
+// C ABI of the gfx950 FMM-preconditioned Poisson solver: argument checks,
+// plan setup (PCSetUp of Sec. 7.1 of arXiv:1308.3339) and the entry points.
+//
+// The operator tables are built here on the host, in FP64, from the
+// translation formulas of Sec. 5.3 rewritten for level-scaled expansions:
+//   M2M (item 2):  M~par_n = -M~_0 c^n/n + sum_{k=1..n} 2^-k c^(n-k) C(n-1,k-1) M~_k,
+//                  c = (child - parent centre)/w_parent
+//   M2L (item 3):  Hankel generators H_0 = -log|d|, H_m = (m-1)!/d^m with
+//                  d = target minus source centre in cell widths, and the
+//                  scalings a_n = (-1)^n/n!, b_0 = -1, b_k = 1/(k-1)!
+//   P2M (item 1) / L2P (item 5) on the fixed 8x8 leaf pattern,
+//                  tau_j = (x_j - centre)/w_leaf
+//   near field     T(d) = log(h |d|) on the integer lattice, T(0) = log(eps h)
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmmprec {
+
+thread_local std::string g_setup_error;
+
+int fail(fmm_plan *plan, int code, const std::string &msg)
+{
+    if (plan) plan->err = msg;
+    else g_setup_error = msg;
+    return code;
+}
+
+int m2l_kernel_setup(fmm_plan *pl);  // fmm_grid.hip
+
+using cd = std::complex<double>;
+
+static double factorial(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+static double binom(int a, int b)
+{
+    if (b < 0 || b > a) return 0.0;
+    double r = 1.0;
+    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+    return std::floor(r + 0.5);
+}
+
+static cd ipow(cd z, int k)
+{
+    cd r = 1.0;
+    for (int i = 0; i < k; ++i) r *= z;
+    return r;
+}
+
+template <class T>
+static int upload(fmm_plan *pl, T **dst, const std::vector<T> &src)
+{
+    FMM_HIP(pl, hipMalloc(dst, src.size() * sizeof(T)));
+    FMM_HIP(pl, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FMM_OK;
+}
+
+static int build_tables(fmm_plan *pl)
+{
+    const int p = pl->p;
+    // M2M
+    std::vector<double2> m2m((size_t)4 * p * p, double2{0.0, 0.0});
+    for (int qd = 0; qd < 4; ++qd) {
+        const cd c(0.5 * ((qd & 1) - 0.5), 0.5 * ((qd >> 1) - 0.5));
+        for (int n = 0; n < p; ++n)
+            for (int k = 0; k <= n; ++k) {
+                cd v;
+                if (n == 0) v = 1.0;
+                else if (k == 0) v = -ipow(c, n) / (double)n;
+                else v = std::ldexp(1.0, -k) * ipow(c, n - k) * binom(n - 1, k - 1);
+                m2m[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
+            }
+    }
+    // M2L Hankel generators for source offsets (dx, dy) in [-3, 3]^2 (source
+    // cell = target cell + (dx, dy)); the expansion variable of Sec. 5.3 is
+    // z_{Lambda M} = target centre - source centre = -(dx + i dy) cell widths
+    const int nh = 2 * p - 1;
+    std::vector<double2> hank((size_t)49 * nh, double2{0.0, 0.0});
+    for (int dy = -3; dy <= 3; ++dy)
+        for (int dx = -3; dx <= 3; ++dx) {
+            if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+            const cd d(-(double)dx, -(double)dy);
+            const size_t o = (size_t)((dy + 3) * 7 + dx + 3) * nh;
+            hank[o] = double2{-std::log(std::abs(d)), 0.0};
+            for (int m = 1; m < nh; ++m) {
+                const cd v = factorial(m - 1) / ipow(d, m);
+                hank[o + m] = double2{v.real(), v.imag()};
+            }
+        }
+    // interaction-list offsets per parity class (children of the parent's
+    // 3x3 neighbourhood that are not adjacent to the target)
+    std::vector<int4> offs((size_t)4 * 27);
+    for (int w = 0; w < 4; ++w) {
+        const int px = w & 1, py = w >> 1;
+        int c = 0;
+        for (int dy = -2 - py; dy <= 3 - py; ++dy)
+            for (int dx = -2 - px; dx <= 3 - px; ++dx) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                offs[(size_t)w * 27 + c++] = int4{dx, dy, (dy + 3) * 7 + dx + 3, 0};
+            }
+        if (c != 27) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
+    }
+    std::vector<double> an(p), bk(p);
+    for (int k = 0; k < p; ++k) {
+        an[k] = ((k & 1) ? -1.0 : 1.0) / factorial(k);
+        bk[k] = (k == 0) ? -1.0 : 1.0 / factorial(k - 1);
+    }
+    // leaf point pattern
+    std::vector<double2> p2m((size_t)p * 64), l2p((size_t)64 * p);
+    for (int j = 0; j < 64; ++j) {
+        const int a = j & 7, b = j >> 3;
+        const cd tau((a - 3.5) / 8.0, (b - 3.5) / 8.0);
+        for (int k = 0; k < p; ++k) {
+            const cd pk = ipow(tau, k);
+            const cd w = (k == 0) ? cd(1.0) : -pk / (double)k;
+            p2m[(size_t)k * 64 + j] = double2{w.real(), w.imag()};
+            l2p[(size_t)j * p + k] = double2{pk.real(), pk.imag()};
+        }
+    }
+    // near-field kernel table
+    std::vector<double> kt(31 * 31);
+    const double h = pl->h;
+    for (int dy = -15; dy <= 15; ++dy)
+        for (int dx = -15; dx <= 15; ++dx) {
+            const double v = (dx == 0 && dy == 0)
+                                 ? std::log(pl->self_eps * h)
+                                 : std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
+            kt[(dy + 15) * 31 + dx + 15] = v;
+        }
+    int st;
+    if ((st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.hank, hank)) ||
+        (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
+        (st = upload(pl, &pl->tab.m2l_b, bk)) || (st = upload(pl, &pl->tab.p2m, p2m)) ||
+        (st = upload(pl, &pl->tab.l2p, l2p)) || (st = upload(pl, &pl->tab.ktab, kt)))
+        return st;
+    return FMM_OK;
+}
+
+static int build_levels_and_work(fmm_plan *pl)
+{
+    const int L = pl->L, p = pl->p;
+    int64_t off = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+        pl->lv.off[l] = 0;
+        pl->lv.logw[l] = 0.0;
+    }
+    for (int l = 2; l <= L; ++l) {
+        pl->lv.off[l] = off;
+        off += ((int64_t)1 << (2 * l)) * p;
+        pl->lv.logw[l] = std::log(pl->side / (double)(1 << l));
+    }
+    pl->exp_elems = off;
+    std::vector<M2LItem> all, edge;
+    for (int l = L; l >= 2; --l) {
+        const int nc = 1 << l, tw = std::min(16, nc), nt = nc / tw;
+        for (int ty = 0; ty < nt; ++ty)
+            for (int tx = 0; tx < nt; ++tx)
+                for (int g = 0; g < kM2LGroups; ++g) {
+                    M2LItem it;
+                    it.level = (int16_t)l;
+                    it.group = (int16_t)g;
+                    it.tx0 = tx * tw;
+                    it.ty0 = ty * tw;
+                    all.push_back(it);
+                    if (tx == 0 || ty == 0 || tx == nt - 1 || ty == nt - 1) edge.push_back(it);
+                }
+    }
+    pl->n_m2l_items = (int)all.size();
+    pl->n_m2l_edge_items = (int)edge.size();
+    int st;
+    if (!all.empty() && (st = upload(pl, &pl->m2l_items, all))) return st;
+    if (!edge.empty() && (st = upload(pl, &pl->m2l_edge_items, edge))) return st;
+    if (off > 0) {
+        const size_t bytes = (size_t)off * sizeof(double2);
+        FMM_HIP(pl, hipMalloc(&pl->ws.M, bytes));
+        FMM_HIP(pl, hipMalloc(&pl->ws.Lt, bytes));
+        for (int g = 0; g < kM2LGroups; ++g) FMM_HIP(pl, hipMalloc(&pl->ws.Lp[g], bytes));
+        if (pl->kind == FMM_GRID && pl->bem) {
+            // the boundary-source pass writes only boundary cells of M2 and
+            // only edge tiles of Lp2: everything else must stay zero
+            FMM_HIP(pl, hipMalloc(&pl->ws.M2, bytes));
+            FMM_HIP(pl, hipMemset(pl->ws.M2, 0, bytes));
+            FMM_HIP(pl, hipMalloc(&pl->ws.Lt2, bytes));
+            for (int g = 0; g < kM2LGroups; ++g) {
+                FMM_HIP(pl, hipMalloc(&pl->ws.Lp2[g], bytes));
+                FMM_HIP(pl, hipMemset(pl->ws.Lp2[g], 0, bytes));
+            }
+        }
+    }
+    return FMM_OK;
+}
+
+static void release(fmm_plan *pl)
+{
+    void *ptrs[] = {pl->tab.m2m, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+                    pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->ws.M, pl->ws.Lt,
+                    pl->ws.Lp[0], pl->ws.Lp[1], pl->ws.Lp[2], pl->ws.M2, pl->ws.Lt2,
+                    pl->ws.Lp2[0], pl->ws.Lp2[1], pl->ws.Lp2[2], pl->m2l_items,
+                    pl->m2l_edge_items, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
+                    pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
+                    pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (pl->hpin) (void)hipHostFree(pl->hpin);
+}
+
+
+}  // namespace fmmprec
+
+using namespace fmmprec;
+
+extern "C" {
+
+const char *fmm_version(void) { return "fmmprec 0.1 gfx950"; }
+
+const char *fmm_last_error(const fmm_plan *plan)
+{
+    return plan ? plan->err.c_str() : g_setup_error.c_str();
+}
+
+int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_plan **out)
+{
+    if (!out) return fail(nullptr, FMM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!prob || !prm) return fail(nullptr, FMM_ERR_ARG, "problem or params is NULL");
+    if (prm->p < kPMin || prm->p > kPMax)
+        return fail(nullptr, FMM_ERR_ARG, "p must be in [2, 20]");
+    if (prm->leaf != 64) return fail(nullptr, FMM_ERR_ARG, "leaf must be 64");
+    if (prm->prec != FMM_FP64) return fail(nullptr, FMM_ERR_UNSUPPORTED, "only FMM_FP64 is built");
+    if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
+        return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    fmm_plan *pl = new (std::nothrow) fmm_plan();
+    if (!pl) return fail(nullptr, FMM_ERR_ALLOC, "host allocation failed");
+    pl->kind = prob->kind;
+    pl->n = prob->n;
+    pl->p = prm->p;
+    pl->bem = prm->bem ? 1 : 0;
+    int st = FMM_OK;
+    if (prob->kind == FMM_GRID) {
+        const int64_t n = prob->n;
+        int L = 0;
+        while (((int64_t)8 << L) < n && L < 16) ++L;
+        if (n < 8 || ((int64_t)8 << L) != n) {
+            delete pl;
+            return fail(nullptr, FMM_ERR_ARG, "GRID n must be 8 * 2^L");
+        }
+        pl->L = L;
+        pl->nl = 1 << L;
+        pl->h = 1.0 / (double)(n + 1);
+        pl->self_eps = prm->self_eps > 0.0 ? prm->self_eps
+                                           : std::exp(-0.57721566490153286061) / (2.0 * std::sqrt(2.0));
+        pl->x0 = pl->y0 = 0.5 * pl->h;
+        pl->side = (double)n * pl->h;
+    } else if (prob->kind == FMM_POINTS) {
+        delete pl;
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "POINTS plans are not built yet");
+    } else {
+        delete pl;
+        return fail(nullptr, FMM_ERR_ARG, "unknown problem kind");
+    }
+    if ((st = build_tables(pl)) || (st = build_levels_and_work(pl)) || (st = m2l_kernel_setup(pl))) {
+        g_setup_error = pl->err;
+        release(pl);
+        delete pl;
+        return st;
+    }
+    if (pl->kind == FMM_GRID && pl->bem) {
+        if ((st = bem_setup(pl, s)) != FMM_OK) {
+            g_setup_error = pl->err;
+            release(pl);
+            delete pl;
+            return st;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        g_setup_error = std::string("setup: ") + hipGetErrorString(e);
+        release(pl);
+        delete pl;
+        return FMM_ERR_DEVICE;
+    }
+    *out = pl;
+    return FMM_OK;
+}
+
+int fmm_destroy(fmm_plan *plan)
+{
+    if (!plan) return FMM_OK;
+    (void)hipDeviceSynchronize();
+    release(plan);
+    delete plan;
+    return FMM_OK;
+}
+
+int fmm_apply(fmm_plan *pl, const double *q, double *u, int nrhs, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (!q || !u || nrhs < 1) return fail(pl, FMM_ERR_ARG, "q/u NULL or nrhs < 1");
+    if (q == u) return fail(pl, FMM_ERR_ARG, "u must not alias q");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (pl->kind == FMM_GRID) ? (size_t)pl->n * pl->n : (size_t)pl->n;
+    for (int r = 0; r < nrhs; ++r) {
+        int st = (pl->kind == FMM_GRID) ? grid_volume_fmm(pl, q + r * N, 1.0, u + r * N, nullptr, s)
+                                        : FMM_ERR_UNSUPPORTED;
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+int fmm_precond_apply(fmm_plan *pl, const double *r, double *z, int nrhs, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "preconditioner needs a GRID plan");
+    if (!r || !z || nrhs < 1) return fail(pl, FMM_ERR_ARG, "r/z NULL or nrhs < 1");
+    if (r == z) return fail(pl, FMM_ERR_ARG, "z must not alias r");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)pl->n * pl->n;
+    for (int k = 0; k < nrhs; ++k) {
+        int st = precond_apply_one(pl, r + k * N, z + k * N, nullptr, nullptr, s);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+int fmm_precond_stages(fmm_plan *pl, const double *r, double *z, double *phi_ring, double *sigma,
+                       void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "preconditioner needs a GRID plan");
+    if (!r || !z || r == z) return fail(pl, FMM_ERR_ARG, "r/z NULL or aliased");
+    return precond_apply_one(pl, r, z, phi_ring, pl->bem ? sigma : nullptr, (hipStream_t)stream);
+}
+
+int fmm_stencil_apply(fmm_plan *pl, const double *v, double *w, int nrhs, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "stencil needs a GRID plan");
+    if (!v || !w || nrhs < 1 || v == w) return fail(pl, FMM_ERR_ARG, "v/w NULL, aliased or nrhs < 1");
+    const size_t N = (size_t)pl->n * pl->n;
+    for (int k = 0; k < nrhs; ++k) {
+        int st = stencil_apply(pl, v + k * N, w + k * N, (hipStream_t)stream);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+int precond_gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u,
+                        const gmres_params *prm, gmres_result *res, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "solve needs a GRID plan");
+    if (!f || !u) return fail(pl, FMM_ERR_ARG, "f or u is NULL");
+    if (f == u) return fail(pl, FMM_ERR_ARG, "u must not alias f");
+    gmres_params q{1e-8, 30, 600};
+    if (prm) q = *prm;
+    if (!(q.tol > 0.0) || !std::isfinite(q.tol)) return fail(pl, FMM_ERR_ARG, "tol must be > 0");
+    if (q.restart < 1 || q.restart > 32) return fail(pl, FMM_ERR_ARG, "restart must be in [1, 32]");
+    if (q.maxit < 1) return fail(pl, FMM_ERR_ARG, "maxit must be >= 1");
+    return gmres_solve(pl, f, g, u, &q, res, (hipStream_t)stream);
+}
+
+}  // extern "C"

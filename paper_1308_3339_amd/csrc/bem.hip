@@ -1,0 +1,242 @@
+// Boundary correction of the FMM-BEM preconditioner (Sec. 4.1 and 4.3 of
+// arXiv:1308.3339) for zero Dirichlet data.
+//
+// Collocation at the 4n ring nodes with constant elements of length h:
+//   S_kl = h G(|y_k - y_l|) (k != l),  S_kk = -(h/2pi)(log(h/2) - 1),
+// and the density solves S sigma = -phi_ring.
+//
+// The ring is invariant under the 90-degree rotation of the square, which
+// maps node (side s, k) to (s+1, k).  S is therefore block circulant,
+// S_{s,s'} = C_{(s'-s) mod 4}, and the 4-point DFT over sides diagonalises
+// it into S^_m = sum_r C_r i^(mr):
+//   S^_0 = C0 + C1 + C2 + C3 (real),  S^_2 = C0 - C1 + C2 - C3 (real),
+//   S^_1 = (C0 - C2) + i (C1 - C3) (Hermitian),  S^_3 = conj(S^_1).
+// All three are Hermitian positive definite (S is SPD), so they are inverted
+// once at setup by Gauss-Jordan without pivoting, and every application is
+// a DFT over the four sides, three n x n matrix-vector products and the
+// inverse DFT: 4n^2 doubles read instead of the 16n^2 of a dense inverse.
+#include "fmm_internal.h"
+
+namespace fmmprec {
+
+__device__ __forceinline__ void ring_xy(int t, int n, int &Ix, int &Iy)
+{
+    const int s = t / n, k = t - s * n;
+    if (s == 0) { Ix = k + 1; Iy = 0; }
+    else if (s == 1) { Ix = n + 1; Iy = k + 1; }
+    else if (s == 2) { Ix = n - k; Iy = n + 1; }
+    else { Ix = 0; Iy = n - k; }
+}
+
+// S^_0, S^_2 (real) and S^_1 (complex) for rows k (bottom side) and columns k'
+__global__ __launch_bounds__(256) void k_bem_build(double *__restrict__ S0,
+                                                   double *__restrict__ S2,
+                                                   double2 *__restrict__ S1, int n)
+{
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const double h = 1.0 / (double)(n + 1);
+    int xi, yi;
+    ring_xy(i, n, xi, yi);
+    double C[4];
+    for (int r = 0; r < 4; ++r) {
+        int xj, yj;
+        ring_xy(r * n + j, n, xj, yj);
+        if (r == 0 && i == j) {
+            C[r] = -(h * kInv2Pi) * (log(0.5 * h) - 1.0);
+        } else {
+            const double dx = (double)(xi - xj), dy = (double)(yi - yj);
+            C[r] = -(h * kInv2Pi) * log(h * sqrt(dx * dx + dy * dy));
+        }
+    }
+    const size_t e = (size_t)i * n + j;
+    S0[e] = (C[0] + C[1]) + (C[2] + C[3]);
+    S2[e] = (C[0] - C[1]) + (C[2] - C[3]);
+    S1[e] = make_double2(C[0] - C[2], C[1] - C[3]);
+}
+
+// Gauss-Jordan inversion without pivoting, one elimination step per pair of
+// launches (row kernel, then update into the other buffer).
+__global__ void k_gj_row_real(const double *__restrict__ A, double *__restrict__ rk, int n, int k)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double piv = A[(size_t)k * n + k];
+    rk[j] = (j == k) ? 1.0 / piv : A[(size_t)k * n + j] / piv;
+}
+
+__global__ __launch_bounds__(256) void k_gj_upd_real(const double *__restrict__ A,
+                                                     double *__restrict__ B,
+                                                     const double *__restrict__ rk, int n, int k)
+{
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const size_t e = (size_t)i * n + j;
+    double v;
+    if (i == k) v = rk[j];
+    else if (j == k) v = -A[(size_t)i * n + k] * rk[k];
+    else v = fma(-A[(size_t)i * n + k], rk[j], A[e]);
+    B[e] = v;
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b)
+{
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__global__ void k_gj_row_cplx(const double2 *__restrict__ A, double2 *__restrict__ rk, int n, int k)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double2 piv = A[(size_t)k * n + k];
+    rk[j] = (j == k) ? cdiv(make_double2(1.0, 0.0), piv) : cdiv(A[(size_t)k * n + j], piv);
+}
+
+__global__ __launch_bounds__(256) void k_gj_upd_cplx(const double2 *__restrict__ A,
+                                                     double2 *__restrict__ B,
+                                                     const double2 *__restrict__ rk, int n, int k)
+{
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= n) return;
+    const size_t e = (size_t)i * n + j;
+    const double2 aik = A[(size_t)i * n + k];
+    double2 v;
+    if (i == k) {
+        v = rk[j];
+    } else if (j == k) {
+        const double2 r = rk[k];
+        v = make_double2(-(aik.x * r.x - aik.y * r.y), -(aik.x * r.y + aik.y * r.x));
+    } else {
+        const double2 r = rk[j], a = A[e];
+        v = make_double2(a.x - (aik.x * r.x - aik.y * r.y), a.y - (aik.x * r.y + aik.y * r.x));
+    }
+    B[e] = v;
+}
+
+// b = -phi: b^_0 = sum_s b_s, b^_2 = sum_s (-1)^s b_s, b^_1 = sum_s i^(-s) b_s
+__global__ void k_bem_rhs(const double *__restrict__ phi, double2 *__restrict__ bh, int n)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const double b0 = -phi[k], b1 = -phi[n + k], b2 = -phi[2 * n + k], b3 = -phi[3 * n + k];
+    bh[k] = make_double2((b0 + b1) + (b2 + b3), 0.0);
+    bh[n + k] = make_double2((b0 - b1) + (b2 - b3), 0.0);
+    bh[2 * n + k] = make_double2(b0 - b2, b3 - b1);
+}
+
+// sigma^ = X b^ for the three blocks: blockIdx.y = 0 (X0), 1 (X2), 2 (X1, complex).
+// One wave per row.
+__global__ __launch_bounds__(256) void k_bem_gemv(const double *__restrict__ X0,
+                                                  const double *__restrict__ X2,
+                                                  const double2 *__restrict__ X1,
+                                                  const double2 *__restrict__ bh,
+                                                  double2 *__restrict__ sh, int n)
+{
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int which = blockIdx.y;
+    if (row >= n) return;
+    double ax = 0.0, ay = 0.0;
+    if (which < 2) {
+        const double *X = (which == 0 ? X0 : X2) + (size_t)row * n;
+        const double2 *bv = bh + which * n;
+        for (int j = lane; j < n; j += 64) ax = fma(X[j], bv[j].x, ax);
+    } else {
+        const double2 *X = X1 + (size_t)row * n;
+        const double2 *bv = bh + 2 * n;
+        for (int j = lane; j < n; j += 64) {
+            const double2 x = X[j], b = bv[j];
+            ax = fma(x.x, b.x, fma(-x.y, b.y, ax));
+            ay = fma(x.x, b.y, fma(x.y, b.x, ay));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ax += __shfl_xor(ax, o);
+        ay += __shfl_xor(ay, o);
+    }
+    if (lane == 0) sh[which * n + row] = make_double2(ax, ay);
+}
+
+// sigma_s = (1/4)[ s^_0 + (-1)^s s^_2 + 2 Re(i^s s^_1) ]; ring charges h sigma
+__global__ void k_bem_sigma(const double2 *__restrict__ sh, double *__restrict__ rq,
+                            double *__restrict__ sig_out, int n, double h)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= 4 * n) return;
+    const int s = t / n, k = t - s * n;
+    const double a0 = sh[k].x, a2 = sh[n + k].x;
+    const double2 a1 = sh[2 * n + k];
+    double re1;
+    if (s == 0) re1 = a1.x;
+    else if (s == 1) re1 = -a1.y;
+    else if (s == 2) re1 = -a1.x;
+    else re1 = a1.y;
+    const double sg = 0.25 * (a0 + ((s & 1) ? -a2 : a2) + 2.0 * re1);
+    rq[t] = h * sg;
+    if (sig_out) sig_out[t] = sg;
+}
+
+int bem_setup(fmm_plan *pl, hipStream_t s)
+{
+    const int n = (int)pl->n;
+    const size_t nn = (size_t)n * n;
+    double2 *tmp = nullptr, *rk = nullptr;
+    FMM_HIP(pl, hipMalloc(&pl->X0, nn * sizeof(double)));
+    FMM_HIP(pl, hipMalloc(&pl->X2, nn * sizeof(double)));
+    FMM_HIP(pl, hipMalloc(&pl->X1, nn * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&pl->phi_ring, 4 * (size_t)n * sizeof(double)));
+    FMM_HIP(pl, hipMalloc(&pl->ring_q, 4 * (size_t)n * sizeof(double)));
+    FMM_HIP(pl, hipMalloc(&pl->bhat, 3 * (size_t)n * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&pl->shat, 3 * (size_t)n * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&tmp, nn * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&rk, (size_t)n * sizeof(double2)));
+    const dim3 g2((n + 63) / 64, (n + 3) / 4), g1((n + 255) / 256);
+    hipLaunchKernelGGL(k_bem_build, g2, dim3(256), 0, s, pl->X0, pl->X2, pl->X1, n);
+    // real blocks
+    for (int b = 0; b < 2; ++b) {
+        double *A = (b == 0) ? pl->X0 : pl->X2;
+        double *B = reinterpret_cast<double *>(tmp);
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_gj_row_real, g1, dim3(256), 0, s, A, reinterpret_cast<double *>(rk), n, k);
+            hipLaunchKernelGGL(k_gj_upd_real, g2, dim3(256), 0, s, A, B,
+                               reinterpret_cast<const double *>(rk), n, k);
+            double *t = A; A = B; B = t;
+        }
+        double *dst = (b == 0) ? pl->X0 : pl->X2;
+        if (A != dst) FMM_HIP(pl, hipMemcpyAsync(dst, A, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    {
+        double2 *A = pl->X1, *B = tmp;
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_gj_row_cplx, g1, dim3(256), 0, s, A, rk, n, k);
+            hipLaunchKernelGGL(k_gj_upd_cplx, g2, dim3(256), 0, s, A, B, rk, n, k);
+            double2 *t = A; A = B; B = t;
+        }
+        if (A != pl->X1)
+            FMM_HIP(pl, hipMemcpyAsync(pl->X1, A, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
+    }
+    FMM_HIP(pl, hipGetLastError());
+    FMM_HIP(pl, hipStreamSynchronize(s));
+    FMM_HIP(pl, hipFree(tmp));
+    FMM_HIP(pl, hipFree(rk));
+    return FMM_OK;
+}
+
+// sigma = -S^{-1} phi_ring (pl->phi_ring), ring charges h sigma -> pl->ring_q
+int bem_apply(fmm_plan *pl, double *sigma_out, hipStream_t s)
+{
+    const int n = (int)pl->n;
+    hipLaunchKernelGGL(k_bem_rhs, dim3((n + 255) / 256), dim3(256), 0, s, pl->phi_ring, pl->bhat, n);
+    hipLaunchKernelGGL(k_bem_gemv, dim3((n + 3) / 4, 3), dim3(256), 0, s, pl->X0, pl->X2, pl->X1,
+                       pl->bhat, pl->shat, n);
+    hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256), dim3(256), 0, s, pl->shat,
+                       pl->ring_q, sigma_out, n, pl->h);
+    FMM_HIP(pl, hipGetLastError());
+    return FMM_OK;
+}
+
+}  // namespace fmmprec

@@ -1,0 +1,176 @@
+// Internal declarations of the gfx950 FMM-preconditioner library.
+//
+// Data layout in HBM (all FP64):
+//   grid vectors      row-major n x n, node (i, j) at j*n + i
+//   expansions        per level l (2..L) and coefficient k (0..p-1), a
+//                     double2 (re, im) per cell: exp[off(l) + k*4^l + cell],
+//                     cell = iy*2^l + ix.  Coefficient-major so that a wave
+//                     reading coefficient k of 64 neighbouring cells is one
+//                     contiguous 1 KB segment.
+//   scaled expansions M~_k = M_k / w^k and L~_k = L_k w^k with w the cell
+//                     width of the level, so every translation operator is
+//                     level independent (only Re L_0 picks up M_0 log w).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fmmprec.h"
+
+namespace fmmprec {
+
+constexpr int kPMin = 2;
+constexpr int kPMax = 20;
+constexpr int kMaxLevels = 24;
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+
+// number of M2L partial sums (the 27 list entries are split 9 + 9 + 9 so a
+// tile of work is a third of a cell's list, which balances the launch)
+constexpr int kM2LGroups = 3;
+
+// Work item of the all-levels M2L launch: (level, tile origin x, y, group).
+struct M2LItem {
+    int16_t level, group;
+    int32_t tx0, ty0;
+};
+
+// Per-level bookkeeping passed by value to kernels.
+struct LevelInfo {
+    int64_t off[kMaxLevels + 1];  // double2 offset of level l in an expansion buffer
+    double logw[kMaxLevels + 1];  // log(cell width) at level l
+};
+
+// Device-resident FMM tables for one p.
+struct FmmTables {
+    double2 *m2m;     // [4 quadrants][p][p]  M~ parent = A_q M~ child (lower triangular)
+    double2 *hank;    // [7*7 offsets][2p-1]  Hankel generators of M2L (offset index (dy+3)*7+dx+3)
+    int4 *m2l_off;    // [4 parity classes][27] (dx, dy, hank index, 0)
+    double *m2l_a;    // [p]  (-1)^n / n!   M2L output scale
+    double *m2l_b;    // [p]  input scale: -1 for k = 0, 1/(k-1)! for k >= 1
+    double2 *p2m;     // [p][64] grid P2M weights, -tau_j^k / k (1 for k = 0)
+    double2 *l2p;     // [64][p] grid L2P powers tau_j^k
+    double *ktab;     // [31][31] log(h |d|), d in [-15, 15]^2, self entry log(eps h)
+};
+
+struct Workspace {
+    double2 *M = nullptr;                 // multipoles, levels 2..L
+    double2 *Lt = nullptr;                // local expansions, levels 2..L-1
+    double2 *Lp[kM2LGroups] = {};         // M2L partials, levels 2..L
+    // second (boundary-source) pass of the preconditioner
+    double2 *M2 = nullptr;
+    double2 *Lt2 = nullptr;
+    double2 *Lp2[kM2LGroups] = {};
+};
+
+}  // namespace fmmprec
+
+struct fmm_plan {
+    int kind = FMM_GRID;
+    int64_t n = 0;        // GRID: side; POINTS: N
+    int L = 0;            // leaf level
+    int nl = 1;           // leaves per side, 2^L
+    int p = 10;
+    int bem = 1;
+    double h = 0.0;       // GRID mesh width
+    double self_eps = 0.0;
+    double x0 = 0.0, y0 = 0.0, side = 1.0;  // tree root square
+    fmmprec::LevelInfo lv{};
+    int64_t exp_elems = 0;                  // double2 elements per expansion buffer
+
+    fmmprec::FmmTables tab{};
+    fmmprec::Workspace ws{};
+    fmmprec::M2LItem *m2l_items = nullptr;  // all tiles of levels 2..L
+    int n_m2l_items = 0;
+    fmmprec::M2LItem *m2l_edge_items = nullptr;  // tiles that see boundary cells
+    int n_m2l_edge_items = 0;
+
+    // boundary correction (GRID, bem = 1): inverses of the three distinct
+    // diagonal blocks of the rotation-diagonalised collocation matrix
+    double *X0 = nullptr;     // n x n real
+    double *X2 = nullptr;     // n x n real
+    double2 *X1 = nullptr;    // n x n complex
+    double *phi_ring = nullptr;   // 4n
+    double *ring_q = nullptr;     // 4n  (h * sigma)
+    double2 *bhat = nullptr;      // 3n  (b^_0, b^_2 real parts in .x; b^_1 complex)
+    double2 *shat = nullptr;      // 3n
+
+    // POINTS
+    int *perm = nullptr;          // sorted position -> caller index
+    int *leaf_start = nullptr;    // 4^L + 1
+    double *px = nullptr, *py = nullptr;  // sorted coordinates
+    double *qs = nullptr, *us = nullptr;  // sorted charges / potentials
+
+    // Krylov workspace (GRID)
+    int kry_m = 0;
+    double *V = nullptr;          // (m+1) x N
+    double *Z = nullptr;          // m x N
+    double *w = nullptr, *b = nullptr;
+    double *partial = nullptr;    // reduction partials
+    double *dscal = nullptr;      // small device scalars / coefficient vectors
+    double *hpin = nullptr;       // pinned host mirror of dscal
+
+    std::string err;
+};
+
+namespace fmmprec {
+
+// status helpers
+int fail(fmm_plan *plan, int code, const std::string &msg);
+extern thread_local std::string g_setup_error;
+
+#define FMM_HIP(plan, call)                                                       \
+    do {                                                                          \
+        hipError_t e__ = (call);                                                  \
+        if (e__ != hipSuccess)                                                    \
+            return ::fmmprec::fail((plan), FMM_ERR_DEVICE,                        \
+                                   std::string(#call ": ") + hipGetErrorString(e__)); \
+    } while (0)
+
+// ---- FMM stages (fmm_grid.hip / fmm_points.hip) ----
+// q -> u for grid plans: u = -(1/2pi) [ qscale * near(q) + far ], optionally
+// also the ring potential.  `accumulate` adds into u instead of storing.
+int grid_volume_fmm(fmm_plan *plan, const double *q, double qscale, double *u,
+                    double *ring_out, hipStream_t s);
+// second pass: ring charges plan->ring_q, add their potential to u
+int grid_ring_source_fmm(fmm_plan *plan, double *u, hipStream_t s);
+int m2l_kernel_setup(fmm_plan *plan);
+int points_fmm(fmm_plan *plan, const double *q, double *u, hipStream_t s);
+int points_setup(fmm_plan *plan, const double *dx, const double *dy, hipStream_t s);
+
+// ---- boundary correction (bem.hip) ----
+int bem_setup(fmm_plan *plan, hipStream_t s);
+int bem_apply(fmm_plan *plan, double *sigma_out, hipStream_t s);
+
+// ---- Krylov (krylov.hip) ----
+int stencil_apply(fmm_plan *plan, const double *v, double *w, hipStream_t s);
+int gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
+                const gmres_params *prm, gmres_result *res, hipStream_t s);
+int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
+                      double *sigma, hipStream_t s);
+
+}  // namespace fmmprec
+
+// p dispatch: instantiates FN<P> for P = 2..20
+#define FMM_P_CASE(P, FN, ...) \
+    case P:                    \
+        return FN<P>(__VA_ARGS__);
+#define FMM_DISPATCH_P(p, FN, ...)                                                   \
+    switch (p) {                                                                     \
+        FMM_P_CASE(2, FN, __VA_ARGS__) FMM_P_CASE(3, FN, __VA_ARGS__)                 \
+        FMM_P_CASE(4, FN, __VA_ARGS__) FMM_P_CASE(5, FN, __VA_ARGS__)                 \
+        FMM_P_CASE(6, FN, __VA_ARGS__) FMM_P_CASE(7, FN, __VA_ARGS__)                 \
+        FMM_P_CASE(8, FN, __VA_ARGS__) FMM_P_CASE(9, FN, __VA_ARGS__)                 \
+        FMM_P_CASE(10, FN, __VA_ARGS__) FMM_P_CASE(11, FN, __VA_ARGS__)               \
+        FMM_P_CASE(12, FN, __VA_ARGS__) FMM_P_CASE(13, FN, __VA_ARGS__)               \
+        FMM_P_CASE(14, FN, __VA_ARGS__) FMM_P_CASE(15, FN, __VA_ARGS__)               \
+        FMM_P_CASE(16, FN, __VA_ARGS__) FMM_P_CASE(17, FN, __VA_ARGS__)               \
+        FMM_P_CASE(18, FN, __VA_ARGS__) FMM_P_CASE(19, FN, __VA_ARGS__)               \
+        FMM_P_CASE(20, FN, __VA_ARGS__)                                              \
+        default:                                                                     \
+            return FMM_ERR_ARG;                                                      \
+    }

@@ -1,0 +1,73 @@
+"""Host-side checks of the C ABI (no GPU compute): the library loads, exports
+every function include/fmmprec.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1308_3339_amd as fp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fmmprec.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm_\w+|precond_gmres_solve)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    assert set(_declared()) == set(fp.exported_symbols)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fp.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_version_string():
+    assert "gfx950" in fp.fmm_version()
+
+
+def _setup_raw(kind=0, n=64, p=10, leaf=64, prec=0, bem=1, eps=0.0):
+    from paper_1308_3339_amd._binding import fmm_params, fmm_problem
+    lib = fp.load_library()
+    prob = fmm_problem(kind, n, None, None, 0.0, 0.0, 1.0)
+    prm = fmm_params(p, leaf, prec, bem, eps)
+    out = ctypes.c_void_p(123)
+    code = lib.fmm_setup(ctypes.byref(prob), ctypes.byref(prm), None, ctypes.byref(out))
+    return code, out.value, lib.fmm_last_error(None).decode()
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(p=1), "p must"),
+    (dict(p=21), "p must"),
+    (dict(leaf=32), "leaf"),
+    (dict(n=12), "8 * 2^L"),
+    (dict(n=4), "8 * 2^L"),
+    (dict(kind=7), "kind"),
+    (dict(eps=-1.0), "self_eps"),
+])
+def test_setup_rejects_bad_arguments(kw, frag):
+    code, ptr, msg = _setup_raw(**kw)
+    assert code == fp.FMM_ERR_ARG
+    assert not ptr
+    assert frag in msg
+
+
+def test_setup_rejects_unbuilt_precision():
+    code, ptr, msg = _setup_raw(prec=3)
+    assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
+
+
+def test_null_arguments():
+    lib = fp.load_library()
+    assert lib.fmm_setup(None, None, None, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_apply(None, None, None, 1, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_precond_apply(None, None, None, 1, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_stencil_apply(None, None, None, 1, None) == fp.FMM_ERR_ARG
+    assert lib.precond_gmres_solve(None, None, None, None, None, None, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_destroy(None) == fp.FMM_OK

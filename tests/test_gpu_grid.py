@@ -1,0 +1,232 @@
+"""GPU parity of the grid path against the CPU FP64 oracle, through the C ABI.
+
+Tolerances (FP64 end to end, different summation orders, level-scaled
+expansions on the GPU vs unscaled ones in the oracle):
+  FMM volume potential        max |u_gpu - u_oracle| <= 1e-12 max |u_oracle|
+  stencil                     <= 4 ulp-scale (1e-15 relative)
+  preconditioner stages       phi_ring 1e-12, sigma and z 1e-11 (the boundary
+                              inverse is built differently: Gauss-Jordan on
+                              rotation blocks vs LU of the full matrix,
+                              kappa(S) ~ 1.8 n)
+  solve                       true residual <= 1e-8 recomputed on the CPU,
+                              solution within 1e-6 of the oracle's solution
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_1308_3339_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _fp():
+    import paper_1308_3339_amd as fp
+    return fp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def empty(n):
+    import torch
+    return torch.empty(n, dtype=torch.float64, device="cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("n,p", [(8, 6), (16, 10), (32, 6), (32, 10), (64, 10), (64, 14),
+                                 (128, 8), (128, 10), (256, 12)])
+def test_fmm_apply_matches_oracle(n, p):
+    say("case fmm_apply grid n=%d p=%d" % (n, p))
+    fp = _fp()
+    q = inputs.random_charges(n * n, seed=100 + n + p)
+    with fp.fmm_setup(n=n, p=p, bem=0) as plan:
+        u = empty(n * n)
+        plan.apply(dev(q), u)
+        ug = host(u)
+    uo = o.grid_fmm(n, p, q)
+    err = relmax(ug, uo)
+    say("  max rel err vs oracle FMM %.3e" % err)
+    assert err <= 1e-12
+
+
+def test_fmm_apply_accuracy_against_direct_sum():
+    """p = 12 reaches 1e-6 relative L2 against the exact sum (FFT form)."""
+    n = 256
+    say("case fmm_apply accuracy n=256 p=12")
+    fp = _fp()
+    q = inputs.random_charges(n * n, seed=7)
+    with fp.fmm_setup(n=n, p=12, bem=0) as plan:
+        u = empty(n * n)
+        plan.apply(dev(q), u)
+        ug = host(u)
+    ue = o.grid_direct_fft(n, q)
+    err = np.linalg.norm(ug - ue) / np.linalg.norm(ue)
+    say("  rel L2 err vs exact sum %.3e" % err)
+    assert err <= 1e-6
+
+
+def test_fmm_apply_multi_rhs_and_determinism():
+    n, p = 64, 10
+    say("case fmm_apply nrhs=3 n=64")
+    fp = _fp()
+    Q = np.stack([inputs.random_charges(n * n, seed=s) for s in (1, 2, 3)])
+    with fp.fmm_setup(n=n, p=p, bem=0) as plan:
+        U = empty(3 * n * n)
+        plan.apply(dev(Q.reshape(-1)), U, nrhs=3)
+        U1 = host(U).reshape(3, -1)
+        U2 = empty(3 * n * n)
+        plan.apply(dev(Q.reshape(-1)), U2, nrhs=3)
+        assert np.array_equal(U1, host(U2).reshape(3, -1))   # no atomics: bitwise repeat
+        u1 = empty(n * n)
+        plan.apply(dev(Q[1]), u1)
+        assert np.array_equal(host(u1), U1[1])
+    for k in range(3):
+        assert relmax(U1[k], o.grid_fmm(n, p, Q[k])) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_stencil_matches_oracle(n):
+    say("case stencil n=%d" % n)
+    fp = _fp()
+    v = inputs.random_charges(n * n, seed=n)
+    with fp.fmm_setup(n=n, p=4, bem=0) as plan:
+        w = empty(n * n)
+        plan.stencil_apply(dev(v), w)
+        wg = host(w)
+    wo = o.stencil(n, v)
+    assert np.abs(wg - wo).max() <= 1e-15 * np.abs(wo).max()
+
+
+@pytest.mark.parametrize("n,p", [(8, 6), (16, 10), (32, 10), (64, 10), (128, 12)])
+def test_preconditioner_stages_match_oracle(n, p):
+    say("case precond stages n=%d p=%d" % (n, p))
+    fp = _fp()
+    r = inputs.random_charges(n * n, seed=300 + n)
+    with fp.fmm_setup(n=n, p=p, bem=1) as plan:
+        z, phi, sig = empty(n * n), empty(4 * n), empty(4 * n)
+        plan.precond_stages(dev(r), z, phi, sig)
+        zg, phig, sigg = host(z), host(phi), host(sig)
+        z2 = empty(n * n)
+        plan.precond_apply(dev(r), z2)
+        assert np.array_equal(host(z2), zg)
+    pc = o.Preconditioner(n, p=p)
+    zo, phio, sigo = pc.apply(r, stages=True)
+    e_phi, e_sig, e_z = relmax(phig, phio), relmax(sigg, sigo), relmax(zg, zo)
+    say("  phi_ring %.2e sigma %.2e z %.2e" % (e_phi, e_sig, e_z))
+    assert e_phi <= 1e-12
+    assert e_sig <= 1e-11
+    assert e_z <= 1e-11
+
+
+def test_preconditioner_without_bem_is_the_volume_potential():
+    n, p = 64, 10
+    say("case precond bem=0 n=64")
+    fp = _fp()
+    r = inputs.random_charges(n * n, seed=5)
+    with fp.fmm_setup(n=n, p=p, bem=0) as plan:
+        z = empty(n * n)
+        plan.precond_apply(dev(r), z)
+        zg = host(z)
+    zo = o.Preconditioner(n, p=p, bem=False).apply(r)
+    assert relmax(zg, zo) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_solve_manufactured(n):
+    """Config-1 problem: the discrete solution is known in closed form."""
+    say("case solve manufactured n=%d" % n)
+    fp = _fp()
+    f = inputs.manufactured(n)
+    h = 1.0 / (n + 1)
+    uh = (math.pi * h / 2 / math.sin(math.pi * h / 2)) ** 2 * inputs.manufactured_solution(n)
+    with fp.fmm_setup(n=n, p=10, bem=1) as plan:
+        u = dev(np.zeros(n * n))
+        info = plan.solve(dev(f), u)
+        ug = host(u)
+    say("  info", info)
+    assert info["converged"]
+    res = np.linalg.norm(f - o.stencil(n, ug)) / np.linalg.norm(f)
+    assert res <= 1e-8 and abs(res - info["true_rel_res"]) <= 1e-3 * res + 1e-15
+    xo, io = o.fgmres(n, f, o.Preconditioner(n, p=10))
+    say("  oracle iters", io["iters"])
+    assert abs(info["iters"] - io["iters"]) <= 1
+    assert np.linalg.norm(ug - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert np.linalg.norm(ug - uh) <= 1e-6 * np.linalg.norm(uh)
+
+
+def test_solve_bumps_and_warm_start():
+    n = 128
+    say("case solve bumps n=128")
+    fp = _fp()
+    f = inputs.gaussian_bumps(n, 16, seed=11)
+    with fp.fmm_setup(n=n, p=10) as plan:
+        u = dev(np.zeros(n * n))
+        info = plan.solve(dev(f), u)
+        ug = host(u)
+        assert info["converged"]
+        res = np.linalg.norm(f - o.stencil(n, ug)) / np.linalg.norm(f)
+        assert res <= 1e-8
+        info2 = plan.solve(dev(f), u)          # warm start at the solution
+        assert info2["converged"] and info2["iters"] == 0
+        u3 = dev(np.zeros(n * n))
+        info3 = plan.solve(dev(f), u3, restart=3)
+        assert info3["converged"] and info3["restarts"] >= 2
+        assert np.linalg.norm(host(u3) - ug) <= 1e-6 * np.linalg.norm(ug)
+
+
+def test_solve_inhomogeneous_boundary():
+    """b = f + g/h^2 next to the ring; u = x^2 + y^2 has Lap u = 4 and the
+    5-point stencil is exact on quadratics, so f = -4 with g = x^2 + y^2
+    on the ring reproduces u at the nodes (Sec. 6.1's third problem)."""
+    n = 64
+    say("case solve inhomogeneous n=64")
+    fp = _fp()
+    x, y = inputs.grid_nodes(n)
+    rx, ry = o.ring_points(n)
+    with fp.fmm_setup(n=n, p=10) as plan:
+        u = dev(np.zeros(n * n))
+        info = plan.solve(dev(np.full(n * n, -4.0)), u, g=dev(rx ** 2 + ry ** 2))
+        ug = host(u)
+    assert info["converged"]
+    ue = x ** 2 + y ** 2
+    assert np.abs(ug - ue).max() <= 1e-6 * np.abs(ue).max()
+
+
+def test_solve_zero_rhs_and_errors():
+    n = 16
+    say("case solve zero rhs / errors")
+    fp = _fp()
+    with fp.fmm_setup(n=n, p=6) as plan:
+        u = dev(np.ones(n * n))
+        info = plan.solve(dev(np.zeros(n * n)), u)
+        assert info["converged"] and info["iters"] == 0
+        assert np.abs(host(u)).max() == 0.0
+        bad = np.zeros(n * n)
+        bad[3] = np.nan
+        with pytest.raises(fp.FmmError) as ei:
+            plan.solve(dev(bad), dev(np.zeros(n * n)))
+        assert ei.value.code == fp.FMM_ERR_NUMERIC
+        info = plan.solve(dev(inputs.gaussian_bumps(n, 4, seed=2)), dev(np.zeros(n * n)), maxit=1)
+        assert info["status"] == fp.FMM_NOT_CONVERGED and info["iters"] == 1
+        with pytest.raises(fp.FmmError):
+            plan.solve(dev(np.zeros(n * n)), dev(np.zeros(n * n)), restart=0)
