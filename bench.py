@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the FMM-preconditioned Krylov solve on one MI355X.
+
+Workload (one "step"): precond_gmres_solve of the 5-point FD Poisson matrix
+on a 2048 x 2048 interior grid of the unit square, zero Dirichlet data,
+f = 16 seeded Gaussian bumps, FMM-BEM preconditioner with p = 10 and 8x8
+leaves, FGMRES(30) to a 1e-8 true relative residual, all in FP64.  Setup
+(tree tables, boundary inverse) is done once before the warmup and reported
+separately.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Also reports the bare FMM throughput (Mpoints/s),
+a per-stage breakdown, the roofline of the dominant kernel (the fused
+L2P + P2P leaf kernel, timed with HIP events on the library's stream over
+the timed region) and the CPU oracle on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_leaf_grid_2048_p10_traffic.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def leaf_kernel_flops(n, p):
+    """Algorithmic flops of one k_leaf_grid launch on an n x n grid: every
+    near-field pair (target, source in the 3x3 leaves) is one multiply-add
+    (2 flops); every target evaluates the real part of a p-term local
+    expansion (2 multiply-adds per coefficient, 4p flops)."""
+    nl = n // 8
+    pairs = 4096 * (3 * nl - 2) ** 2
+    return 2.0 * pairs + 4.0 * p * n * n
+
+
+def traffic_from_profile(src_hash):
+    """HBM bytes per leaf-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    m_f = re.search(r"fetch_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_w = re.search(r"write_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_hash and m_f and m_w) or m_hash.group(1) != src_hash:
+        return None
+    return float(m_f.group(1)) + float(m_w.group(1))
+
+
+def cpu_baseline(n, p, f, iters):
+    """The oracle (plain C, FP64, OpenMP) on a bounded sample: one volume-FMM
+    application at the full grid size (the dominant per-iteration cost of
+    the oracle's preconditioner), scaled by the GPU solve's iteration count.
+    The oracle's boundary solve, second pass and Arnoldi are not in the
+    sample, so the scaled rate is an upper bound on the oracle's solves/s."""
+    import oracle as o
+    h = 1.0 / (n + 1)
+    q = f * h * h
+    t0 = time.perf_counter()
+    o.grid_fmm(n, p, q)
+    t = time.perf_counter() - t0
+    return {"value": 1.0 / (t * max(iters, 1)), "unit": "solves/s", "cores": o.max_threads(),
+            "kind": "oracle",
+            "sample": "one oracle volume-FMM apply at %dx%d, p=%d (%.2f s wall), scaled by the "
+                      "GPU solve's %d iterations; excludes the oracle's boundary solve, second "
+                      "pass and Arnoldi" % (n, n, p, t, iters),
+            "sample_seconds": t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1308_3339_amd as fp
+    from paper_1308_3339_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    n, p = args.n, args.p
+    N = n * n
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    f_host = inputs.gaussian_bumps(n, 16, seed=inputs.SEED_BUMPS_2048)
+    f = torch.from_numpy(f_host).to(dev)
+    u = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    log("setup n=%d p=%d" % (n, p))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = fp.fmm_setup(n=n, p=p, bem=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log("setup %.3f s" % setup_s)
+
+    for w in range(args.warmup):
+        u.zero_()
+        info = plan.solve(f, u)
+        log("warmup %d: iters %d true rel res %.3e" % (w, info["iters"], info["true_rel_res"]))
+
+    # timed region: K solves; the leaf kernel is timed by HIP events on this stream
+    plan.profile(("LEAF",))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        u.zero_()
+        infos.append(plan.solve(f, u))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    leaf_ms, leaf_launches = plan.profile_read().get("LEAF", (0.0, 0))
+    plan.profile(())
+    log("timed %d solves in %.4f s" % (args.steps, t_total))
+    ms_per_step = 1000.0 * t_total / args.steps
+    solves_per_s = args.steps / t_total
+
+    # correctness of the last solve (true residual recomputed on the GPU)
+    w = torch.empty_like(u)
+    plan.stencil_apply(u, w)
+    rel_res = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
+
+    # per-stage breakdown of one solve (separate, untimed)
+    plan.profile(fp.STAGES)
+    u.zero_()
+    plan.solve(f, u)
+    stages = {k: round(v[0], 4) for k, v in plan.profile_read().items()}
+    plan.profile(())
+
+    # bare FMM and preconditioner throughput (HIP events on the same stream)
+    q = torch.from_numpy(inputs.random_charges(N, seed=9)).to(dev)
+    out = torch.empty_like(q)
+    reps = 10
+    for _ in range(2):
+        plan.apply(q, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.apply(q, out)
+    e1.record(stream)
+    e1.synchronize()
+    fmm_ms = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        plan.precond_apply(q, out)
+    e1.record(stream)
+    e1.synchronize()
+    pc_ms = e0.elapsed_time(e1) / reps
+    log("fmm apply %.3f ms, precond apply %.3f ms" % (fmm_ms, pc_ms))
+
+    src = open(os.path.join(ROOT, "paper_1308_3339_amd", "csrc", "fmm_grid.hip"), "rb").read()
+    src_hash = hashlib.sha256(src).hexdigest()
+    leaf_avg_ms = leaf_ms / max(leaf_launches, 1)
+    flops = leaf_kernel_flops(n, p)
+    achieved = flops / (leaf_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_VALU_TFLOPS, 4),
+                "traffic": traffic_from_profile(src_hash), "kernel": "k_leaf_grid<10>",
+                "avg_launch_ms": round(leaf_avg_ms, 5), "launches": leaf_launches,
+                "flops_per_launch": flops}
+
+    iters = infos[-1]["iters"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(n, p, f_host, iters)
+        log("cpu baseline %.2f s" % cpu["sample_seconds"])
+        cpu.pop("sample_seconds")
+
+    res = {
+        "metric": "FMM-precond GMRES solves/s to 1e-8 rel. residual, 2048^2 grid; FMM Mpoints/s",
+        "value": round(solves_per_s, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "5-point FD Poisson, %dx%d interior grid, zero Dirichlet data, "
+                               "f = 16 Gaussian bumps (seed %d), FMM-BEM preconditioner p=%d "
+                               "leaf 64, FGMRES(30) to 1e-8, FP64"
+                               % (n, n, inputs.SEED_BUMPS_2048, p),
+                   "n": n, "N": N, "p": p, "restart": 30, "tol": 1e-8},
+        "fmm_mpoints_per_s": round(N / (fmm_ms * 1e-3) / 1e6, 2),
+        "precond_mpoints_per_s": round(N / (pc_ms * 1e-3) / 1e6, 2),
+        "fmm_apply_ms": round(fmm_ms, 4),
+        "precond_apply_ms": round(pc_ms, 4),
+        "iters": iters,
+        "true_rel_res": rel_res,
+        "setup_s": round(setup_s, 3),
+        "stages_ms_per_solve": stages,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,33 @@ int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void
 int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                         const gmres_params *prm, gmres_result *res, void *stream);
 
+/* Per-stage device timing (tracing support).  Stages of an apply or solve:
+ * P2M, M2M, M2L, L2L (Sec. 5.3 items 1-4), LEAF (fused L2P + P2P of the
+ * volume pass, items 5 and Sec. 5.1), RING (potential at the ring nodes),
+ * BEM (boundary solve, Sec. 4.3), PASS2 (boundary-source FMM pass), STENCIL
+ * (A v and residuals), ARNOLDI (orthogonalisation and updates). */
+enum {
+    FMM_STAGE_P2M = 0, FMM_STAGE_M2M, FMM_STAGE_M2L, FMM_STAGE_L2L, FMM_STAGE_LEAF,
+    FMM_STAGE_RING, FMM_STAGE_BEM, FMM_STAGE_PASS2, FMM_STAGE_STENCIL, FMM_STAGE_ARNOLDI,
+    FMM_STAGE_COUNT
+};
+
+/* HOST struct: accumulated GPU milliseconds and launch counts per stage. */
+typedef struct {
+    double ms[16];
+    int64_t launches[16];
+} fmm_profile_stats;
+
+/* Enables hipEvent timing of the stages in stage_mask (bit s = stage s;
+ * 0 disables) and clears the accumulated statistics.  Events are recorded
+ * on the stream of each later call, around that stage's launches only, so
+ * an enabled stage adds two event records per occurrence. */
+int fmm_profile(fmm_plan *plan, uint32_t stage_mask);
+
+/* Waits for the recorded events and returns the accumulated statistics
+ * (HOST pointer). */
+int fmm_profile_read(fmm_plan *plan, fmm_profile_stats *out);
+
 /* Frees the plan and everything it owns.  NULL is accepted. */
 int fmm_destroy(fmm_plan *plan);
 

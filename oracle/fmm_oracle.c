@@ -689,3 +689,16 @@ done:
     free(V); free(Z); free(w); free(H); free(cs); free(sn); free(g); free(yv);
     return status;
 }
+
+/* number of OpenMP threads a parallel region of the oracle uses */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

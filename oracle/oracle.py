@@ -94,8 +94,14 @@ def lib():
         L.orc_fgmres.argtypes = [ctypes.c_int, ctypes.c_void_p, _dp, _dp, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, _ip, _dp, _dp]
         L.orc_fgmres.restype = ctypes.c_int
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _f64(a) -> np.ndarray:

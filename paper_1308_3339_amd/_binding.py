@@ -18,8 +18,11 @@ FMM_FP64 = 0
 # every symbol include/fmmprec.h declares
 exported_symbols = (
     "fmm_setup", "fmm_apply", "fmm_precond_apply", "fmm_precond_stages", "fmm_stencil_apply",
-    "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version",
+    "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
+    "fmm_profile_read",
 )
+
+STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
 
 
 class FmmError(RuntimeError):
@@ -41,6 +44,10 @@ class fmm_params(ctypes.Structure):
 
 class gmres_params(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+
+
+class fmm_profile_stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 16), ("launches", ctypes.c_int64 * 16)]
 
 
 class gmres_result(ctypes.Structure):
@@ -85,6 +92,10 @@ def load_library():
     L.fmm_last_error.restype = ctypes.c_char_p
     L.fmm_version.argtypes = []
     L.fmm_version.restype = ctypes.c_char_p
+    L.fmm_profile.argtypes = [vp, ctypes.c_uint32]
+    L.fmm_profile.restype = i32
+    L.fmm_profile_read.argtypes = [vp, ctypes.POINTER(fmm_profile_stats)]
+    L.fmm_profile_read.restype = i32
     _lib = L
     return L
 
@@ -187,6 +198,22 @@ def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, str
             "true_rel_res": res.true_rel_res}
 
 
+def fmm_profile(plan, stages=()):
+    """Enable hipEvent timing of the named stages (empty: disable)."""
+    mask = 0
+    for st in stages:
+        mask |= 1 << STAGES.index(st)
+    return _check(load_library().fmm_profile(plan._ptr, mask), plan._ptr)
+
+
+def fmm_profile_read(plan):
+    """{stage: (milliseconds, launches)} accumulated since fmm_profile."""
+    out = fmm_profile_stats()
+    _check(load_library().fmm_profile_read(plan._ptr, ctypes.byref(out)), plan._ptr)
+    return {st: (out.ms[i], int(out.launches[i])) for i, st in enumerate(STAGES)
+            if out.launches[i] > 0}
+
+
 def fmm_destroy(plan):
     if isinstance(plan, Plan):
         plan.close()
@@ -207,6 +234,8 @@ class Plan:
     precond_stages = fmm_precond_stages
     stencil_apply = fmm_stencil_apply
     solve = precond_gmres_solve
+    profile = fmm_profile
+    profile_read = fmm_profile_read
 
     def close(self):
         if self._ptr is not None and self._ptr.value:

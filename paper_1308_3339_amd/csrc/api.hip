@@ -294,10 +294,39 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     return FMM_OK;
 }
 
+int fmm_profile(fmm_plan *pl, uint32_t mask)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (mask && pl->ev_pool.empty()) {
+        const int pairs = 8192;
+        pl->ev_pool.resize(2 * pairs);
+        pl->ev_stage.assign(pairs, 0);
+        for (auto &e : pl->ev_pool) FMM_HIP(pl, hipEventCreate(&e));
+    }
+    pl->prof_mask = mask;
+    pl->ev_used = 0;
+    return FMM_OK;
+}
+
+int fmm_profile_read(fmm_plan *pl, fmm_profile_stats *out)
+{
+    if (!pl || !out) return fail(pl, FMM_ERR_ARG, "plan or out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    for (int i = 0; i < pl->ev_used; ++i) {
+        FMM_HIP(pl, hipEventSynchronize(pl->ev_pool[2 * i + 1]));
+        float ms = 0.0f;
+        FMM_HIP(pl, hipEventElapsedTime(&ms, pl->ev_pool[2 * i], pl->ev_pool[2 * i + 1]));
+        out->ms[pl->ev_stage[i]] += ms;
+        out->launches[pl->ev_stage[i]] += 1;
+    }
+    return FMM_OK;
+}
+
 int fmm_destroy(fmm_plan *plan)
 {
     if (!plan) return FMM_OK;
     (void)hipDeviceSynchronize();
+    for (auto &e : plan->ev_pool) (void)hipEventDestroy(e);
     release(plan);
     delete plan;
     return FMM_OK;

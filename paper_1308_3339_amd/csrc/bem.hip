@@ -230,6 +230,7 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
 int bem_apply(fmm_plan *pl, double *sigma_out, hipStream_t s)
 {
     const int n = (int)pl->n;
+    StageTimer t(pl, FMM_STAGE_BEM, s);
     hipLaunchKernelGGL(k_bem_rhs, dim3((n + 255) / 256), dim3(256), 0, s, pl->phi_ring, pl->bhat, n);
     hipLaunchKernelGGL(k_bem_gemv, dim3((n + 3) / 4, 3), dim3(256), 0, s, pl->X0, pl->X2, pl->X1,
                        pl->bhat, pl->shat, n);

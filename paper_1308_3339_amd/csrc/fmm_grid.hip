@@ -529,29 +529,42 @@ __global__ __launch_bounds__(256) void k_pass2_leaf(LeafArgs a, const double *__
 // host drivers
 // ---------------------------------------------------------------------------
 template <int P>
-static int run_upward(fmm_plan *pl, const double *q, double qscale, double2 *M, hipStream_t s)
+static void run_m2m(fmm_plan *pl, double2 *M, hipStream_t s)
 {
-    const int L = pl->L, nl = pl->nl;
-    dim3 g1((nl + 31) / 32, nl);
-    hipLaunchKernelGGL(k_p2m_grid<P>, g1, dim3(256), 0, s, q, qscale, pl->tab.p2m,
-                       M + pl->lv.off[L], (int)pl->n, nl);
-    for (int l = L - 1; l >= 2; --l) {
+    for (int l = pl->L - 1; l >= 2; --l) {
         const int ncp = 1 << l;
         hipLaunchKernelGGL(k_m2m<P>, dim3((ncp * ncp + 255) / 256), dim3(256), 0, s,
                            M + pl->lv.off[l + 1], M + pl->lv.off[l], pl->tab.m2m, ncp);
     }
+}
+
+template <int P>
+static int run_upward(fmm_plan *pl, const double *q, double qscale, double2 *M, hipStream_t s)
+{
+    const int L = pl->L, nl = pl->nl;
+    {
+        StageTimer t(pl, FMM_STAGE_P2M, s);
+        dim3 g1((nl + 31) / 32, nl);
+        hipLaunchKernelGGL(k_p2m_grid<P>, g1, dim3(256), 0, s, q, qscale, pl->tab.p2m,
+                           M + pl->lv.off[L], (int)pl->n, nl);
+    }
+    StageTimer t(pl, FMM_STAGE_M2M, s);
+    run_m2m<P>(pl, M, s);
     return FMM_OK;
 }
 
 template <int P>
 static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *const Lp[3], double2 *Lt,
-                       const M2LItem *items, int nitems, hipStream_t s)
+                       const M2LItem *items, int nitems, hipStream_t s, bool timed)
 {
     const size_t shm = (size_t)P * 400 * sizeof(double2);
-    if (nitems > 0)
+    if (nitems > 0) {
+        StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
         hipLaunchKernelGGL(k_m2l<P>, dim3(nitems), dim3(256), shm, s, items, M, Lp[0], Lp[1],
                            Lp[2], pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
                            pl->tab.m2l_b);
+    }
+    StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (int l = 2; l <= pl->L - 1; ++l) {
         const int nc = 1 << l;
         hipLaunchKernelGGL(k_l2l<P>, dim3((nc * nc + 255) / 256), dim3(256), 0, s, Lp[0], Lp[1],
@@ -568,7 +581,7 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     const bool far = L >= 2;
     if (far) {
         run_upward<P>(pl, q, qscale, pl->ws.M, s);
-        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lp, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s);
+        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lp, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
     }
     LeafArgs a;
     a.q = q;
@@ -585,11 +598,16 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     a.nl = nl;
     a.L = L;
     a.far = far ? 1 : 0;
-    dim3 gl((nl + 7) / 8, (nl + 7) / 8);
-    hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(256), 0, s, a);
-    if (ring_out)
+    {
+        StageTimer t(pl, FMM_STAGE_LEAF, s);
+        dim3 gl((nl + 7) / 8, (nl + 7) / 8);
+        hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(256), 0, s, a);
+    }
+    if (ring_out) {
+        StageTimer t(pl, FMM_STAGE_RING, s);
         hipLaunchKernelGGL(k_ring_targets<P>, dim3((4 * pl->n + 255) / 256), dim3(256), 0, s, a,
                            ring_out);
+    }
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }
@@ -599,17 +617,13 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
 {
     const int L = pl->L, nl = pl->nl;
     const bool far = L >= 2;
+    StageTimer t(pl, FMM_STAGE_PASS2, s);
     if (far) {
         hipLaunchKernelGGL(k_p2m_ring<P>, dim3((nl * nl + 255) / 256), dim3(256), 0, s,
                            pl->ring_q, pl->ws.M2 + pl->lv.off[L], (int)pl->n, nl);
-        for (int l = L - 1; l >= 2; --l) {
-            const int ncp = 1 << l;
-            hipLaunchKernelGGL(k_m2m<P>, dim3((ncp * ncp + 255) / 256), dim3(256), 0, s,
-                               pl->ws.M2 + pl->lv.off[l + 1], pl->ws.M2 + pl->lv.off[l],
-                               pl->tab.m2m, ncp);
-        }
+        run_m2m<P>(pl, pl->ws.M2, s);
         run_m2l_l2l<P>(pl, pl->ws.M2, pl->ws.Lp2, pl->ws.Lt2, pl->m2l_edge_items,
-                       pl->n_m2l_edge_items, s);
+                       pl->n_m2l_edge_items, s, false);
     }
     LeafArgs a;
     a.q = nullptr;

@@ -114,6 +114,12 @@ struct fmm_plan {
     double *dscal = nullptr;      // small device scalars / coefficient vectors
     double *hpin = nullptr;       // pinned host mirror of dscal
 
+    // stage timing (fmm_profile)
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;          // created on first enable
+    std::vector<int> ev_stage;                // stage of event pair i (events 2i, 2i+1)
+    int ev_used = 0;
+
     std::string err;
 };
 
@@ -130,6 +136,28 @@ extern thread_local std::string g_setup_error;
             return ::fmmprec::fail((plan), FMM_ERR_DEVICE,                        \
                                    std::string(#call ": ") + hipGetErrorString(e__)); \
     } while (0)
+
+// Scoped hipEvent pair around the launches of one stage (no-op unless the
+// stage is enabled by fmm_profile).
+struct StageTimer {
+    fmm_plan *pl;
+    hipStream_t s;
+    int pair = -1;
+    StageTimer(fmm_plan *plan, int stage, hipStream_t stream) : pl(plan), s(stream)
+    {
+        if (stage < 0 || !(pl->prof_mask & (1u << stage))) return;
+        if ((size_t)(2 * pl->ev_used + 1) >= pl->ev_pool.size()) return;
+        pair = pl->ev_used++;
+        pl->ev_stage[pair] = stage;
+        (void)hipEventRecord(pl->ev_pool[2 * pair], s);
+    }
+    void stop()
+    {
+        if (pair >= 0) (void)hipEventRecord(pl->ev_pool[2 * pair + 1], s);
+        pair = -1;
+    }
+    ~StageTimer() { stop(); }
+};
 
 // ---- FMM stages (fmm_grid.hip / fmm_points.hip) ----
 // q -> u for grid plans: u = -(1/2pi) [ qscale * near(q) + far ], optionally

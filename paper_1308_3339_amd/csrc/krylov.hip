@@ -240,6 +240,7 @@ int stencil_apply(fmm_plan *pl, const double *v, double *w, hipStream_t s)
 {
     const int n = (int)pl->n;
     const double ih2 = 1.0 / (pl->h * pl->h);
+    StageTimer t(pl, FMM_STAGE_STENCIL, s);
     hipLaunchKernelGGL(k_stencil, dim3((n + 63) / 64, (n + 3) / 4), dim3(256), 0, s, v, w, n, ih2);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
@@ -324,7 +325,10 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
     double est = 1.0;
     for (;;) {
         // true residual of the current iterate
-        hipLaunchKernelGGL(k_residual, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ih2);
+        {
+            StageTimer t(pl, FMM_STAGE_STENCIL, s);
+            hipLaunchKernelGGL(k_residual, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ih2);
+        }
         double beta = 0.0;
         if ((st = fetch_norm(pl, nblk, kScal, &beta, s)) != FMM_OK) return st;
         if (!std::isfinite(beta)) return fail(pl, FMM_ERR_NUMERIC, "residual is not finite");
@@ -339,6 +343,7 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
             double *vj = pl->V + (size_t)j * N, *zj = pl->Z + (size_t)j * N;
             if ((st = precond_apply_one(pl, vj, zj, nullptr, nullptr, s)) != FMM_OK) return st;
             const int nv = j + 1;
+            StageTimer ta(pl, FMM_STAGE_ARNOLDI, s);
             // pass 1: w = A z_j, h1 = V^T w
             hipLaunchKernelGGL(k_stencil_dots, gv, bv, 0, s, zj, pl->w, pl->V, N, nv, pl->partial, n, ih2);
             hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, nv, pl->dscal + kH1,
@@ -352,6 +357,7 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
             hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, 1, pl->dscal + kNrm,
                                nullptr, nullptr, 1);
             hipLaunchKernelGGL(k_scale, gv, bv, 0, s, pl->w, pl->V + (size_t)(j + 1) * N, pl->dscal + kNrm, 0.0, N);
+            ta.stop();
             FMM_HIP(pl, hipMemcpyAsync(pl->hpin + kHsum, pl->dscal + kHsum, 33 * sizeof(double),
                                        hipMemcpyDeviceToHost, s));
             FMM_HIP(pl, hipStreamSynchronize(s));
