@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter-collection driver: one 512 MiB device copy (the calibration "
+                         "kernel of known size), then 3 FMM applies and 3 preconditioner "
+                         "applies; prints timings only")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -117,6 +121,23 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log("setup %.3f s" % setup_s)
+
+    if args.probe:
+        x = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        q = torch.from_numpy(inputs.random_charges(N, seed=9)).to(dev)
+        out = torch.empty_like(q)
+        for _ in range(3):
+            plan.apply(q, out)
+        for _ in range(3):
+            plan.precond_apply(q, out)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "done", "copy_bytes_each_way": x.numel() * 8, "n": n, "p": p}))
+        plan.close()
+        return
 
     for w in range(args.warmup):
         u.zero_()

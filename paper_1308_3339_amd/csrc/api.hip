@@ -5,6 +5,7 @@
 // translation formulas of Sec. 5.3 rewritten for level-scaled expansions:
 //   M2M (item 2):  M~par_n = -M~_0 c^n/n + sum_{k=1..n} 2^-k c^(n-k) C(n-1,k-1) M~_k,
 //                  c = (child - parent centre)/w_parent
+//   L2L (item 4):  L~child_n = 2^-n sum_{k>=n} C(k,n) c^(k-n) L~par_k
 //   M2L (item 3):  Hankel generators H_0 = -log|d|, H_m = (m-1)!/d^m with
 //                  d = target minus source centre in cell widths, and the
 //                  scalings a_n = (-1)^n/n!, b_0 = -1, b_k = 1/(k-1)!
@@ -81,6 +82,16 @@ static int build_tables(fmm_plan *pl)
                 m2m[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
             }
     }
+    // L2L: L~child_n = sum_{k>=n} C(k,n) c^(k-n) 2^-n L~parent_k
+    std::vector<double2> l2l((size_t)4 * p * p, double2{0.0, 0.0});
+    for (int qd = 0; qd < 4; ++qd) {
+        const cd c(0.5 * ((qd & 1) - 0.5), 0.5 * ((qd >> 1) - 0.5));
+        for (int n = 0; n < p; ++n)
+            for (int k = n; k < p; ++k) {
+                const cd v = binom(k, n) * ipow(c, k - n) * std::ldexp(1.0, -n);
+                l2l[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
+            }
+    }
     // M2L Hankel generators for source offsets (dx, dy) in [-3, 3]^2 (source
     // cell = target cell + (dx, dy)); the expansion variable of Sec. 5.3 is
     // z_{Lambda M} = target centre - source centre = -(dx + i dy) cell widths
@@ -137,8 +148,13 @@ static int build_tables(fmm_plan *pl)
                                  : std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
             kt[(dy + 15) * 31 + dx + 15] = v;
         }
+    std::vector<double> rt(17 * 17, 0.0);
+    for (int dy = 0; dy <= 16; ++dy)
+        for (int dx = 0; dx <= 16; ++dx)
+            if (dx || dy) rt[dy * 17 + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
     int st;
-    if ((st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.hank, hank)) ||
+    if ((st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
+        (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
         (st = upload(pl, &pl->tab.m2l_b, bk)) || (st = upload(pl, &pl->tab.p2m, p2m)) ||
         (st = upload(pl, &pl->tab.l2p, l2p)) || (st = upload(pl, &pl->tab.ktab, kt)))
@@ -164,16 +180,15 @@ static int build_levels_and_work(fmm_plan *pl)
     for (int l = L; l >= 2; --l) {
         const int nc = 1 << l, tw = std::min(16, nc), nt = nc / tw;
         for (int ty = 0; ty < nt; ++ty)
-            for (int tx = 0; tx < nt; ++tx)
-                for (int g = 0; g < kM2LGroups; ++g) {
-                    M2LItem it;
-                    it.level = (int16_t)l;
-                    it.group = (int16_t)g;
-                    it.tx0 = tx * tw;
-                    it.ty0 = ty * tw;
-                    all.push_back(it);
-                    if (tx == 0 || ty == 0 || tx == nt - 1 || ty == nt - 1) edge.push_back(it);
-                }
+            for (int tx = 0; tx < nt; ++tx) {
+                M2LItem it;
+                it.level = l;
+                it.pad = 0;
+                it.tx0 = tx * tw;
+                it.ty0 = ty * tw;
+                all.push_back(it);
+                if (tx == 0 || ty == 0 || tx == nt - 1 || ty == nt - 1) edge.push_back(it);
+            }
     }
     pl->n_m2l_items = (int)all.size();
     pl->n_m2l_edge_items = (int)edge.size();
@@ -184,17 +199,15 @@ static int build_levels_and_work(fmm_plan *pl)
         const size_t bytes = (size_t)off * sizeof(double2);
         FMM_HIP(pl, hipMalloc(&pl->ws.M, bytes));
         FMM_HIP(pl, hipMalloc(&pl->ws.Lt, bytes));
-        for (int g = 0; g < kM2LGroups; ++g) FMM_HIP(pl, hipMalloc(&pl->ws.Lp[g], bytes));
+        FMM_HIP(pl, hipMalloc(&pl->ws.Lm, bytes));
         if (pl->kind == FMM_GRID && pl->bem) {
             // the boundary-source pass writes only boundary cells of M2 and
-            // only edge tiles of Lp2: everything else must stay zero
+            // only edge tiles of Lm2: everything else must stay zero
             FMM_HIP(pl, hipMalloc(&pl->ws.M2, bytes));
             FMM_HIP(pl, hipMemset(pl->ws.M2, 0, bytes));
             FMM_HIP(pl, hipMalloc(&pl->ws.Lt2, bytes));
-            for (int g = 0; g < kM2LGroups; ++g) {
-                FMM_HIP(pl, hipMalloc(&pl->ws.Lp2[g], bytes));
-                FMM_HIP(pl, hipMemset(pl->ws.Lp2[g], 0, bytes));
-            }
+            FMM_HIP(pl, hipMalloc(&pl->ws.Lm2, bytes));
+            FMM_HIP(pl, hipMemset(pl->ws.Lm2, 0, bytes));
         }
     }
     return FMM_OK;
@@ -202,10 +215,9 @@ static int build_levels_and_work(fmm_plan *pl)
 
 static void release(fmm_plan *pl)
 {
-    void *ptrs[] = {pl->tab.m2m, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
-                    pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->ws.M, pl->ws.Lt,
-                    pl->ws.Lp[0], pl->ws.Lp[1], pl->ws.Lp[2], pl->ws.M2, pl->ws.Lt2,
-                    pl->ws.Lp2[0], pl->ws.Lp2[1], pl->ws.Lp2[2], pl->m2l_items,
+    void *ptrs[] = {pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+                    pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
+                    pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->m2l_edge_items, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
                     pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
                     pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal};

@@ -3,12 +3,15 @@
 // The grid is uniform, so every leaf holds the same 8 x 8 point pattern and
 // every translation operator depends only on a small integer offset.  The
 // stages are:
-//   P2M    (Sec. 5.3 item 1)  leaf multipoles, a fixed p x 64 weight table
-//   M2M    (item 2)           4 fixed quadrant matrices, one launch per level
+//   P2M + M2M (Sec. 5.3 items 1-2)  one block per 8x8 tile of cells builds the
+//                             tile's multipoles and those of its ancestors
+//                             three levels up (LDS), so the upward pass is
+//                             ceil((L-1)/3) launches
 //   M2L    (item 3)           one launch for all levels; a block is a 16x16
 //                             tile of target cells and a third of their
 //                             27-entry lists, sources staged in LDS
-//   L2L    (item 4)           Taylor shift by the child offset, per level
+//   L2L    (item 4)           one block per cell three levels up builds the
+//                             local expansions of its 2x2, 4x4, 8x8 descendants
 //   L2P + P2P (item 5, Sec. 5.1)  one fused leaf kernel; the near field is a
 //                             3x3-leaf restricted convolution whose kernel
 //                             values log(h|d|) are wave-uniform (scalar
@@ -16,6 +19,10 @@
 //
 // Expansions are scaled by the cell width w of their level (M~_k = M_k/w^k,
 // L~_k = L_k w^k), which makes M2M, M2L and L2L level independent.
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "fmm_internal.h"
 
 namespace fmmprec {
@@ -31,75 +38,170 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// ---------------------------------------------------------------------------
-// P2M on grid leaves: M~_k = qscale * sum_j W[k][j] q_j with
-// W[0][j] = 1, W[k][j] = -tau_j^k / k, tau_j = ((a-3.5) + i(b-3.5)) / 8.
-// Block: 256 threads = 32 leaves of one leaf row x 8 coefficient lanes.
-// ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void k_p2m_grid(const double *__restrict__ q, double qscale,
-                                                  const double2 *__restrict__ W,
-                                                  double2 *__restrict__ M, int n, int nl)
+__device__ __forceinline__ double wave_sum(double a)
 {
-    __shared__ double sq[8][256 + 2];
-    __shared__ double2 sw[P][64];
-    const int tid = threadIdx.x;
-    const int ly = blockIdx.y;
-    const int lx0 = blockIdx.x * 32;
-    for (int e = tid; e < P * 64; e += 256) sw[e >> 6][e & 63] = W[e];
-    const int gx = lx0 * 8 + tid;
-    for (int b = 0; b < 8; ++b)
-        sq[b][tid] = (gx < n) ? q[(size_t)(ly * 8 + b) * n + gx] : 0.0;
-    __syncthreads();
-    const int lxl = tid >> 3, g = tid & 7;
-    const int lx = lx0 + lxl;
-    if (lx >= nl) return;
-    const int64_t ncell = (int64_t)nl * nl;
-    const int64_t cell = (int64_t)ly * nl + lx;
-    for (int k = g; k < P; k += 8) {
-        double ax = 0.0, ay = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < 64; ++j) {
-            const double v = sq[j >> 3][lxl * 8 + (j & 7)];
-            ax = fma(sw[k][j].x, v, ax);
-            ay = fma(sw[k][j].y, v, ay);
-        }
-        M[k * ncell + cell] = make_double2(ax * qscale, ay * qscale);
-    }
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    return a;
 }
 
 // ---------------------------------------------------------------------------
-// M2M: parent (ix, iy) of level l from its 4 children at level l+1.
-// A[qd][n][k] (k <= n), qd = 2*(child y parity) + (child x parity).
+// Upward pass.
+// m2m_tile: parents of a cw x cw child tile held in LDS as [k][cw*cw];
+// A = M2M table [4 quadrants][P][P] (lower triangular), quadrant
+// qd = 2*(child y parity) + (child x parity).
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(256) void k_m2m(const double2 *__restrict__ Mc,
-                                             double2 *__restrict__ Mp,
-                                             const double2 *__restrict__ A, int ncp)
+__device__ __forceinline__ void m2m_tile(const double2 *__restrict__ sA,
+                                         const double2 *__restrict__ child,
+                                         double2 *__restrict__ parent, int cw)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= ncp * ncp) return;
-    const int ix = idx % ncp, iy = idx / ncp;
-    const int ncc = 2 * ncp;
-    const int64_t nC = (int64_t)ncc * ncc, nP = (int64_t)ncp * ncp;
-    double2 acc[P];
+    const int pw = cw >> 1, np = pw * pw, nch = cw * cw;
+    for (int t = threadIdx.x; t < np * P; t += blockDim.x) {
+        const int nn = t / np, pc = t - nn * np;
+        const int px = pc % pw, py = pc / pw;
+        double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
+        for (int qd = 0; qd < 4; ++qd) {
+            const int ci = (2 * py + (qd >> 1)) * cw + 2 * px + (qd & 1);
+            const double2 *Ar = sA + (qd * P + nn) * P;
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-        const int cx = 2 * ix + (qd & 1), cy = 2 * iy + (qd >> 1);
-        const int64_t cc = (int64_t)cy * ncc + cx;
-        double2 mc[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) mc[k] = Mc[k * nC + cc];
-        const double2 *Aq = A + qd * P * P;
-#pragma unroll
-        for (int nn = 0; nn < P; ++nn)
-#pragma unroll
-            for (int k = 0; k <= nn; ++k) cmac(acc[nn], Aq[nn * P + k], mc[k]);
+            for (int k = 0; k < P; ++k)
+                if (k <= nn) cmac(acc, Ar[k], child[k * nch + ci]);
+        }
+        parent[nn * np + pc] = acc;
     }
+}
+
+// tile (LDS [k][tw*tw]) -> level array at origin (x0, y0)
+template <int P>
+__device__ __forceinline__ void store_tile(const double2 *__restrict__ src, double2 *__restrict__ Ml,
+                                           int nc, int x0, int y0, int tw)
+{
+    const int cnt = tw * tw;
+    const int64_t ncell = (int64_t)nc * nc;
+    for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
+        const int k = t / cnt, c = t - k * cnt;
+        Ml[k * ncell + (int64_t)(y0 + c / tw) * nc + x0 + c % tw] = src[t];
+    }
+}
+
+// tile coordinates of block b: all tiles row-major, or only the border tiles
+__device__ __forceinline__ void tile_of_block(int b, int nt, int edge_only, int &tx, int &ty)
+{
+    if (!edge_only || nt == 1) {
+        tx = b % nt;
+        ty = b / nt;
+        return;
+    }
+    const int side = b / (nt - 1), k = b - side * (nt - 1);
+    if (side == 0) { tx = k; ty = 0; }
+    else if (side == 1) { tx = nt - 1; ty = k; }
+    else if (side == 2) { tx = nt - 1 - k; ty = nt - 1; }
+    else { tx = 0; ty = nt - 1 - k; }
+}
+
+// multipoles of a tile three more levels up, each level stored to global
+template <int P>
+__device__ __forceinline__ void m2m_chain(const double2 *sA, double2 *s0, double2 *s1, double2 *s2,
+                                          double2 *s3, double2 *__restrict__ M, const LevelInfo &lv,
+                                          int l, int tw, int x0, int y0)
+{
+    double2 *cur = s0;
+    double2 *bufs[3] = {s1, s2, s3};
+    for (int st = 0; st < 3 && l - 1 >= 2 && tw >= 2; ++st) {
+        m2m_tile<P>(sA, cur, bufs[st], tw);
+        __syncthreads();
+        tw >>= 1;
+        --l;
+        x0 >>= 1;
+        y0 >>= 1;
+        store_tile<P>(bufs[st], M + lv.off[l], 1 << l, x0, y0, tw);
+        cur = bufs[st];
+    }
+}
+
+// P2M at the leaves of an 8x8-leaf tile, then M2M three levels up:
+// M~_k = qscale sum_j W[k][j] q_j, W[0][j] = 1, W[k][j] = -tau_j^k / k,
+// tau_j = ((a-3.5) + i(b-3.5)) / 8, j = 8b + a.  Lane = leaf; wave w
+// computes coefficients w, w+4, ...  The 64x64 point tile sits in LDS at
+// y*73 + (x/8)*9 + x%8: 9 doubles per leaf and 73 per row put the 32 lanes
+// of each half-wave on 32 distinct bank pairs.
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m_up(const double *__restrict__ q, double qscale,
+                                                const double2 *__restrict__ W,
+                                                const double2 *__restrict__ A,
+                                                double2 *__restrict__ M, LevelInfo lv, int n, int L)
+{
+    __shared__ double sq[64 * 73];
+    __shared__ double2 sw[P * 64];
+    __shared__ double2 sA[4 * P * P];
+    __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
+    const int nl = 1 << L, tw = nl < 8 ? nl : 8, pw = tw * 8;
+    const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < P * 64; e += 256) sw[e] = W[e];
+    for (int e = tid; e < 4 * P * P; e += 256) sA[e] = A[e];
+    for (int e = tid; e < pw * pw; e += 256) {
+        const int yy = e / pw, xx = e - yy * pw;
+        sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = q[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx];
+    }
+    __syncthreads();
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int nleaf = tw * tw;
+    constexpr int KW = (P + 3) / 4;
+    if (lane < nleaf) {
+        const int lx = lane % tw, ly = lane / tw;
+        const double *base = sq + ly * 8 * 73 + lx * 9;
+        double ax[KW], ay[KW];
 #pragma unroll
-    for (int k = 0; k < P; ++k) Mp[k * nP + idx] = acc[k];
+        for (int i = 0; i < KW; ++i) ax[i] = ay[i] = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < 64; ++j) {
+            const double v = base[(j >> 3) * 73 + (j & 7)];
+#pragma unroll
+            for (int i = 0; i < KW; ++i) {
+                const int k = w + 4 * i;
+                if (k < P) {
+                    const double2 wk = sw[k * 64 + j];
+                    ax[i] = fma(wk.x, v, ax[i]);
+                    ay[i] = fma(wk.y, v, ay[i]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < KW; ++i) {
+            const int k = w + 4 * i;
+            if (k < P) s0[k * nleaf + lane] = make_double2(ax[i] * qscale, ay[i] * qscale);
+        }
+    }
+    __syncthreads();
+    store_tile<P>(s0, M + lv.off[L], nl, lx0, ly0, tw);
+    m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, L, tw, lx0, ly0);
+}
+
+// M2M from level l_in three levels up, one 8x8 tile of level-l_in cells per
+// block (only the border tiles when edge_only: the boundary-source pass has
+// non-zero multipoles in boundary cells only).
+template <int P>
+__global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
+                                                const double2 *__restrict__ A, LevelInfo lv,
+                                                int l_in, int edge_only)
+{
+    __shared__ double2 sA[4 * P * P];
+    __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
+    const int nc = 1 << l_in, tw = nc < 8 ? nc : 8, nt = nc / tw;
+    int tx, ty;
+    tile_of_block(blockIdx.x, nt, edge_only, tx, ty);
+    const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
+    const int64_t ncell = (int64_t)nc * nc;
+    const double2 *Ml = M + lv.off[l_in];
+    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sA[e] = A[e];
+    for (int t = threadIdx.x; t < P * cnt; t += 256) {
+        const int k = t / cnt, c = t - k * cnt;
+        s0[t] = Ml[k * ncell + (int64_t)(y0 + c / tw) * nc + x0 + c % tw];
+    }
+    __syncthreads();
+    m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, l_in, tw, x0, y0);
 }
 
 // ---------------------------------------------------------------------------
@@ -109,31 +211,30 @@ __global__ __launch_bounds__(256) void k_m2m(const double2 *__restrict__ Mc,
 //   M'_0 = -M~_0, M'_k = M~_k/(k-1)!,
 //   H_0 = -(log|d^| + log w), H_m = (m-1)!/d^^m.
 // A block is a 16x16 tile of target cells (the whole level if it is
-// smaller) and one of the three 9-entry thirds of their interaction lists.
-// Wave w serves the cells of parity class (w&1, w>>1): those share one list
-// shape, so the offset and its Hankel generators are wave-uniform.
-// Sources (20x20 cells around the tile) are staged in LDS split by parity,
-// which makes the per-offset LDS reads of a wave consecutive.
+// smaller) with 12 waves: wave w serves parity class w&3 (cells that share
+// one list shape, so the offset and its Hankel generators are wave-uniform)
+// and third w>>2 of the 27-entry list.  Sources (20x20 cells around the
+// tile) are staged once in LDS, split by parity so that the per-offset LDS
+// reads of a wave are consecutive; the three thirds are summed in LDS in a
+// fixed order.
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(256) void k_m2l(const M2LItem *__restrict__ items,
+__global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                                              const double2 *__restrict__ M,
-                                             double2 *__restrict__ Lp0,
-                                             double2 *__restrict__ Lp1,
-                                             double2 *__restrict__ Lp2, LevelInfo lv,
+                                             double2 *__restrict__ Lm, LevelInfo lv,
                                              const double2 *__restrict__ hank,
                                              const int4 *__restrict__ offs,
                                              const double *__restrict__ a_n,
                                              const double *__restrict__ b_k)
 {
-    extern __shared__ double2 sm[];  // [P][RW*RW], parity split
+    extern __shared__ double2 sm[];  // [P][RW*RW] parity split; later [P][256] reduction
     const M2LItem it = items[blockIdx.x];
     const int l = it.level, nc = 1 << l;
     const int tw = nc < 16 ? nc : 16;
     const int RW = tw + 4, RH = RW >> 1, SUB = RH * RH, RR = RW * RW;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l];
-    for (int e = threadIdx.x; e < P * RR; e += 256) {
+    for (int e = threadIdx.x; e < P * RR; e += 768) {
         const int k = e / RR, r = e - k * RR;
         const int sy = r / RW, sx = r - sy * RW;
         const int gx = it.tx0 - 2 + sx, gy = it.ty0 - 2 + sy;
@@ -149,14 +250,15 @@ __global__ __launch_bounds__(256) void k_m2l(const M2LItem *__restrict__ items,
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int px = wave & 1, py = wave >> 1;
+    const int cls = wave & 3, grp = wave >> 2;
+    const int px = cls & 1, py = cls >> 1;
     const int ltx = 2 * (lane & 7) + px, lty = 2 * (lane >> 3) + py;
     const bool active = ltx < tw && lty < tw;
     double2 acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
     const double logw = lv.logw[l];
-    const int4 *ol = offs + wave * 27 + it.group * 9;
+    const int4 *ol = offs + cls * 27 + grp * 9;
     if (active) {
         for (int o = 0; o < 9; ++o) {
             const int4 od = ol[o];
@@ -177,9 +279,27 @@ __global__ __launch_bounds__(256) void k_m2l(const M2LItem *__restrict__ items,
             }
         }
     }
-    if (!active) return;
+    // sum the three list thirds: (third 0 + third 1) + third 2
+    const int slot = cls * 64 + lane;
+    for (int g = 1; g < 3; ++g) {
+        __syncthreads();
+        if (grp == g && active) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) sm[k * 256 + slot] = acc[k];
+        }
+        __syncthreads();
+        if (grp == 0 && active) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double2 v = sm[k * 256 + slot];
+                acc[k].x += v.x;
+                acc[k].y += v.y;
+            }
+        }
+    }
+    if (grp != 0 || !active) return;
     const int tx = it.tx0 + ltx, ty = it.ty0 + lty;
-    double2 *out = (it.group == 0 ? Lp0 : (it.group == 1 ? Lp1 : Lp2)) + lv.off[l];
+    double2 *out = Lm + lv.off[l];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const double an = a_n[k];
@@ -187,74 +307,69 @@ __global__ __launch_bounds__(256) void k_m2l(const M2LItem *__restrict__ items,
     }
 }
 
-// Taylor shift of a local expansion to a child: L~child_n = 2^-n sum_{k>=n}
-// C(k,n) c^(k-n) L~parent_k with c = (child centre - parent centre)/w_parent
-// = ((ex - 1/2) + i(ey - 1/2)) / 2.  Repeated synthetic division.
+// ---------------------------------------------------------------------------
+// Downward pass: one block per cell at level r builds the local expansions
+// of its descendants at levels r+1 .. r+m (m <= 3):
+//   L~child_n = sum_{k>=n} B[qd][n][k] L~parent_k + (M2L sum of the child),
+//   B[qd][n][k] = C(k,n) c^(k-n) 2^-n, c = (child - parent centre)/w_parent.
+// With top = 1 the root is a level-2 cell, whose expansion is its M2L sum
+// alone (lists start at level 2), and is written too.  All M2L sums the
+// block needs are fetched into LDS up front (one memory round trip).
+// ---------------------------------------------------------------------------
 template <int P>
-__device__ __forceinline__ void l2l_shift(double2 a[P], int ex, int ey)
+__global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
+                                              double2 *__restrict__ Lt,
+                                              const double2 *__restrict__ B, LevelInfo lv, int r,
+                                              int m, int top)
 {
-    const double2 c = make_double2(0.5 * (ex - 0.5), 0.5 * (ey - 0.5));
-#pragma unroll
-    for (int i = 0; i < P - 1; ++i)
-#pragma unroll
-        for (int k = P - 2; k >= i; --k) cmac(a[k], c, a[k + 1]);
-    double sc = 1.0;
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        a[k].x *= sc;
-        a[k].y *= sc;
-        sc *= 0.5;
+    __shared__ double2 sB[4 * P * P];
+    __shared__ double2 sm2l[P * 84];          // M2L sums of the 4 + 16 + 64 descendants
+    __shared__ double2 buf0[P * 64], buf1[P * 64];
+    const int nr = 1 << r;
+    const int rx = blockIdx.x % nr, ry = blockIdx.x / nr;
+    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sB[e] = B[e];
+    // descendants' M2L sums: level r+st occupies [base_st, base_st + 4^st)
+    for (int st = 1; st <= m; ++st) {
+        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
+        const int base = ((1 << (2 * st)) - 4) / 3;   // 0, 4, 20
+        const int64_t ncell = (int64_t)nc * nc;
+        for (int t = threadIdx.x; t < P * cnt; t += 256) {
+            const int nn = t / cnt, c = t - nn * cnt;
+            sm2l[nn * 84 + base + c] =
+                Lm[lv.off[l] + nn * ncell + (int64_t)(ry * tw + c / tw) * nc + rx * tw + c % tw];
+        }
     }
-}
-
-// Local expansion of cell (ix, iy) at level l: sum of its M2L partials plus
-// the shifted expansion of its parent (levels >= 3).
-template <int P>
-__device__ __forceinline__ void local_expansion(const double2 *__restrict__ Lp0,
-                                                const double2 *__restrict__ Lp1,
-                                                const double2 *__restrict__ Lp2,
-                                                const double2 *__restrict__ Lt,
-                                                const LevelInfo &lv, int l, int ix, int iy,
-                                                double2 out[P])
-{
-    const int nc = 1 << l;
-    const int64_t ncell = (int64_t)nc * nc, cell = (int64_t)iy * nc + ix;
-    if (l >= 3) {
-        const int ncp = nc >> 1;
-        const int64_t nP = (int64_t)ncp * ncp, pc = (int64_t)(iy >> 1) * ncp + (ix >> 1);
-        const double2 *Lpar = Lt + lv.off[l - 1];
-#pragma unroll
-        for (int k = 0; k < P; ++k) out[k] = Lpar[k * nP + pc];
-        l2l_shift<P>(out, ix & 1, iy & 1);
-    } else {
-#pragma unroll
-        for (int k = 0; k < P; ++k) out[k] = make_double2(0.0, 0.0);
+    if (threadIdx.x < P) {
+        const int64_t gi = lv.off[r] + (int64_t)threadIdx.x * nr * nr + (int64_t)ry * nr + rx;
+        const double2 v = top ? Lm[gi] : Lt[gi];
+        buf0[threadIdx.x] = v;
+        if (top) Lt[gi] = v;
     }
-    const int64_t o = lv.off[l];
+    __syncthreads();
+    const double2 *prev = buf0;
+    int pw = 1;
+    for (int st = 1; st <= m; ++st) {
+        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
+        const int base = ((1 << (2 * st)) - 4) / 3;
+        const int64_t ncell = (int64_t)nc * nc;
+        double2 *next = (st & 1) ? buf1 : buf0;
+        const int pcnt = pw * pw;
+        for (int t = threadIdx.x; t < P * cnt; t += 256) {
+            const int nn = t / cnt, c = t - nn * cnt;
+            const int cx = c % tw, cy = c / tw;
+            const int pc = (cy >> 1) * pw + (cx >> 1), qd = (cy & 1) * 2 + (cx & 1);
+            double2 acc = sm2l[nn * 84 + base + c];
+            const double2 *Br = sB + (qd * P + nn) * P;
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const double2 a = Lp0[o + k * ncell + cell], b = Lp1[o + k * ncell + cell],
-                      c = Lp2[o + k * ncell + cell];
-        out[k].x += (a.x + b.x) + c.x;
-        out[k].y += (a.y + b.y) + c.y;
+            for (int k = 0; k < P; ++k)
+                if (k >= nn) cmac(acc, Br[k], prev[k * pcnt + pc]);
+            next[t] = acc;
+            Lt[lv.off[l] + nn * ncell + (int64_t)(ry * tw + cy) * nc + rx * tw + cx] = acc;
+        }
+        __syncthreads();
+        prev = next;
+        pw = tw;
     }
-}
-
-// L2L cascade: Lt[l] for one level (2 <= l <= L-1)
-template <int P>
-__global__ __launch_bounds__(256) void k_l2l(const double2 *__restrict__ Lp0,
-                                             const double2 *__restrict__ Lp1,
-                                             const double2 *__restrict__ Lp2,
-                                             double2 *__restrict__ Lt, LevelInfo lv, int l)
-{
-    const int nc = 1 << l;
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= nc * nc) return;
-    double2 a[P];
-    local_expansion<P>(Lp0, Lp1, Lp2, Lt, lv, l, idx % nc, idx / nc, a);
-    const int64_t ncell = (int64_t)nc * nc;
-#pragma unroll
-    for (int k = 0; k < P; ++k) Lt[lv.off[l] + k * ncell + idx] = a[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -270,8 +385,9 @@ struct LeafArgs {
     const double *q;
     double qscale;
     double *u;
-    const double2 *Lp0, *Lp1, *Lp2, *Lt;
+    const double2 *Lt;    // local expansions (leaf level used)
     const double *ktab;   // [31][31]
+    const double *rtab;   // [17][17]
     const double2 *l2p;   // [64][P]
     LevelInfo lv;
     int n, nl, L, far;
@@ -334,8 +450,11 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
 #pragma unroll
     for (int t = 0; t < 16; ++t) far[t] = 0.0;
     if (a.far) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        const double2 *Ll = a.Lt + a.lv.off[a.L];
         double2 Lc[P];
-        local_expansion<P>(a.Lp0, a.Lp1, a.Lp2, a.Lt, a.lv, a.L, gLx, gLy, Lc);
+#pragma unroll
+        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const double2 *tp = a.l2p + ((ty0 + (t >> 3)) * 8 + (t & 7)) * P;
@@ -370,82 +489,92 @@ __device__ __forceinline__ int leaf_of(int I, int nl)
     return l < nl ? l : nl - 1;
 }
 
+// Re sum_k L_k tau^k
+template <int P>
+__device__ __forceinline__ double l2p_eval(const double2 *__restrict__ Lc, double2 tau)
+{
+    double s = 0.0;
+    double2 pw = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double2 c = Lc[k];
+        s = fma(c.x, pw.x, fma(-c.y, pw.y, s));
+        pw = cmul(pw, tau);
+    }
+    return s;
+}
+
 // ---------------------------------------------------------------------------
-// Pass-1 potential at the 4n ring nodes: near field from the 3x3 leaves
-// around the attached boundary leaf (direct log), far field by L2P from
-// that leaf's local expansion.
+// Pass-1 potential at the 4n ring nodes, one wave per node: near field from
+// the (at most 6) in-domain leaves of the 3x3 block around the attached
+// boundary leaf, split over the lanes and summed with shuffles; far field by
+// L2P from that leaf's local expansion.
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__restrict__ phi)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int n = a.n, nl = a.nl;
     if (t >= 4 * n) return;
     int Ix, Iy;
     ring_node(t, n, Ix, Iy);
     const int lx = leaf_of(Ix, nl), ly = leaf_of(Iy, nl);
-    const double h = 1.0 / (double)(n + 1);
     double near = 0.0;
+    const int ia = lane & 7, jb = lane >> 3;
     for (int b = -1; b <= 1; ++b)
         for (int c = -1; c <= 1; ++c) {
             const int qx = lx + c, qy = ly + b;
             if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
-            for (int j = 0; j < 8; ++j) {
-                const int gy = qy * 8 + j;
-                const double dy = (double)(Iy - (gy + 1));
-                for (int i = 0; i < 8; ++i) {
-                    const int gx = qx * 8 + i;
-                    const double dx = (double)(Ix - (gx + 1));
-                    near = fma(a.q[(size_t)gy * n + gx], log(h * sqrt(dx * dx + dy * dy)), near);
-                }
-            }
+            const int gx = qx * 8 + ia, gy = qy * 8 + jb;
+            const int dx = abs(Ix - (gx + 1)), dy = abs(Iy - (gy + 1));
+            near = fma(a.q[(size_t)gy * n + gx], a.rtab[dy * 17 + dx], near);
         }
+    near = wave_sum(near);
     double far = 0.0;
-    if (a.far) {
+    if (a.far && lane == 0) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
+        const double2 *Ll = a.Lt + a.lv.off[a.L];
         double2 Lc[P];
-        local_expansion<P>(a.Lp0, a.Lp1, a.Lp2, a.Lt, a.lv, a.L, lx, ly, Lc);
-        const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
-        double2 pw = make_double2(1.0, 0.0);
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            far = fma(Lc[k].x, pw.x, fma(-Lc[k].y, pw.y, far));
-            pw = cmul(pw, tau);
-        }
+        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
+        far = l2p_eval<P>(Lc, make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125));
     }
-    phi[t] = -(fma(a.qscale, near, far)) * kInv2Pi;
+    if (lane == 0) phi[t] = -(fma(a.qscale, near, far)) * kInv2Pi;
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2 (boundary sources): P2M of the ring charges into the boundary
 // leaves they attach to.  Interior leaves are never written (stay zero).
 // ---------------------------------------------------------------------------
-// ring nodes attached to leaf (lx, ly): up to two runs of 8 consecutive
-// node indices; returns the number of runs.
+// ring nodes attached to leaf (lx, ly) with nl >= 2: one or two runs of 8
+// consecutive node indices; returns the number of runs.
 __device__ __forceinline__ int attached_runs(int lx, int ly, int n, int nl, int start[2])
 {
     int r = 0;
-    if (ly == 0) start[r++] = 8 * lx;                        // bottom
-    if (lx == nl - 1 && r < 2) start[r++] = n + 8 * ly;        // right
+    if (ly == 0) start[r++] = 8 * lx;                                   // bottom
+    if (lx == nl - 1 && r < 2) start[r++] = n + 8 * ly;                 // right
     if (ly == nl - 1 && r < 2) start[r++] = 2 * n + (n - 8 * lx - 8);   // top
     if (lx == 0 && r < 2) start[r++] = 3 * n + (n - 8 * ly - 8);        // left
     return r;
 }
 
+// one thread per (boundary leaf, coefficient k); 4 (nl - 1) boundary leaves, nl >= 2
 template <int P>
 __global__ __launch_bounds__(256) void k_p2m_ring(const double *__restrict__ rq,
                                                   double2 *__restrict__ M, int n, int nl)
 {
     const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= nl * nl) return;
-    const int lx = idx % nl, ly = idx / nl;
-    if (!(lx == 0 || ly == 0 || lx == nl - 1 || ly == nl - 1)) return;
+    if (idx >= 4 * (nl - 1) * P) return;
+    const int k = idx % P, bl = idx / P;
+    const int side = bl / (nl - 1), kk = bl - side * (nl - 1);
+    int lx, ly;
+    if (side == 0) { lx = kk; ly = 0; }
+    else if (side == 1) { lx = nl - 1; ly = kk; }
+    else if (side == 2) { lx = nl - 1 - kk; ly = nl - 1; }
+    else { lx = 0; ly = nl - 1 - kk; }
     int start[2];
-    // a leaf in a corner touches two sides; with nl == 1 it touches four,
-    // which only happens for L = 0, where no multipoles are used
     const int runs = attached_runs(lx, ly, n, nl, start);
-    double2 m[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) m[k] = make_double2(0.0, 0.0);
+    double2 m = make_double2(0.0, 0.0);
     for (int r = 0; r < runs; ++r)
         for (int j = 0; j < 8; ++j) {
             const int t = start[r] + j;
@@ -453,88 +582,122 @@ __global__ __launch_bounds__(256) void k_p2m_ring(const double *__restrict__ rq,
             ring_node(t, n, Ix, Iy);
             const double c = rq[t];
             const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
-            m[0].x += c;
             double2 pw = make_double2(1.0, 0.0);
-#pragma unroll
-            for (int k = 1; k < P; ++k) {
-                pw = cmul(pw, tau);
-                m[k].x -= c * pw.x / k;
-                m[k].y -= c * pw.y / k;
-            }
+            for (int e = 0; e < k; ++e) pw = cmul(pw, tau);
+            m.x += c * pw.x;
+            m.y += c * pw.y;
         }
-    const int64_t ncell = (int64_t)nl * nl;
-#pragma unroll
-    for (int k = 0; k < P; ++k) M[k * ncell + idx] = m[k];
+    // M~_0 = sum c, M~_k = -sum c tau^k / k
+    const double f = (k == 0) ? 1.0 : -1.0 / (double)k;
+    const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
+    M[k * ncell + cell] = make_double2(f * m.x, f * m.y);
 }
 
-// Pass 2 at the interior nodes: u += -(1/2pi) [ L2P + direct sum over the
-// ring nodes attached to the 3x3 neighbouring leaves ].  Block = 4 leaves
-// of 64 points; the leaf's local expansion is built once per leaf.
+// Pass 2 far field at the interior nodes: u += -(1/2pi) Re sum_k L~_k tau^k.
+// Block = a tile of up to 8x8 leaves whose local expansions are staged in
+// LDS; threads walk rows of the tile, so the read-modify-write of u is
+// coalesced.
 template <int P>
-__global__ __launch_bounds__(256) void k_pass2_leaf(LeafArgs a, const double *__restrict__ rq)
+__global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a)
 {
-    __shared__ double2 sL[4][P];
-    const int n = a.n, nl = a.nl;
-    const int sub = threadIdx.x >> 6, j = threadIdx.x & 63;
-    const int leaf = blockIdx.x * 4 + sub;
-    const bool valid = leaf < nl * nl;
-    const int lx = valid ? leaf % nl : 0, ly = valid ? leaf / nl : 0;
-    if (a.far && j == 0 && valid) {
-        double2 Lc[P];
-        local_expansion<P>(a.Lp0, a.Lp1, a.Lp2, a.Lt, a.lv, a.L, lx, ly, Lc);
-#pragma unroll
-        for (int k = 0; k < P; ++k) sL[sub][k] = Lc[k];
+    __shared__ double2 sL[P * 64];
+    const int n = a.n, nl = a.nl, tw = nl < 8 ? nl : 8, pw = tw * 8;
+    const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw, cnt = tw * tw;
+    const int64_t ncell = (int64_t)nl * nl;
+    const double2 *Ll = a.Lt + a.lv.off[a.L];
+    for (int t = threadIdx.x; t < P * cnt; t += 256) {
+        const int k = t / cnt, c = t - k * cnt;
+        sL[t] = Ll[k * ncell + (int64_t)(ly0 + c / tw) * nl + lx0 + c % tw];
     }
     __syncthreads();
-    if (!valid) return;
-    const int ia = j & 7, jb = j >> 3;
-    double far = 0.0;
-    if (a.far) {
-        const double2 *tp = a.l2p + j * P;
+    for (int e = threadIdx.x; e < pw * pw; e += 256) {
+        const int yy = e / pw, xx = e - yy * pw;
+        const int lc = (yy >> 3) * tw + (xx >> 3);
+        const double2 tau = make_double2(((xx & 7) - 3.5) * 0.125, ((yy & 7) - 3.5) * 0.125);
+        double far = 0.0;
+        double2 pk = make_double2(1.0, 0.0);
 #pragma unroll
-        for (int k = 0; k < P; ++k) far = fma(sL[sub][k].x, tp[k].x, fma(-sL[sub][k].y, tp[k].y, far));
+        for (int k = 0; k < P; ++k) {
+            const double2 c = sL[k * cnt + lc];
+            far = fma(c.x, pk.x, fma(-c.y, pk.y, far));
+            pk = cmul(pk, tau);
+        }
+        a.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far * kInv2Pi;
     }
-    const int gx = lx * 8 + ia, gy = ly * 8 + jb;
+}
+
+// Pass 2 near field: u += -(1/2pi) sum over the ring nodes attached to the
+// 3x3 leaves around the target's leaf.  Only targets within two leaves of
+// the boundary have such neighbours: one thread per point of that band
+// (every point when n <= 32).
+__global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
+                                                    const double *__restrict__ rq,
+                                                    const double *__restrict__ rtab, int n, int nl)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int gx, gy;
+    if (n <= 32) {
+        if (idx >= (int64_t)n * n) return;
+        gx = (int)(idx % n);
+        gy = (int)(idx / n);
+    } else {
+        const int B = 16;
+        const int64_t strip = (int64_t)B * n, side = (int64_t)B * (n - 2 * B);
+        if (idx < strip) {
+            gy = (int)(idx / n); gx = (int)(idx % n);
+        } else if (idx < 2 * strip) {
+            const int64_t i2 = idx - strip;
+            gy = n - B + (int)(i2 / n); gx = (int)(i2 % n);
+        } else if (idx < 2 * strip + side) {
+            const int64_t i3 = idx - 2 * strip;
+            gy = B + (int)(i3 / B); gx = (int)(i3 % B);
+        } else if (idx < 2 * strip + 2 * side) {
+            const int64_t i4 = idx - 2 * strip - side;
+            gy = B + (int)(i4 / B); gx = n - B + (int)(i4 % B);
+        } else {
+            return;
+        }
+    }
+    const int lx = gx >> 3, ly = gy >> 3;
     double near = 0.0;
-    if (lx <= 1 || ly <= 1 || lx >= nl - 2 || ly >= nl - 2) {
-        const double h = 1.0 / (double)(n + 1);
-        for (int b = -1; b <= 1; ++b)
-            for (int c = -1; c <= 1; ++c) {
-                const int qx = lx + c, qy = ly + b;
-                if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
-                if (!(qx == 0 || qy == 0 || qx == nl - 1 || qy == nl - 1)) continue;
-                int start[4], runs = 0;
-                if (nl == 1) {
-                    start[0] = 0; start[1] = n; start[2] = 2 * n; start[3] = 3 * n;
-                    runs = 4;
-                } else {
-                    runs = attached_runs(qx, qy, n, nl, start);
-                }
-                for (int r = 0; r < runs; ++r) {
-                    const int len = (nl == 1) ? n : 8;
-                    for (int e = 0; e < len; ++e) {
-                        const int t = start[r] + e;
-                        int Ix, Iy;
-                        ring_node(t, n, Ix, Iy);
-                        const double dx = (double)(gx + 1 - Ix), dy = (double)(gy + 1 - Iy);
-                        near = fma(rq[t], log(h * sqrt(dx * dx + dy * dy)), near);
-                    }
-                }
+    for (int b = -1; b <= 1; ++b)
+        for (int c = -1; c <= 1; ++c) {
+            const int qx = lx + c, qy = ly + b;
+            if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
+            if (!(qx == 0 || qy == 0 || qx == nl - 1 || qy == nl - 1)) continue;
+            int start[4], runs, len;
+            if (nl == 1) {
+                start[0] = 0; start[1] = n; start[2] = 2 * n; start[3] = 3 * n;
+                runs = 4;
+                len = n;
+            } else {
+                runs = attached_runs(qx, qy, n, nl, start);
+                len = 8;
             }
-    }
-    a.u[(size_t)gy * n + gx] += -(near + far) * kInv2Pi;
+            for (int r = 0; r < runs; ++r)
+                for (int j = 0; j < len; ++j) {
+                    const int t = start[r] + j;
+                    int Ix, Iy;
+                    ring_node(t, n, Ix, Iy);
+                    const int dx = abs(gx + 1 - Ix), dy = abs(gy + 1 - Iy);
+                    near = fma(rq[t], rtab[dy * 17 + dx], near);
+                }
+        }
+    u[(size_t)gy * n + gx] += -near * kInv2Pi;
 }
 
 // ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
 template <int P>
-static void run_m2m(fmm_plan *pl, double2 *M, hipStream_t s)
+static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, int edge_only, hipStream_t s)
 {
-    for (int l = pl->L - 1; l >= 2; --l) {
-        const int ncp = 1 << l;
-        hipLaunchKernelGGL(k_m2m<P>, dim3((ncp * ncp + 255) / 256), dim3(256), 0, s,
-                           M + pl->lv.off[l + 1], M + pl->lv.off[l], pl->tab.m2m, ncp);
+    // each launch lifts the multipoles three levels, from l_in down to 2
+    for (int l = l_in; l > 2; l -= 3) {
+        const int nc = 1 << l, tw = std::min(nc, 8), nt = nc / tw;
+        const int nblk = (edge_only && nt > 1) ? 4 * (nt - 1) : nt * nt;
+        hipLaunchKernelGGL(k_m2m_up<P>, dim3(nblk), dim3(256), 0, s, M, pl->tab.m2m, pl->lv, l,
+                           edge_only);
     }
 }
 
@@ -542,62 +705,75 @@ template <int P>
 static int run_upward(fmm_plan *pl, const double *q, double qscale, double2 *M, hipStream_t s)
 {
     const int L = pl->L, nl = pl->nl;
-    {
-        StageTimer t(pl, FMM_STAGE_P2M, s);
-        dim3 g1((nl + 31) / 32, nl);
-        hipLaunchKernelGGL(k_p2m_grid<P>, g1, dim3(256), 0, s, q, qscale, pl->tab.p2m,
-                           M + pl->lv.off[L], (int)pl->n, nl);
-    }
-    StageTimer t(pl, FMM_STAGE_M2M, s);
-    run_m2m<P>(pl, M, s);
+    StageTimer t(pl, FMM_STAGE_P2M, s);
+    const int tw = std::min(nl, 8);
+    hipLaunchKernelGGL(k_p2m_up<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, q, qscale,
+                       pl->tab.p2m, pl->tab.m2m, M, pl->lv, (int)pl->n, L);
+    t.stop();
+    StageTimer t2(pl, FMM_STAGE_M2M, s);
+    run_m2m_from<P>(pl, M, L - 3, 0, s);
     return FMM_OK;
 }
 
+// downward launches: (root level, levels below it, root is a level-2 cell)
+struct DownChunk {
+    int r, m, top;
+};
+static std::vector<DownChunk> down_chunks(int L)
+{
+    std::vector<DownChunk> ch;
+    ch.push_back({2, std::min(3, L - 2), 1});
+    for (int r = 5; r < L; r += 3) ch.push_back({r, std::min(3, L - r), 0});
+    return ch;
+}
+
 template <int P>
-static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *const Lp[3], double2 *Lt,
+static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
                        const M2LItem *items, int nitems, hipStream_t s, bool timed)
 {
     const size_t shm = (size_t)P * 400 * sizeof(double2);
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(nitems), dim3(256), shm, s, items, M, Lp[0], Lp[1],
-                           Lp[2], pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
-                           pl->tab.m2l_b);
+        hipLaunchKernelGGL(k_m2l<P>, dim3(nitems), dim3(768), shm, s, items, M, Lm, pl->lv,
+                           pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
-    for (int l = 2; l <= pl->L - 1; ++l) {
-        const int nc = 1 << l;
-        hipLaunchKernelGGL(k_l2l<P>, dim3((nc * nc + 255) / 256), dim3(256), 0, s, Lp[0], Lp[1],
-                           Lp[2], Lt, pl->lv, l);
-    }
+    for (const auto &c : down_chunks(pl->L))
+        hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, Lm, Lt, pl->tab.l2l,
+                           pl->lv, c.r, c.m, c.top);
     return FMM_OK;
+}
+
+static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *u,
+                          const double2 *Lt, bool far)
+{
+    LeafArgs a;
+    a.q = q;
+    a.qscale = qscale;
+    a.u = u;
+    a.Lt = Lt;
+    a.ktab = pl->tab.ktab;
+    a.rtab = pl->tab.rtab;
+    a.l2p = pl->tab.l2p;
+    a.lv = pl->lv;
+    a.n = (int)pl->n;
+    a.nl = pl->nl;
+    a.L = pl->L;
+    a.far = far ? 1 : 0;
+    return a;
 }
 
 template <int P>
 static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, double *u,
                              double *ring_out, hipStream_t s)
 {
-    const int L = pl->L, nl = pl->nl;
-    const bool far = L >= 2;
+    const int nl = pl->nl;
+    const bool far = pl->L >= 2;
     if (far) {
         run_upward<P>(pl, q, qscale, pl->ws.M, s);
-        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lp, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
+        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
     }
-    LeafArgs a;
-    a.q = q;
-    a.qscale = qscale;
-    a.u = u;
-    a.Lp0 = pl->ws.Lp[0];
-    a.Lp1 = pl->ws.Lp[1];
-    a.Lp2 = pl->ws.Lp[2];
-    a.Lt = pl->ws.Lt;
-    a.ktab = pl->tab.ktab;
-    a.l2p = pl->tab.l2p;
-    a.lv = pl->lv;
-    a.n = (int)pl->n;
-    a.nl = nl;
-    a.L = L;
-    a.far = far ? 1 : 0;
+    const LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far);
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
@@ -605,7 +781,7 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
-        hipLaunchKernelGGL(k_ring_targets<P>, dim3((4 * pl->n + 255) / 256), dim3(256), 0, s, a,
+        hipLaunchKernelGGL(k_ring_targets<P>, dim3((4 * pl->n + 3) / 4), dim3(256), 0, s, a,
                            ring_out);
     }
     FMM_HIP(pl, hipGetLastError());
@@ -619,28 +795,19 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
     const bool far = L >= 2;
     StageTimer t(pl, FMM_STAGE_PASS2, s);
     if (far) {
-        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((nl * nl + 255) / 256), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((4 * (nl - 1) * P + 255) / 256), dim3(256), 0, s,
                            pl->ring_q, pl->ws.M2 + pl->lv.off[L], (int)pl->n, nl);
-        run_m2m<P>(pl, pl->ws.M2, s);
-        run_m2l_l2l<P>(pl, pl->ws.M2, pl->ws.Lp2, pl->ws.Lt2, pl->m2l_edge_items,
+        run_m2m_from<P>(pl, pl->ws.M2, L, 1, s);
+        run_m2l_l2l<P>(pl, pl->ws.M2, pl->ws.Lm2, pl->ws.Lt2, pl->m2l_edge_items,
                        pl->n_m2l_edge_items, s, false);
+        const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far);
+        const int tw = std::min(nl, 8);
+        hipLaunchKernelGGL(k_pass2_far<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a);
     }
-    LeafArgs a;
-    a.q = nullptr;
-    a.qscale = 1.0;
-    a.u = u;
-    a.Lp0 = pl->ws.Lp2[0];
-    a.Lp1 = pl->ws.Lp2[1];
-    a.Lp2 = pl->ws.Lp2[2];
-    a.Lt = pl->ws.Lt2;
-    a.ktab = pl->tab.ktab;
-    a.l2p = pl->tab.l2p;
-    a.lv = pl->lv;
-    a.n = (int)pl->n;
-    a.nl = nl;
-    a.L = L;
-    a.far = far ? 1 : 0;
-    hipLaunchKernelGGL(k_pass2_leaf<P>, dim3((nl * nl + 3) / 4), dim3(256), 0, s, a, pl->ring_q);
+    const int n = (int)pl->n;
+    const int64_t nband = n <= 32 ? (int64_t)n * n : (int64_t)4 * 16 * n - 4 * 16 * 16;
+    hipLaunchKernelGGL(k_pass2_near, dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s, u,
+                       pl->ring_q, pl->tab.rtab, n, nl);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }

@@ -29,13 +29,10 @@ constexpr int kMaxLevels = 24;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
 
-// number of M2L partial sums (the 27 list entries are split 9 + 9 + 9 so a
-// tile of work is a third of a cell's list, which balances the launch)
-constexpr int kM2LGroups = 3;
-
-// Work item of the all-levels M2L launch: (level, tile origin x, y, group).
+// Work item of the all-levels M2L launch: a tile of target cells at a level.
 struct M2LItem {
-    int16_t level, group;
+    int32_t level;
+    int32_t pad;
     int32_t tx0, ty0;
 };
 
@@ -48,6 +45,7 @@ struct LevelInfo {
 // Device-resident FMM tables for one p.
 struct FmmTables {
     double2 *m2m;     // [4 quadrants][p][p]  M~ parent = A_q M~ child (lower triangular)
+    double2 *l2l;     // [4 quadrants][p][p]  L~ child = B_q L~ parent (upper triangular)
     double2 *hank;    // [7*7 offsets][2p-1]  Hankel generators of M2L (offset index (dy+3)*7+dx+3)
     int4 *m2l_off;    // [4 parity classes][27] (dx, dy, hank index, 0)
     double *m2l_a;    // [p]  (-1)^n / n!   M2L output scale
@@ -55,16 +53,17 @@ struct FmmTables {
     double2 *p2m;     // [p][64] grid P2M weights, -tau_j^k / k (1 for k = 0)
     double2 *l2p;     // [64][p] grid L2P powers tau_j^k
     double *ktab;     // [31][31] log(h |d|), d in [-15, 15]^2, self entry log(eps h)
+    double *rtab;     // [17][17] log(h |d|), |dx|, |dy| <= 16: ring node to interior node
 };
 
 struct Workspace {
-    double2 *M = nullptr;                 // multipoles, levels 2..L
-    double2 *Lt = nullptr;                // local expansions, levels 2..L-1
-    double2 *Lp[kM2LGroups] = {};         // M2L partials, levels 2..L
+    double2 *M = nullptr;    // multipoles, levels 2..L
+    double2 *Lt = nullptr;   // local expansions, levels 2..L
+    double2 *Lm = nullptr;   // M2L sums, levels 2..L
     // second (boundary-source) pass of the preconditioner
     double2 *M2 = nullptr;
     double2 *Lt2 = nullptr;
-    double2 *Lp2[kM2LGroups] = {};
+    double2 *Lm2 = nullptr;
 };
 
 }  // namespace fmmprec

@@ -20,7 +20,7 @@
 namespace fmmprec {
 
 constexpr int kMaxBasis = 32;   // restart <= 32: at most 32 basis vectors in a dot
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = 4096;  // partial sums per reduction (coefficient-major)
 
 // layout of plan->dscal (device) / plan->hpin (host mirror)
 constexpr int kH1 = 0, kHsum = 32, kNrm = 64, kH2 = 96, kScal = 128;
@@ -51,7 +51,7 @@ __device__ __forceinline__ double stencil_at(const double *__restrict__ v, int64
     return c;
 }
 
-// block-level sum of NV per-thread values into part[blockIdx.x * kMaxBasis + i]
+// block-level sum of NV per-thread values into part[i * kRedBlocks + blockIdx.x]
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, double *part)
 {
@@ -67,62 +67,95 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, do
     }
     __syncthreads();
     if (threadIdx.x < nv)
-        part[(size_t)blockIdx.x * kMaxBasis + threadIdx.x] =
+        part[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] =
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-// w = A z (scaled by 1/h^2) and partial dots V_i . w, i < nv
+// w = A z (scaled by 1/h^2) and partial dots V_i . w, i < NV
+template <int NV>
 __global__ __launch_bounds__(256) void k_stencil_dots(const double *__restrict__ z,
                                                       double *__restrict__ w,
                                                       const double *__restrict__ V, int64_t ldv,
-                                                      int nv, double *__restrict__ part, int n,
-                                                      double ih2)
+                                                      double *__restrict__ part, int n, double ih2)
 {
     const int64_t N = (int64_t)n * n;
-    double acc[kMaxBasis];
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < kMaxBasis; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
+        double vv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vv[i] = V[i * ldv + e];
         const double we = stencil_at(z, e, n) * ih2;
         w[e] = we;
 #pragma unroll
-        for (int i = 0; i < kMaxBasis; ++i)
-            if (i < nv) acc[i] = fma(V[i * ldv + e], we, acc[i]);
+        for (int i = 0; i < NV; ++i) acc[i] = fma(vv[i], we, acc[i]);
     }
-    block_reduce_store<kMaxBasis>(acc, nv, part);
+    block_reduce_store<NV>(acc, NV, part);
 }
 
-// w -= sum_i h_i V_i; then partial dots V_i . w (mode 0) or partial w.w (mode 1)
-__global__ __launch_bounds__(256) void k_update(const double *__restrict__ V, int64_t ldv, int nv,
+// w -= sum_i h_i V_i; then partial dots V_i . w (MODE 0) or partial w.w (MODE 1)
+template <int NV, int MODE>
+__global__ __launch_bounds__(256) void k_update(const double *__restrict__ V, int64_t ldv,
                                                 double *__restrict__ w,
                                                 const double *__restrict__ hc,
-                                                double *__restrict__ part, int64_t N, int mode)
+                                                double *__restrict__ part, int64_t N)
 {
-    double acc[kMaxBasis];
+    constexpr int NA = MODE == 0 ? NV : 1;
+    double acc[NA];
 #pragma unroll
-    for (int i = 0; i < kMaxBasis; ++i) acc[i] = 0.0;
-    double hv[kMaxBasis];
+    for (int i = 0; i < NA; ++i) acc[i] = 0.0;
+    double hv[NV];
 #pragma unroll
-    for (int i = 0; i < kMaxBasis; ++i) hv[i] = (i < nv) ? hc[i] : 0.0;
+    for (int i = 0; i < NV; ++i) hv[i] = hc[i];
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-        double vv[kMaxBasis];
+        double vv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) vv[i] = V[i * ldv + e];
         double we = w[e];
 #pragma unroll
-        for (int i = 0; i < kMaxBasis; ++i)
-            if (i < nv) {
-                vv[i] = V[i * ldv + e];
-                we = fma(-hv[i], vv[i], we);
-            }
+        for (int i = 0; i < NV; ++i) we = fma(-hv[i], vv[i], we);
         w[e] = we;
-        if (mode == 0) {
+        if (MODE == 0) {
 #pragma unroll
-            for (int i = 0; i < kMaxBasis; ++i)
-                if (i < nv) acc[i] = fma(vv[i], we, acc[i]);
+            for (int i = 0; i < NA; ++i) acc[i] = fma(vv[i], we, acc[i]);
         } else {
             acc[0] = fma(we, we, acc[0]);
         }
     }
-    block_reduce_store<kMaxBasis>(acc, mode == 0 ? nv : 1, part);
+    block_reduce_store<NA>(acc, NA, part);
+}
+
+#define KRY_NV_CASES(X) \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
+    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+static void launch_stencil_dots(int nv, dim3 g, hipStream_t s, const double *z, double *w,
+                                const double *V, int64_t ldv, double *part, int n, double ih2)
+{
+    switch (nv) {
+#define X(k) case k: hipLaunchKernelGGL(k_stencil_dots<k>, g, dim3(256), 0, s, z, w, V, ldv, part, n, ih2); break;
+        KRY_NV_CASES(X)
+#undef X
+    }
+}
+
+static void launch_update(int nv, int mode, dim3 g, hipStream_t s, const double *V, int64_t ldv,
+                          double *w, const double *hc, double *part, int64_t N)
+{
+    if (mode == 0) {
+        switch (nv) {
+#define X(k) case k: hipLaunchKernelGGL((k_update<k, 0>), g, dim3(256), 0, s, V, ldv, w, hc, part, N); break;
+            KRY_NV_CASES(X)
+#undef X
+        }
+    } else {
+        switch (nv) {
+#define X(k) case k: hipLaunchKernelGGL((k_update<k, 1>), g, dim3(256), 0, s, V, ldv, w, hc, part, N); break;
+            KRY_NV_CASES(X)
+#undef X
+        }
+    }
 }
 
 // r = b - A x, partial r.r
@@ -151,33 +184,31 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ v,
     block_reduce_store<1>(acc, 1, part);
 }
 
-// out[i] = sum_b part[b][i] (+ add[i]); mode 1: out[0] = sqrt(sum); mode 2: also
-// write the sum into out2[i].  Single block, fixed summation order.
-__global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part, int nblk, int nv,
+// out[i] = sum_b part[i][b] (+ add[i]); mode 1: out[i] = sqrt(sum); out2, if
+// given, also receives the plain sum.  One block per coefficient i; the
+// summation order is fixed.
+__global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part, int nblk,
                                                 double *__restrict__ out,
                                                 const double *__restrict__ add,
                                                 double *__restrict__ out2, int mode)
 {
-    __shared__ double red[256];
-    for (int i = 0; i < nv; ++i) {
-        double a = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 256) a += part[(size_t)b * kMaxBasis + i];
-        red[threadIdx.x] = a;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-            __syncthreads();
+    __shared__ double red[4];
+    const int i = blockIdx.x;
+    const double *pi = part + (size_t)i * kRedBlocks;
+    double a = 0.0;
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nblk; b += 256) a += pi[b];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sum = (red[0] + red[1]) + (red[2] + red[3]);
+        if (mode == 1) {
+            out[i] = sqrt(sum);
+        } else {
+            if (out2) out2[i] = sum;
+            out[i] = add ? sum + add[i] : sum;
         }
-        if (threadIdx.x == 0) {
-            double s = red[0];
-            if (mode == 1) {
-                out[i] = sqrt(s);
-            } else {
-                if (out2) out2[i] = s;
-                out[i] = add ? s + add[i] : s;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -230,7 +261,7 @@ __global__ void k_make_rhs(const double *__restrict__ f, const double *__restric
 
 static int red_blocks(int64_t N)
 {
-    int64_t b = (N + 2047) / 2048;
+    int64_t b = (N + 1023) / 1024;
     if (b < 1) b = 1;
     if (b > kRedBlocks) b = kRedBlocks;
     return (int)b;
@@ -287,7 +318,7 @@ static int ensure_krylov(fmm_plan *pl, int m)
 // reduce partials of a norm kernel into dscal[slot] = sqrt(sum) and fetch it
 static int fetch_norm(fmm_plan *pl, int nblk, int slot, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, 1, pl->dscal + slot,
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, pl->dscal + slot,
                        nullptr, nullptr, 1);
     FMM_HIP(pl, hipMemcpyAsync(pl->hpin + slot, pl->dscal + slot, sizeof(double), hipMemcpyDeviceToHost, s));
     FMM_HIP(pl, hipStreamSynchronize(s));
@@ -345,16 +376,16 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
             const int nv = j + 1;
             StageTimer ta(pl, FMM_STAGE_ARNOLDI, s);
             // pass 1: w = A z_j, h1 = V^T w
-            hipLaunchKernelGGL(k_stencil_dots, gv, bv, 0, s, zj, pl->w, pl->V, N, nv, pl->partial, n, ih2);
-            hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, nv, pl->dscal + kH1,
+            launch_stencil_dots(nv, gv, s, zj, pl->w, pl->V, N, pl->partial, n, ih2);
+            hipLaunchKernelGGL(k_finish, dim3(nv), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kH1,
                                nullptr, nullptr, 0);
             // pass 2: w -= V h1, h2 = V^T w, hsum = h1 + h2
-            hipLaunchKernelGGL(k_update, gv, bv, 0, s, pl->V, N, nv, pl->w, pl->dscal + kH1, pl->partial, N, 0);
-            hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, nv, pl->dscal + kHsum,
+            launch_update(nv, 0, gv, s, pl->V, N, pl->w, pl->dscal + kH1, pl->partial, N);
+            hipLaunchKernelGGL(k_finish, dim3(nv), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kHsum,
                                pl->dscal + kH1, pl->dscal + kH2, 0);
             // pass 3: w -= V h2, ||w||
-            hipLaunchKernelGGL(k_update, gv, bv, 0, s, pl->V, N, nv, pl->w, pl->dscal + kH2, pl->partial, N, 1);
-            hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, 1, pl->dscal + kNrm,
+            launch_update(nv, 1, gv, s, pl->V, N, pl->w, pl->dscal + kH2, pl->partial, N);
+            hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kNrm,
                                nullptr, nullptr, 1);
             hipLaunchKernelGGL(k_scale, gv, bv, 0, s, pl->w, pl->V + (size_t)(j + 1) * N, pl->dscal + kNrm, 0.0, N);
             ta.stop();
