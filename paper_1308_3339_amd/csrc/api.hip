@@ -275,8 +275,22 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
         pl->x0 = pl->y0 = 0.5 * pl->h;
         pl->side = (double)n * pl->h;
     } else if (prob->kind == FMM_POINTS) {
-        delete pl;
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "POINTS plans are not built yet");
+        const int64_t N = prob->n;
+        if (N < 1 || !prob->x || !prob->y || !(prob->side > 0.0) || !std::isfinite(prob->side) ||
+            !std::isfinite(prob->x0) || !std::isfinite(prob->y0)) {
+            delete pl;
+            return fail(nullptr, FMM_ERR_ARG, "POINTS needs n >= 1, x, y and a root square with side > 0");
+        }
+        int L = 0;
+        while (((int64_t)64 << (2 * L)) < N && L < 12) ++L;   // L = ceil(log4(N / 64))
+        pl->L = L;
+        pl->nl = 1 << L;
+        pl->h = 1.0;                 // grid tables are unused by point clouds
+        pl->self_eps = 1.0;
+        pl->bem = 0;
+        pl->x0 = prob->x0;
+        pl->y0 = prob->y0;
+        pl->side = prob->side;
     } else {
         delete pl;
         return fail(nullptr, FMM_ERR_ARG, "unknown problem kind");
@@ -286,6 +300,14 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
         release(pl);
         delete pl;
         return st;
+    }
+    if (pl->kind == FMM_POINTS) {
+        if ((st = points_setup(pl, prob->x, prob->y, s)) != FMM_OK) {
+            g_setup_error = pl->err;
+            release(pl);
+            delete pl;
+            return st;
+        }
     }
     if (pl->kind == FMM_GRID && pl->bem) {
         if ((st = bem_setup(pl, s)) != FMM_OK) {
@@ -353,7 +375,7 @@ int fmm_apply(fmm_plan *pl, const double *q, double *u, int nrhs, void *stream)
     const size_t N = (pl->kind == FMM_GRID) ? (size_t)pl->n * pl->n : (size_t)pl->n;
     for (int r = 0; r < nrhs; ++r) {
         int st = (pl->kind == FMM_GRID) ? grid_volume_fmm(pl, q + r * N, 1.0, u + r * N, nullptr, s)
-                                        : FMM_ERR_UNSUPPORTED;
+                                        : points_fmm(pl, q + r * N, u + r * N, s);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;

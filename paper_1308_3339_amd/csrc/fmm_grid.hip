@@ -823,6 +823,32 @@ int grid_ring_source_fmm(fmm_plan *pl, double *u, hipStream_t s)
     FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, s);
 }
 
+// level-generic stages reused by point-cloud plans
+template <int P>
+static int points_up_p(fmm_plan *pl, hipStream_t s)
+{
+    StageTimer t(pl, FMM_STAGE_M2M, s);
+    run_m2m_from<P>(pl, pl->ws.M, pl->L, 0, s);
+    return FMM_OK;
+}
+
+template <int P>
+static int points_down_p(fmm_plan *pl, hipStream_t s)
+{
+    return run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s,
+                          true);
+}
+
+int points_upward_rest(fmm_plan *pl, hipStream_t s)
+{
+    FMM_DISPATCH_P(pl->p, points_up_p, pl, s);
+}
+
+int points_m2l_down(fmm_plan *pl, hipStream_t s)
+{
+    FMM_DISPATCH_P(pl->p, points_down_p, pl, s);
+}
+
 // enable > 64 KB of dynamic LDS for the M2L kernels (gfx950 has 160 KB per CU)
 template <int P>
 static int m2l_attr_p(fmm_plan *pl)

@@ -71,3 +71,10 @@ def test_null_arguments():
     assert lib.fmm_stencil_apply(None, None, None, 1, None) == fp.FMM_ERR_ARG
     assert lib.precond_gmres_solve(None, None, None, None, None, None, None) == fp.FMM_ERR_ARG
     assert lib.fmm_destroy(None) == fp.FMM_OK
+
+
+@pytest.mark.parametrize("n", [0, 100])
+def test_points_setup_rejects_missing_coordinates(n):
+    code, ptr, msg = _setup_raw(kind=1, n=n)
+    assert code == fp.FMM_ERR_ARG and not ptr
+    assert "POINTS" in msg

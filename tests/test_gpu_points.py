@@ -1,0 +1,140 @@
+"""GPU parity of point-cloud plans (u_i = sum_{j != i} q_j G(x_i - x_j)) against
+the CPU FP64 oracle through the C ABI.
+
+Tolerances: GPU FMM vs oracle FMM <= 1e-12 relative (max-norm), FMM vs the
+direct sum <= 1e-6 relative L2 at p = 12 (Sec. 5.3: accuracy set by p).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_1308_3339_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _fp():
+    import paper_1308_3339_amd as fp
+    return fp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def levels(N):
+    L = 0
+    while (64 << (2 * L)) < N:
+        L += 1
+    return L
+
+
+def run_points(x, y, q, p, x0=0.0, y0=0.0, side=1.0, nrhs=1):
+    fp = _fp()
+    import torch
+    N = len(x)
+    with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=dev(x), y=dev(y), x0=x0, y0=y0,
+                      side=side) as plan:
+        u = torch.empty(N * nrhs, dtype=torch.float64, device="cuda")
+        plan.apply(dev(q), u, nrhs=nrhs)
+        return host(u)
+
+
+@pytest.mark.parametrize("N,p", [(1, 6), (50, 6), (300, 8), (8192, 12), (20000, 10)])
+def test_points_match_oracle(N, p):
+    say("case points N=%d p=%d" % (N, p))
+    x, y, q = inputs.random_points(N, seed_xy=10 + N, seed_q=20 + N)
+    ug = run_points(x, y, q, p)
+    uo = o.fmm(levels(N), 0.0, 0.0, 1.0, p, x, y, q, x, y, 0.0)
+    scale = max(np.abs(uo).max(), 1e-300)
+    err = np.abs(ug - uo).max() / scale
+    say("  max rel err vs oracle FMM %.3e" % err)
+    assert err <= 1e-12
+    if N <= 20000:
+        ud = o.direct(x, y, q, x, y, 0.0)
+        if N > 1:
+            e2 = np.linalg.norm(ug - ud) / np.linalg.norm(ud)
+            say("  rel L2 vs direct %.3e" % e2)
+            # truncation error of the p-term series (Sec. 5.3); exact without far field
+            tol = {6: 3e-4, 8: 3e-5, 10: 5e-6, 12: 1e-6}[p]
+            assert e2 <= (1e-13 if levels(N) < 2 else tol)
+
+
+def test_points_clustered_and_on_the_boundary():
+    """A cluster of 2500 points inside one leaf (more sources than one LDS
+    chunk), points exactly on the root square's edges and corners (clamped
+    into the boundary leaves), and a second root square."""
+    say("case points clustered")
+    rng = np.random.default_rng(5)
+    N = 6000
+    x = rng.uniform(0.0, 1.0, N)
+    y = rng.uniform(0.0, 1.0, N)
+    x[:2500] = 0.3 + rng.uniform(0.0, 1e-3, 2500)
+    y[:2500] = 0.6 + rng.uniform(0.0, 1e-3, 2500)
+    x[2500:2510] = 1.0
+    y[2510:2520] = 0.0
+    x[2520], y[2520] = 1.0, 1.0
+    q = rng.uniform(-1, 1, N)
+    ug = run_points(x, y, q, 10)
+    uo = o.fmm(levels(N), 0.0, 0.0, 1.0, 10, x, y, q, x, y, 0.0)
+    err = np.abs(ug - uo).max() / np.abs(uo).max()
+    say("  max rel err %.3e" % err)
+    assert err <= 1e-12
+    # shifted, scaled root square
+    xs, ys = 2.0 + 3.0 * x, -1.0 + 3.0 * y
+    ug2 = run_points(xs, ys, q, 10, x0=2.0, y0=-1.0, side=3.0)
+    uo2 = o.fmm(levels(N), 2.0, -1.0, 3.0, 10, xs, ys, q, xs, ys, 0.0)
+    assert np.abs(ug2 - uo2).max() <= 1e-12 * np.abs(uo2).max()
+
+
+def test_points_multi_rhs_and_determinism():
+    say("case points nrhs=2")
+    N = 5000
+    x, y, _ = inputs.random_points(N, seed_xy=3, seed_q=4)
+    Q = np.stack([inputs.random_charges(N, s) for s in (1, 2)])
+    U = run_points(x, y, Q.reshape(-1), 8, nrhs=2).reshape(2, -1)
+    U2 = run_points(x, y, Q.reshape(-1), 8, nrhs=2).reshape(2, -1)
+    assert np.array_equal(U, U2)
+    for k in range(2):
+        uo = o.fmm(levels(N), 0.0, 0.0, 1.0, 8, x, y, Q[k], x, y, 0.0)
+        assert np.abs(U[k] - uo).max() <= 1e-12 * np.abs(uo).max()
+
+
+def test_points_one_million_against_direct_subset():
+    """The bare-FMM workload: 1M U(0,1)^2 points, U(-1,1) charges, p = 12,
+    checked against the direct sum on the seeded 4096-target subset."""
+    say("case points N=1M p=12")
+    N = 1 << 20
+    x, y, q = inputs.random_points(N)
+    ug = run_points(x, y, q, 12)
+    idx = inputs.target_subset(N, 4096)
+    ud = o.direct(x, y, q, x[idx], y[idx], 0.0)
+    err = np.linalg.norm(ug[idx] - ud) / np.linalg.norm(ud)
+    say("  rel L2 vs direct on 4096 targets %.3e" % err)
+    assert err <= 1e-6
+
+
+def test_points_bad_arguments():
+    fp = _fp()
+    import torch
+    x = torch.zeros(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(fp.FmmError):
+        fp.fmm_setup(kind=fp.FMM_POINTS, n=4, p=6, x=x, y=x, side=0.0)
+    bad = dev(np.array([0.1, np.nan, 0.3, 0.4]))
+    with pytest.raises(fp.FmmError):
+        fp.fmm_setup(kind=fp.FMM_POINTS, n=4, p=6, x=bad, y=x, side=1.0)
