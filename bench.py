@@ -44,6 +44,16 @@ def leaf_kernel_flops(n, p):
     return 2.0 * pairs + 4.0 * p * n * n
 
 
+def leaf_kernel_hash():
+    """sha256 of the source text of k_leaf_grid (from its template line to the
+    closing brace), so that only a change of that kernel invalidates the
+    committed counter summary."""
+    src = open(os.path.join(ROOT, "paper_1308_3339_amd", "csrc", "fmm_grid.hip")).read()
+    i = src.index("__global__ __launch_bounds__(256) void k_leaf_grid(")
+    j = src.index("\n}\n", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
 def traffic_from_profile(src_hash):
     """HBM bytes per leaf-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
@@ -87,9 +97,9 @@ def main():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true",
-                    help="counter-collection driver: one 512 MiB device copy (the calibration "
-                         "kernel of known size), then 3 FMM applies and 3 preconditioner "
-                         "applies; prints timings only")
+                    help="counter-collection driver: one 512 MiB elementwise y = x*1 (the "
+                         "calibration kernel of known size: 512 MiB read, 512 MiB written), "
+                         "then 3 FMM applies and 3 preconditioner applies")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -126,7 +136,7 @@ def main():
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
         y = torch.empty_like(x)
         torch.cuda.synchronize()
-        y.copy_(x)
+        torch.mul(x, 1.0, out=y)     # calibration: reads 512 MiB, writes 512 MiB
         torch.cuda.synchronize()
         q = torch.from_numpy(inputs.random_charges(N, seed=9)).to(dev)
         out = torch.empty_like(q)
@@ -193,8 +203,7 @@ def main():
     pc_ms = e0.elapsed_time(e1) / reps
     log("fmm apply %.3f ms, precond apply %.3f ms" % (fmm_ms, pc_ms))
 
-    src = open(os.path.join(ROOT, "paper_1308_3339_amd", "csrc", "fmm_grid.hip"), "rb").read()
-    src_hash = hashlib.sha256(src).hexdigest()
+    src_hash = leaf_kernel_hash()
     leaf_avg_ms = leaf_ms / max(leaf_launches, 1)
     flops = leaf_kernel_flops(n, p)
     achieved = flops / (leaf_avg_ms * 1e-3) / 1e12

@@ -141,9 +141,20 @@ __global__ __launch_bounds__(256) void k_p2m_up(const double *__restrict__ q, do
     const int tid = threadIdx.x;
     for (int e = tid; e < P * 64; e += 256) sw[e] = W[e];
     for (int e = tid; e < 4 * P * P; e += 256) sA[e] = A[e];
-    for (int e = tid; e < pw * pw; e += 256) {
-        const int yy = e / pw, xx = e - yy * pw;
-        sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = q[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx];
+    for (int e0 = tid; e0 < pw * pw; e0 += 256 * 8) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + 256 * i;
+            const int yy = e / pw, xx = e - yy * pw;
+            v[i] = (e < pw * pw) ? q[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + 256 * i;
+            const int yy = e / pw, xx = e - yy * pw;
+            if (e < pw * pw) sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = v[i];
+        }
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -234,18 +245,30 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     const int RW = tw + 4, RH = RW >> 1, SUB = RH * RH, RR = RW * RW;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l];
-    for (int e = threadIdx.x; e < P * RR; e += 768) {
-        const int k = e / RR, r = e - k * RR;
-        const int sy = r / RW, sx = r - sy * RW;
-        const int gx = it.tx0 - 2 + sx, gy = it.ty0 - 2 + sy;
-        double2 v = make_double2(0.0, 0.0);
-        if (gx >= 0 && gx < nc && gy >= 0 && gy < nc) {
-            v = Ml[k * ncell + (int64_t)gy * nc + gx];
-            const double bk = b_k[k];
-            v.x *= bk;
-            v.y *= bk;
+    for (int e0 = threadIdx.x; e0 < P * RR; e0 += 768 * 6) {
+        double2 v[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int e = e0 + 768 * i;
+            v[i] = make_double2(0.0, 0.0);
+            if (e < P * RR) {
+                const int k = e / RR, r = e - k * RR;
+                const int sy = r / RW, sx = r - sy * RW;
+                const int gx = it.tx0 - 2 + sx, gy = it.ty0 - 2 + sy;
+                if (gx >= 0 && gx < nc && gy >= 0 && gy < nc) v[i] = Ml[k * ncell + (int64_t)gy * nc + gx];
+            }
         }
-        sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1)] = v;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int e = e0 + 768 * i;
+            if (e < P * RR) {
+                const int k = e / RR, r = e - k * RR;
+                const int sy = r / RW, sx = r - sy * RW;
+                const double bk = b_k[k];
+                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1)] =
+                    make_double2(v[i].x * bk, v[i].y * bk);
+            }
+        }
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -402,12 +425,22 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
     const int n = a.n, nl = a.nl;
     const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
     const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
-    for (int e = tid; e < 6400; e += 256) {
-        const int yy = e / 80, xx = e - yy * 80;
-        const int gx = X0 + xx, gy = Y0 + yy;
-        double v = 0.0;
-        if (gx >= 0 && gx < n && gy >= 0 && gy < n) v = a.q[(size_t)gy * n + gx];
-        sq[((yy & 7) * 8 + (xx & 7)) * 100 + (yy >> 3) * 10 + (xx >> 3)] = v;
+    {
+        // all 25 loads of a thread are issued before any LDS store
+        double v[25];
+#pragma unroll
+        for (int i = 0; i < 25; ++i) {
+            const int e = tid + 256 * i;
+            const int yy = e / 80, xx = e - yy * 80;
+            const int gx = X0 + xx, gy = Y0 + yy;
+            v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 25; ++i) {
+            const int e = tid + 256 * i;
+            const int yy = e / 80, xx = e - yy * 80;
+            sq[((yy & 7) * 8 + (xx & 7)) * 100 + (yy >> 3) * 10 + (xx >> 3)] = v[i];
+        }
     }
     __syncthreads();
     const int lx = lane & 7, ly = lane >> 3;
@@ -547,15 +580,24 @@ __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__rest
 // leaves they attach to.  Interior leaves are never written (stay zero).
 // ---------------------------------------------------------------------------
 // ring nodes attached to leaf (lx, ly) with nl >= 2: one or two runs of 8
-// consecutive node indices; returns the number of runs.
-__device__ __forceinline__ int attached_runs(int lx, int ly, int n, int nl, int start[2])
+// consecutive nodes of one side, given as (side, first k); returns the count.
+__device__ __forceinline__ int attached_runs(int lx, int ly, int n, int nl, int side[2], int k0[2])
 {
     int r = 0;
-    if (ly == 0) start[r++] = 8 * lx;                                   // bottom
-    if (lx == nl - 1 && r < 2) start[r++] = n + 8 * ly;                 // right
-    if (ly == nl - 1 && r < 2) start[r++] = 2 * n + (n - 8 * lx - 8);   // top
-    if (lx == 0 && r < 2) start[r++] = 3 * n + (n - 8 * ly - 8);        // left
+    if (ly == 0) { side[r] = 0; k0[r] = 8 * lx; ++r; }                          // bottom
+    if (lx == nl - 1 && r < 2) { side[r] = 1; k0[r] = 8 * ly; ++r; }            // right
+    if (ly == nl - 1 && r < 2) { side[r] = 2; k0[r] = n - 8 * lx - 8; ++r; }    // top
+    if (lx == 0 && r < 2) { side[r] = 3; k0[r] = n - 8 * ly - 8; ++r; }         // left
     return r;
+}
+
+// lattice coordinates of node k of side s
+__device__ __forceinline__ void side_node(int s, int k, int n, int &Ix, int &Iy)
+{
+    if (s == 0) { Ix = k + 1; Iy = 0; }
+    else if (s == 1) { Ix = n + 1; Iy = k + 1; }
+    else if (s == 2) { Ix = n - k; Iy = n + 1; }
+    else { Ix = 0; Iy = n - k; }
 }
 
 // one thread per (boundary leaf, coefficient k); 4 (nl - 1) boundary leaves, nl >= 2
@@ -572,15 +614,14 @@ __global__ __launch_bounds__(256) void k_p2m_ring(const double *__restrict__ rq,
     else if (side == 1) { lx = nl - 1; ly = kk; }
     else if (side == 2) { lx = nl - 1 - kk; ly = nl - 1; }
     else { lx = 0; ly = nl - 1 - kk; }
-    int start[2];
-    const int runs = attached_runs(lx, ly, n, nl, start);
+    int sd[2], k0[2];
+    const int runs = attached_runs(lx, ly, n, nl, sd, k0);
     double2 m = make_double2(0.0, 0.0);
     for (int r = 0; r < runs; ++r)
         for (int j = 0; j < 8; ++j) {
-            const int t = start[r] + j;
             int Ix, Iy;
-            ring_node(t, n, Ix, Iy);
-            const double c = rq[t];
+            side_node(sd[r], k0[r] + j, n, Ix, Iy);
+            const double c = rq[sd[r] * n + k0[r] + j];
             const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
             double2 pw = make_double2(1.0, 0.0);
             for (int e = 0; e < k; ++e) pw = cmul(pw, tau);
@@ -610,6 +651,7 @@ __global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a)
         sL[t] = Ll[k * ncell + (int64_t)(ly0 + c / tw) * nl + lx0 + c % tw];
     }
     __syncthreads();
+#pragma unroll 4
     for (int e = threadIdx.x; e < pw * pw; e += 256) {
         const int yy = e / pw, xx = e - yy * pw;
         const int lc = (yy >> 3) * tw + (xx >> 3);
@@ -665,22 +707,21 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
             const int qx = lx + c, qy = ly + b;
             if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
             if (!(qx == 0 || qy == 0 || qx == nl - 1 || qy == nl - 1)) continue;
-            int start[4], runs, len;
+            int sd[4], k0[4], runs, len;
             if (nl == 1) {
-                start[0] = 0; start[1] = n; start[2] = 2 * n; start[3] = 3 * n;
+                for (int r = 0; r < 4; ++r) { sd[r] = r; k0[r] = 0; }
                 runs = 4;
                 len = n;
             } else {
-                runs = attached_runs(qx, qy, n, nl, start);
+                runs = attached_runs(qx, qy, n, nl, sd, k0);
                 len = 8;
             }
             for (int r = 0; r < runs; ++r)
                 for (int j = 0; j < len; ++j) {
-                    const int t = start[r] + j;
                     int Ix, Iy;
-                    ring_node(t, n, Ix, Iy);
+                    side_node(sd[r], k0[r] + j, n, Ix, Iy);
                     const int dx = abs(gx + 1 - Ix), dy = abs(gy + 1 - Iy);
-                    near = fma(rq[t], rtab[dy * 17 + dx], near);
+                    near = fma(rq[sd[r] * n + k0[r] + j], rtab[dy * 17 + dx], near);
                 }
         }
     u[(size_t)gy * n + gx] += -near * kInv2Pi;
