@@ -59,7 +59,12 @@ enum {
 
 typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
 
-typedef enum { FMM_FP64 = 0 } fmm_precision;
+/* Arithmetic of the FMM.  FMM_FP64: everything in FP64.  FMM_FP32 (GRID
+ * plans): the near field (P2P) and the multipole-to-local translations run
+ * in FP32 (the preconditioner's tunable accuracy, Sec. 6.2); tree passes,
+ * boundary correction, stencil and Krylov stay FP64.  The flexible outer
+ * iteration reaches the same FP64 residual either way. */
+typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
 
 /* The problem the plan is built for.
  *   GRID:   n = interior points per side, n = 8 * 2^L (L >= 0); x, y unused.
@@ -81,7 +86,7 @@ typedef struct {
 /* FMM parameters.
  *   p        number of expansion coefficients, M_0..M_{p-1} (Sec. 5.3), 2..20.
  *   leaf     points per leaf side squared; must be 64 (8 x 8 grid blocks).
- *   prec     fmm_precision; FMM_FP64 only.
+ *   prec     fmm_precision (FMM_FP32 for GRID plans only).
  *   bem      GRID: 1 = boundary correction on (Sec. 4), 0 = free-space
  *            volume potential only.  Ignored for POINTS.
  *   self_eps GRID: the singular self term is G_self = -(1/2pi) log(self_eps h)

@@ -152,8 +152,12 @@ static int build_tables(fmm_plan *pl)
     for (int dy = 0; dy <= 16; ++dy)
         for (int dx = 0; dx <= 16; ++dx)
             if (dx || dy) rt[dy * 17 + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
+    std::vector<float> kt32(kt.begin(), kt.end());
+    std::vector<float2> hank32(hank.size());
+    for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
     int st;
-    if ((st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
+    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
+        (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
         (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
         (st = upload(pl, &pl->tab.m2l_b, bk)) || (st = upload(pl, &pl->tab.p2m, p2m)) ||
@@ -176,7 +180,8 @@ static int build_levels_and_work(fmm_plan *pl)
         pl->lv.logw[l] = std::log(pl->side / (double)(1 << l));
     }
     pl->exp_elems = off;
-    std::vector<M2LItem> all, edge;
+    std::vector<M2LItem> all;
+    std::vector<int4> ring;
     for (int l = L; l >= 2; --l) {
         const int nc = 1 << l, tw = std::min(16, nc), nt = nc / tw;
         for (int ty = 0; ty < nt; ++ty)
@@ -187,22 +192,38 @@ static int build_levels_and_work(fmm_plan *pl)
                 it.tx0 = tx * tw;
                 it.ty0 = ty * tw;
                 all.push_back(it);
-                if (tx == 0 || ty == 0 || tx == nt - 1 || ty == nt - 1) edge.push_back(it);
             }
+        // strips of cells whose lists can hold a boundary cell of level l (those
+        // within 3 cells of the boundary): (level, side | depth << 2, start, end),
+        // 64 lanes per item stepping by 2 from start
+        if (nc <= 8) {
+            for (int d = 0; d < nc; ++d)
+                for (int par = 0; par < 2; ++par) ring.push_back(int4{l, 0 | (d << 2), par, nc});
+        } else {
+            for (int side = 0; side < 4; ++side)
+                for (int d = 0; d < 4; ++d)
+                    for (int par = 0; par < 2; ++par) {
+                        const int lo = (side & 1) ? 4 : 0, hi = (side & 1) ? nc - 4 : nc;
+                        for (int a0 = lo + par; a0 < hi; a0 += 128)
+                            ring.push_back(int4{l, side | (d << 2), a0, hi});
+                    }
+        }
     }
     pl->n_m2l_items = (int)all.size();
-    pl->n_m2l_edge_items = (int)edge.size();
     int st;
     if (!all.empty() && (st = upload(pl, &pl->m2l_items, all))) return st;
-    if (!edge.empty() && (st = upload(pl, &pl->m2l_edge_items, edge))) return st;
+    if (pl->kind == FMM_GRID && pl->bem && !ring.empty()) {
+        pl->n_ring_cells = (int)ring.size();
+        if ((st = upload(pl, &pl->ring_cells, ring))) return st;
+    }
     if (off > 0) {
         const size_t bytes = (size_t)off * sizeof(double2);
         FMM_HIP(pl, hipMalloc(&pl->ws.M, bytes));
         FMM_HIP(pl, hipMalloc(&pl->ws.Lt, bytes));
         FMM_HIP(pl, hipMalloc(&pl->ws.Lm, bytes));
         if (pl->kind == FMM_GRID && pl->bem) {
-            // the boundary-source pass writes only boundary cells of M2 and
-            // only edge tiles of Lm2: everything else must stay zero
+            // the boundary-source pass writes only border tiles of M2 and only
+            // the boundary band of Lm2: everything else must stay zero
             FMM_HIP(pl, hipMalloc(&pl->ws.M2, bytes));
             FMM_HIP(pl, hipMemset(pl->ws.M2, 0, bytes));
             FMM_HIP(pl, hipMalloc(&pl->ws.Lt2, bytes));
@@ -215,10 +236,10 @@ static int build_levels_and_work(fmm_plan *pl)
 
 static void release(fmm_plan *pl)
 {
-    void *ptrs[] = {pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+    void *ptrs[] = {pl->tab.ktab32, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
-                    pl->m2l_edge_items, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
+                    pl->ring_cells, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
                     pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
                     pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal};
     for (void *p : ptrs)
@@ -248,7 +269,10 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (prm->p < kPMin || prm->p > kPMax)
         return fail(nullptr, FMM_ERR_ARG, "p must be in [2, 20]");
     if (prm->leaf != 64) return fail(nullptr, FMM_ERR_ARG, "leaf must be 64");
-    if (prm->prec != FMM_FP64) return fail(nullptr, FMM_ERR_UNSUPPORTED, "only FMM_FP64 is built");
+    if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "prec must be FMM_FP64 or FMM_FP32");
+    if (prm->prec == FMM_FP32 && prob->kind != FMM_GRID)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "FMM_FP32 is built for GRID plans");
     if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
         return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;
@@ -257,6 +281,7 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     pl->kind = prob->kind;
     pl->n = prob->n;
     pl->p = prm->p;
+    pl->prec = prm->prec;
     pl->bem = prm->bem ? 1 : 0;
     int st = FMM_OK;
     if (prob->kind == FMM_GRID) {

@@ -38,6 +38,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b)
+{
+    acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
+    acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
+}
+
+// real type -> complex pair type
+template <typename R> struct Cplx;
+template <> struct Cplx<double> { using T = double2; };
+template <> struct Cplx<float> { using T = float2; };
+
 __device__ __forceinline__ double wave_sum(double a)
 {
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
@@ -227,18 +238,22 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 // and third w>>2 of the 27-entry list.  Sources (20x20 cells around the
 // tile) are staged once in LDS, split by parity so that the per-offset LDS
 // reads of a wave are consecutive; the three thirds are summed in LDS in a
-// fixed order.
+// fixed order.  R is the arithmetic type of the translation (double, or
+// float for the FP32 variant; the level-scaled expansions and generators
+// stay far inside FP32 range for p <= 20), inputs and outputs are FP64.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, typename R>
 __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                                              const double2 *__restrict__ M,
                                              double2 *__restrict__ Lm, LevelInfo lv,
-                                             const double2 *__restrict__ hank,
+                                             const typename Cplx<R>::T *__restrict__ hank,
                                              const int4 *__restrict__ offs,
                                              const double *__restrict__ a_n,
                                              const double *__restrict__ b_k)
 {
-    extern __shared__ double2 sm[];  // [P][RW*RW] parity split; later [P][256] reduction
+    using C = typename Cplx<R>::T;
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    C *sm = reinterpret_cast<C *>(sm_raw);   // [P][RW*RW] parity split; later [P][256] reduction
     const M2LItem it = items[blockIdx.x];
     const int l = it.level, nc = 1 << l;
     const int tw = nc < 16 ? nc : 16;
@@ -265,8 +280,10 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                 const int k = e / RR, r = e - k * RR;
                 const int sy = r / RW, sx = r - sy * RW;
                 const double bk = b_k[k];
-                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1)] =
-                    make_double2(v[i].x * bk, v[i].y * bk);
+                C c;
+                c.x = (R)(v[i].x * bk);
+                c.y = (R)(v[i].y * bk);
+                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1)] = c;
             }
         }
     }
@@ -277,24 +294,24 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     const int px = cls & 1, py = cls >> 1;
     const int ltx = 2 * (lane & 7) + px, lty = 2 * (lane >> 3) + py;
     const bool active = ltx < tw && lty < tw;
-    double2 acc[P];
+    C acc[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
-    const double logw = lv.logw[l];
+    for (int k = 0; k < P; ++k) acc[k].x = acc[k].y = (R)0;
+    const R logw = (R)lv.logw[l];
     const int4 *ol = offs + cls * 27 + grp * 9;
     if (active) {
         for (int o = 0; o < 9; ++o) {
             const int4 od = ol[o];
-            const double2 *H = hank + od.z * (2 * P - 1);
+            const C *H = hank + od.z * (2 * P - 1);
             const int sx = ltx + od.x + 2, sy = lty + od.y + 2;
             const int sidx = ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1);
-            double2 m[P];
+            C m[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) m[k] = sm[k * RR + sidx];
             // anti-diagonal order: each generator H_s is used by all (n, k), n+k = s
 #pragma unroll
             for (int s = 0; s < 2 * P - 1; ++s) {
-                double2 h = H[s];
+                C h = H[s];
                 if (s == 0) h.x -= logw;
 #pragma unroll
                 for (int nn = (s < P ? 0 : s - P + 1); nn <= (s < P ? s : P - 1); ++nn)
@@ -314,7 +331,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
         if (grp == 0 && active) {
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-                const double2 v = sm[k * 256 + slot];
+                const C v = sm[k * 256 + slot];
                 acc[k].x += v.x;
                 acc[k].y += v.y;
             }
@@ -326,7 +343,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const double an = a_n[k];
-        out[k * ncell + (int64_t)ty * nc + tx] = make_double2(an * acc[k].x, an * acc[k].y);
+        out[k * ncell + (int64_t)ty * nc + tx] = make_double2(an * (double)acc[k].x, an * (double)acc[k].y);
     }
 }
 
@@ -339,6 +356,57 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 // alone (lists start at level 2), and is written too.  All M2L sums the
 // block needs are fetched into LDS up front (one memory round trip).
 // ---------------------------------------------------------------------------
+// Shared body of the downward chain.  The block owns cell (rx, ry) of level
+// r, whose expansion is in buf0[0..P).  Levels r+1..r+m are built in LDS
+// (and stored to Lt when Lt != nullptr); returns the buffer that holds the
+// deepest level, laid out [k][tw*tw] with tw = 2^m.
+template <int P>
+__device__ __forceinline__ const double2 *down_levels(const double2 *__restrict__ Lm,
+                                                      double2 *__restrict__ Lt,
+                                                      const double2 *__restrict__ B,
+                                                      const LevelInfo &lv, int r, int m, int rx,
+                                                      int ry, double2 *sB, double2 *sm2l,
+                                                      double2 *buf0, double2 *buf1)
+{
+    for (int e = threadIdx.x; e < 4 * P * P; e += blockDim.x) sB[e] = B[e];
+    for (int st = 1; st <= m; ++st) {
+        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
+        const int base = ((1 << (2 * st)) - 4) / 3;   // 0, 4, 20
+        const int64_t ncell = (int64_t)nc * nc;
+        for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
+            const int nn = t / cnt, c = t - nn * cnt;
+            sm2l[nn * 84 + base + c] =
+                Lm[lv.off[l] + nn * ncell + (int64_t)(ry * tw + c / tw) * nc + rx * tw + c % tw];
+        }
+    }
+    __syncthreads();
+    const double2 *prev = buf0;
+    int pw = 1;
+    for (int st = 1; st <= m; ++st) {
+        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
+        const int base = ((1 << (2 * st)) - 4) / 3;
+        const int64_t ncell = (int64_t)nc * nc;
+        double2 *next = (st & 1) ? buf1 : buf0;
+        const int pcnt = pw * pw;
+        for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
+            const int nn = t / cnt, c = t - nn * cnt;
+            const int cx = c % tw, cy = c / tw;
+            const int pc = (cy >> 1) * pw + (cx >> 1), qd = (cy & 1) * 2 + (cx & 1);
+            double2 acc = sm2l[nn * 84 + base + c];
+            const double2 *Br = sB + (qd * P + nn) * P;
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+                if (k >= nn) cmac(acc, Br[k], prev[k * pcnt + pc]);
+            next[t] = acc;
+            if (Lt) Lt[lv.off[l] + nn * ncell + (int64_t)(ry * tw + cy) * nc + rx * tw + cx] = acc;
+        }
+        __syncthreads();
+        prev = next;
+        pw = tw;
+    }
+    return prev;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
                                               double2 *__restrict__ Lt,
@@ -350,49 +418,13 @@ __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
     __shared__ double2 buf0[P * 64], buf1[P * 64];
     const int nr = 1 << r;
     const int rx = blockIdx.x % nr, ry = blockIdx.x / nr;
-    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sB[e] = B[e];
-    // descendants' M2L sums: level r+st occupies [base_st, base_st + 4^st)
-    for (int st = 1; st <= m; ++st) {
-        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
-        const int base = ((1 << (2 * st)) - 4) / 3;   // 0, 4, 20
-        const int64_t ncell = (int64_t)nc * nc;
-        for (int t = threadIdx.x; t < P * cnt; t += 256) {
-            const int nn = t / cnt, c = t - nn * cnt;
-            sm2l[nn * 84 + base + c] =
-                Lm[lv.off[l] + nn * ncell + (int64_t)(ry * tw + c / tw) * nc + rx * tw + c % tw];
-        }
-    }
     if (threadIdx.x < P) {
         const int64_t gi = lv.off[r] + (int64_t)threadIdx.x * nr * nr + (int64_t)ry * nr + rx;
         const double2 v = top ? Lm[gi] : Lt[gi];
         buf0[threadIdx.x] = v;
         if (top) Lt[gi] = v;
     }
-    __syncthreads();
-    const double2 *prev = buf0;
-    int pw = 1;
-    for (int st = 1; st <= m; ++st) {
-        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
-        const int base = ((1 << (2 * st)) - 4) / 3;
-        const int64_t ncell = (int64_t)nc * nc;
-        double2 *next = (st & 1) ? buf1 : buf0;
-        const int pcnt = pw * pw;
-        for (int t = threadIdx.x; t < P * cnt; t += 256) {
-            const int nn = t / cnt, c = t - nn * cnt;
-            const int cx = c % tw, cy = c / tw;
-            const int pc = (cy >> 1) * pw + (cx >> 1), qd = (cy & 1) * 2 + (cx & 1);
-            double2 acc = sm2l[nn * 84 + base + c];
-            const double2 *Br = sB + (qd * P + nn) * P;
-#pragma unroll
-            for (int k = 0; k < P; ++k)
-                if (k >= nn) cmac(acc, Br[k], prev[k * pcnt + pc]);
-            next[t] = acc;
-            Lt[lv.off[l] + nn * ncell + (int64_t)(ry * tw + cy) * nc + rx * tw + cx] = acc;
-        }
-        __syncthreads();
-        prev = next;
-        pw = tw;
-    }
+    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1);
 }
 
 // ---------------------------------------------------------------------------
@@ -505,6 +537,103 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
     }
 }
 
+// FP32 variant of the leaf stage (precision variant of the preconditioner):
+// the q tile and the kernel table are FP32, every source row of the 3x3
+// leaves (24 sources) is summed in FP32 and folded into an FP64 accumulator,
+// so the FP32 rounding error stays at the level of one 24-term sum.  L2P and
+// the output are FP64.
+template <int P>
+__global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__restrict__ kt32)
+{
+    __shared__ float sq[64 * 100];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, nl = a.nl;
+    const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
+    const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
+    {
+        float v[25];
+#pragma unroll
+        for (int i = 0; i < 25; ++i) {
+            const int e = tid + 256 * i;
+            const int yy = e / 80, xx = e - yy * 80;
+            const int gx = X0 + xx, gy = Y0 + yy;
+            v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)a.q[(size_t)gy * n + gx] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 25; ++i) {
+            const int e = tid + 256 * i;
+            const int yy = e / 80, xx = e - yy * 80;
+            sq[((yy & 7) * 8 + (xx & 7)) * 100 + (yy >> 3) * 10 + (xx >> 3)] = v[i];
+        }
+    }
+    __syncthreads();
+    const int lx = lane & 7, ly = lane >> 3;
+    const int gLx = TX0 + lx, gLy = TY0 + ly;
+    const bool active = gLx < nl && gLy < nl;
+    const int ty0 = 2 * wave;
+    const int cleaf = (ly + 1) * 10 + (lx + 1);
+    double acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+    for (int oy = -1; oy <= 1; ++oy) {
+        for (int sy = 0; sy < 8; ++sy) {
+            const int dy0 = 8 * oy + sy - ty0;
+            const float *T0 = kt32 + (dy0 + 15) * 31 + 8;
+            const float *T1 = kt32 + (dy0 + 14) * 31 + 8;
+            float pacc[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) pacc[t] = 0.0f;
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                float w0[15], w1[15];
+#pragma unroll
+                for (int c = 0; c < 15; ++c) {
+                    w0[c] = T0[8 * ox + c];
+                    w1[c] = T1[8 * ox + c];
+                }
+                const int sl = cleaf + oy * 10 + ox;
+#pragma unroll
+                for (int sx = 0; sx < 8; ++sx) {
+                    const float v = sq[(sy * 8 + sx) * 100 + sl];
+#pragma unroll
+                    for (int tx = 0; tx < 8; ++tx) {
+                        pacc[tx] = fmaf(w0[sx - tx + 7], v, pacc[tx]);
+                        pacc[8 + tx] = fmaf(w1[sx - tx + 7], v, pacc[8 + tx]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc[t] += (double)pacc[t];
+        }
+    }
+    if (!active) return;
+    double far[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) far[t] = 0.0;
+    if (a.far) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        const double2 *Ll = a.Lt + a.lv.off[a.L];
+        double2 Lc[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const double2 *tp = a.l2p + ((ty0 + (t >> 3)) * 8 + (t & 7)) * P;
+            double sacc = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) sacc = fma(Lc[k].x, tp[k].x, fma(-Lc[k].y, tp[k].y, sacc));
+            far[t] = sacc;
+        }
+    }
+    const double qs = a.qscale;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int gy = gLy * 8 + ty0 + (t >> 3), gx = gLx * 8 + (t & 7);
+        a.u[(size_t)gy * n + gx] = -(fma(qs, acc[t], far[t])) * kInv2Pi;
+    }
+}
+
 // Lattice coordinates (in units of h) of ring node t (counter-clockwise).
 __device__ __forceinline__ void ring_node(int t, int n, int &Ix, int &Iy)
 {
@@ -600,57 +729,176 @@ __device__ __forceinline__ void side_node(int s, int k, int n, int &Ix, int &Iy)
     else { Ix = 0; Iy = n - k; }
 }
 
-// one thread per (boundary leaf, coefficient k); 4 (nl - 1) boundary leaves, nl >= 2
+// Pass 2 upward start: multipoles of the boundary leaves from the ring
+// charges they carry (M~_0 = sum c, M~_k = -sum c tau^k / k), for one border
+// tile of 8x8 leaves, then M2M three levels up.  Only boundary cells are
+// non-zero, and only border tiles are launched.
 template <int P>
-__global__ __launch_bounds__(256) void k_p2m_ring(const double *__restrict__ rq,
-                                                  double2 *__restrict__ M, int n, int nl)
+__global__ __launch_bounds__(256) void k_m2m_up_ring(const double *__restrict__ rq,
+                                                     double2 *__restrict__ M,
+                                                     const double2 *__restrict__ A, LevelInfo lv,
+                                                     int n, int L)
 {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= 4 * (nl - 1) * P) return;
-    const int k = idx % P, bl = idx / P;
-    const int side = bl / (nl - 1), kk = bl - side * (nl - 1);
-    int lx, ly;
-    if (side == 0) { lx = kk; ly = 0; }
-    else if (side == 1) { lx = nl - 1; ly = kk; }
-    else if (side == 2) { lx = nl - 1 - kk; ly = nl - 1; }
-    else { lx = 0; ly = nl - 1 - kk; }
-    int sd[2], k0[2];
-    const int runs = attached_runs(lx, ly, n, nl, sd, k0);
-    double2 m = make_double2(0.0, 0.0);
-    for (int r = 0; r < runs; ++r)
-        for (int j = 0; j < 8; ++j) {
-            int Ix, Iy;
-            side_node(sd[r], k0[r] + j, n, Ix, Iy);
-            const double c = rq[sd[r] * n + k0[r] + j];
-            const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
-            double2 pw = make_double2(1.0, 0.0);
-            for (int e = 0; e < k; ++e) pw = cmul(pw, tau);
-            m.x += c * pw.x;
-            m.y += c * pw.y;
+    __shared__ double2 sA[4 * P * P];
+    __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
+    const int nl = 1 << L, tw = nl < 8 ? nl : 8, nt = nl / tw;
+    int tx, ty;
+    tile_of_block(blockIdx.x, nt, 1, tx, ty);
+    const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
+    const int64_t ncell = (int64_t)nl * nl;
+    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sA[e] = A[e];
+    for (int c = threadIdx.x; c < cnt; c += 256) {
+        const int lx = x0 + c % tw, ly = y0 + c / tw;
+        double2 m[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) m[k] = make_double2(0.0, 0.0);
+        const bool bnd = lx == 0 || ly == 0 || lx == nl - 1 || ly == nl - 1;
+        if (bnd) {
+            int sd[2], k0[2];
+            const int runs = attached_runs(lx, ly, n, nl, sd, k0);
+            for (int r = 0; r < runs; ++r)
+                for (int j = 0; j < 8; ++j) {
+                    int Ix, Iy;
+                    side_node(sd[r], k0[r] + j, n, Ix, Iy);
+                    const double cq = rq[sd[r] * n + k0[r] + j];
+                    const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
+                    double2 pw = make_double2(1.0, 0.0);
+                    m[0].x += cq;
+#pragma unroll
+                    for (int k = 1; k < P; ++k) {
+                        pw = cmul(pw, tau);
+                        m[k].x += cq * pw.x;
+                        m[k].y += cq * pw.y;
+                    }
+                }
+#pragma unroll
+            for (int k = 1; k < P; ++k) {
+                const double f = -1.0 / (double)k;
+                m[k] = make_double2(f * m[k].x, f * m[k].y);
+            }
+#pragma unroll
+            for (int k = 0; k < P; ++k) M[lv.off[L] + k * ncell + (int64_t)ly * nl + lx] = m[k];
         }
-    // M~_0 = sum c, M~_k = -sum c tau^k / k
-    const double f = (k == 0) ? 1.0 : -1.0 / (double)k;
-    const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
-    M[k * ncell + cell] = make_double2(f * m.x, f * m.y);
+#pragma unroll
+        for (int k = 0; k < P; ++k) s0[k * cnt + c] = m[k];
+    }
+    __syncthreads();
+    m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, L, tw, x0, y0);
+}
+
+// Pass 2 M2L: the multipoles are non-zero only in the boundary cells of each
+// level, and those are in the interaction lists of cells at most three cells
+// from the boundary.  A wave takes one row of that band along one side
+// (item = level, side, depth d, first coordinate along the side; lanes step
+// by two, so all lanes share a parity class and hence one list).  For each
+// list entry the source's boundary test is uniform except at the ends of
+// the strip, and the Hankel generators are wave-uniform.  Bottom and top
+// strips span the full width; left and right strips skip the rows the
+// bottom and top strips own; levels with at most 8 cells per side are one
+// "bottom" strip per row.  A block takes one item; its four waves split the
+// list.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items, int nitems,
+                                                  const double2 *__restrict__ M,
+                                                  double2 *__restrict__ Lm, LevelInfo lv,
+                                                  const double2 *__restrict__ hank,
+                                                  const int4 *__restrict__ offs,
+                                                  const double *__restrict__ a_n,
+                                                  const double *__restrict__ b_k)
+{
+    // one item per block; wave w takes list entries w, w+4, ... and the four
+    // partial sums are added in LDS in a fixed order
+    __shared__ double2 red[3][P][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int4 it = items[blockIdx.x];   // (level, side | depth << 2, start, end)
+    const int l = it.x, side = it.y & 3, d = it.y >> 2, nc = 1 << l;
+    const int a = it.z + 2 * lane;
+    const bool valid = a < it.w;
+    int ix, iy;
+    if (side == 0) { ix = a; iy = d; }
+    else if (side == 1) { ix = nc - 1 - d; iy = a; }
+    else if (side == 2) { ix = a; iy = nc - 1 - d; }
+    else { ix = d; iy = a; }
+    const int64_t ncell = (int64_t)nc * nc;
+    const double2 *Ml = M + lv.off[l];
+    const int cls = __builtin_amdgcn_readfirstlane(((iy & 1) * 2 + (ix & 1)));
+    const int4 *ol = offs + cls * 27;
+    const double logw = lv.logw[l];
+    double2 acc[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
+    for (int o = w; o < 27; o += 4) {
+        const int4 od = ol[o];
+        const int sx = ix + od.x, sy = iy + od.y;
+        const bool use = valid && sx >= 0 && sy >= 0 && sx < nc && sy < nc &&
+                         (sx == 0 || sy == 0 || sx == nc - 1 || sy == nc - 1);
+        if (!use) continue;
+        const int64_t sc = (int64_t)sy * nc + sx;
+        double2 m[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double2 v = Ml[k * ncell + sc];
+            const double bk = b_k[k];
+            m[k] = make_double2(v.x * bk, v.y * bk);
+        }
+        const double2 *H = hank + od.z * (2 * P - 1);
+#pragma unroll
+        for (int ss = 0; ss < 2 * P - 1; ++ss) {
+            double2 h = H[ss];
+            if (ss == 0) h.x -= logw;
+#pragma unroll
+            for (int nn = (ss < P ? 0 : ss - P + 1); nn <= (ss < P ? ss : P - 1); ++nn)
+                cmac(acc[nn], h, m[ss - nn]);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) red[w - 1][k][lane] = acc[k];
+    }
+    __syncthreads();
+    if (w != 0 || !valid) return;
+    double2 *out = Lm + lv.off[l];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double2 b1 = red[0][k][lane], b2 = red[1][k][lane], b3 = red[2][k][lane];
+        const double an = a_n[k];
+        const double sx_ = ((acc[k].x + b1.x) + b2.x) + b3.x, sy_ = ((acc[k].y + b1.y) + b2.y) + b3.y;
+        out[k * ncell + (int64_t)iy * nc + ix] = make_double2(an * sx_, an * sy_);
+    }
 }
 
 // Pass 2 far field at the interior nodes: u += -(1/2pi) Re sum_k L~_k tau^k.
-// Block = a tile of up to 8x8 leaves whose local expansions are staged in
-// LDS; threads walk rows of the tile, so the read-modify-write of u is
-// coalesced.
+// Block = a tile of up to 8x8 leaves.  With chain = 1 the tile is one cell
+// of level L-3 and the block first builds the local expansions of levels
+// L-2..L in LDS from that cell's expansion (Lt) and the M2L sums (Lm);
+// otherwise the leaf expansions are read from Lt.  Threads walk rows of the
+// tile, so the read-modify-write of u is coalesced.
 template <int P>
-__global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a)
+__global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a, const double2 *__restrict__ Lm,
+                                                   const double2 *__restrict__ B, int chain)
 {
-    __shared__ double2 sL[P * 64];
+    __shared__ double2 sB[4 * P * P];
+    __shared__ double2 sm2l[P * 84];
+    __shared__ double2 buf0[P * 64], buf1[P * 64];
     const int n = a.n, nl = a.nl, tw = nl < 8 ? nl : 8, pw = tw * 8;
     const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw, cnt = tw * tw;
-    const int64_t ncell = (int64_t)nl * nl;
-    const double2 *Ll = a.Lt + a.lv.off[a.L];
-    for (int t = threadIdx.x; t < P * cnt; t += 256) {
-        const int k = t / cnt, c = t - k * cnt;
-        sL[t] = Ll[k * ncell + (int64_t)(ly0 + c / tw) * nl + lx0 + c % tw];
+    const double2 *sL;
+    if (chain) {
+        const int r = a.L - 3, nr = 1 << r;
+        if (threadIdx.x < P)
+            buf0[threadIdx.x] = a.Lt[a.lv.off[r] + (int64_t)threadIdx.x * nr * nr +
+                                     (int64_t)blockIdx.y * nr + blockIdx.x];
+        sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1);
+    } else {
+        const int64_t ncell = (int64_t)nl * nl;
+        const double2 *Ll = a.Lt + a.lv.off[a.L];
+        for (int t = threadIdx.x; t < P * cnt; t += 256) {
+            const int k = t / cnt, c = t - k * cnt;
+            buf0[t] = Ll[k * ncell + (int64_t)(ly0 + c / tw) * nl + lx0 + c % tw];
+        }
+        __syncthreads();
+        sL = buf0;
     }
-    __syncthreads();
 #pragma unroll 4
     for (int e = threadIdx.x; e < pw * pw; e += 256) {
         const int yy = e / pw, xx = e - yy * pw;
@@ -775,8 +1023,14 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
     const size_t shm = (size_t)P * 400 * sizeof(double2);
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
-        hipLaunchKernelGGL(k_m2l<P>, dim3(nitems), dim3(768), shm, s, items, M, Lm, pl->lv,
-                           pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b);
+        if (pl->prec == FMM_FP32)
+            hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems), dim3(768), shm / 2, s, items, M, Lm,
+                               pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
+                               pl->tab.m2l_b);
+        else
+            hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems), dim3(768), shm, s, items, M, Lm,
+                               pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
+                               pl->tab.m2l_b);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (const auto &c : down_chunks(pl->L))
@@ -818,7 +1072,10 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
-        hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(256), 0, s, a);
+        if (pl->prec == FMM_FP32)
+            hipLaunchKernelGGL(k_leaf_grid32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32);
+        else
+            hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(256), 0, s, a);
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
@@ -836,14 +1093,24 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
     const bool far = L >= 2;
     StageTimer t(pl, FMM_STAGE_PASS2, s);
     if (far) {
-        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((4 * (nl - 1) * P + 255) / 256), dim3(256), 0, s,
-                           pl->ring_q, pl->ws.M2 + pl->lv.off[L], (int)pl->n, nl);
-        run_m2m_from<P>(pl, pl->ws.M2, L, 1, s);
-        run_m2l_l2l<P>(pl, pl->ws.M2, pl->ws.Lm2, pl->ws.Lt2, pl->m2l_edge_items,
-                       pl->n_m2l_edge_items, s, false);
+        // upward: ring charges -> boundary leaves -> three levels up, border tiles only
+        const int tw = std::min(nl, 8), nt = nl / tw;
+        hipLaunchKernelGGL(k_m2m_up_ring<P>, dim3(nt > 1 ? 4 * (nt - 1) : 1), dim3(256), 0, s,
+                           pl->ring_q, pl->ws.M2, pl->tab.m2m, pl->lv, (int)pl->n, L);
+        run_m2m_from<P>(pl, pl->ws.M2, L - 3, 1, s);
+        // M2L from boundary cells into the three-cell band of every level
+        hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells), dim3(256), 0, s,
+                           pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
+                           pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b);
+        // downward: levels 2..L-3 by k_down, the last three inside the far-field kernel
+        const bool chain = L >= 5;
+        const int last = chain ? L - 3 : L;
+        for (const auto &c : down_chunks(last))
+            hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, pl->ws.Lm2,
+                               pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.top);
         const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far);
-        const int tw = std::min(nl, 8);
-        hipLaunchKernelGGL(k_pass2_far<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_pass2_far<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
+                           pl->tab.l2l, chain ? 1 : 0);
     }
     const int n = (int)pl->n;
     const int64_t nband = n <= 32 ? (int64_t)n * n : (int64_t)4 * 16 * n - 4 * 16 * 16;
@@ -895,8 +1162,10 @@ template <int P>
 static int m2l_attr_p(fmm_plan *pl)
 {
     const int shm = P * 400 * (int)sizeof(double2);
-    FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P>,
+    FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P, double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm));
+    FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P, float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, shm / 2));
     return FMM_OK;
 }
 

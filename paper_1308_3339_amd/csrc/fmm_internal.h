@@ -54,6 +54,8 @@ struct FmmTables {
     double2 *l2p;     // [64][p] grid L2P powers tau_j^k
     double *ktab;     // [31][31] log(h |d|), d in [-15, 15]^2, self entry log(eps h)
     double *rtab;     // [17][17] log(h |d|), |dx|, |dy| <= 16: ring node to interior node
+    float *ktab32;    // FP32 copy of ktab (precision variant)
+    float2 *hank32;   // FP32 copy of hank (precision variant)
 };
 
 struct Workspace {
@@ -74,6 +76,7 @@ struct fmm_plan {
     int L = 0;            // leaf level
     int nl = 1;           // leaves per side, 2^L
     int p = 10;
+    int prec = FMM_FP64;  // FMM_FP32: P2P and M2L in FP32
     int bem = 1;
     double h = 0.0;       // GRID mesh width
     double self_eps = 0.0;
@@ -85,8 +88,8 @@ struct fmm_plan {
     fmmprec::Workspace ws{};
     fmmprec::M2LItem *m2l_items = nullptr;  // all tiles of levels 2..L
     int n_m2l_items = 0;
-    fmmprec::M2LItem *m2l_edge_items = nullptr;  // tiles that see boundary cells
-    int n_m2l_edge_items = 0;
+    int4 *ring_cells = nullptr;   // strips within 3 cells of the boundary (see k_m2l_ring)
+    int n_ring_cells = 0;
 
     // boundary correction (GRID, bem = 1): inverses of the three distinct
     // diagonal blocks of the rotation-diagonalised collocation matrix

@@ -1,0 +1,105 @@
+"""Precision variant (P2P and M2L in FP32, everything else FP64) against the
+FP64 oracle.
+
+The variant changes the preconditioner only by rounding, so:
+  * per-stage error against the FP64 oracle (volume potential, ring
+    potential, boundary density, z) <= 1e-5 relative (max-norm); the FP32
+    sums are 24-term partials folded into FP64, the FMM truncation at p = 10
+    is ~1e-6, so a few 1e-6 is the expected level;
+  * the flexible outer iteration still reaches the FP64 true residual
+    <= 1e-8, within two iterations of the FP64 preconditioner, and the
+    solution agrees with the oracle's within 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as o
+from paper_1308_3339_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relmax(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("n", [32, 128, 256])
+def test_fp32_stages_against_fp64_oracle(n):
+    import torch
+
+    import paper_1308_3339_amd as fp
+    say("case fp32 stages n=%d" % n)
+    p = 10
+    r = inputs.random_charges(n * n, seed=600 + n)
+    with fp.fmm_setup(n=n, p=p, bem=1, prec=fp.FMM_FP32) as plan:
+        u = torch.empty(n * n, dtype=torch.float64, device="cuda")
+        plan.apply(dev(r), u)
+        z, phi, sig = (torch.empty(m, dtype=torch.float64, device="cuda") for m in (n * n, 4 * n, 4 * n))
+        plan.precond_stages(dev(r), z, phi, sig)
+        ug, zg, phig, sigg = host(u), host(z), host(phi), host(sig)
+    uo = o.grid_fmm(n, p, r)
+    zo, phio, sigo = o.Preconditioner(n, p=p).apply(r, stages=True)
+    errs = {"volume": relmax(ug, uo), "phi_ring": relmax(phig, phio), "sigma": relmax(sigg, sigo),
+            "z": relmax(zg, zo)}
+    say("  per-stage rel err vs FP64 oracle", errs)
+    for k, v in errs.items():
+        assert v <= 1e-5, k
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_fp32_solve_reaches_fp64_residual(n):
+    import torch
+
+    import paper_1308_3339_amd as fp
+    say("case fp32 solve n=%d" % n)
+    f = inputs.gaussian_bumps(n, 16, seed=700 + n)
+    its = {}
+    sols = {}
+    for prec in (fp.FMM_FP64, fp.FMM_FP32):
+        with fp.fmm_setup(n=n, p=10, prec=prec) as plan:
+            u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+            info = plan.solve(dev(f), u)
+            assert info["converged"]
+            sols[prec], its[prec] = host(u), info["iters"]
+    say("  iterations fp64 %d fp32 %d" % (its[fp.FMM_FP64], its[fp.FMM_FP32]))
+    res = np.linalg.norm(f - o.stencil(n, sols[fp.FMM_FP32])) / np.linalg.norm(f)
+    assert res <= 1e-8
+    assert its[fp.FMM_FP32] <= its[fp.FMM_FP64] + 2
+    xo, _ = o.fgmres(n, f, o.Preconditioner(n, p=10))
+    assert np.linalg.norm(sols[fp.FMM_FP32] - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_fp32_full_size_solve():
+    import torch
+
+    import paper_1308_3339_amd as fp
+    n = 2048
+    say("case fp32 solve n=2048")
+    f = inputs.gaussian_bumps(n, 16, seed=inputs.SEED_BUMPS_2048)
+    with fp.fmm_setup(n=n, p=10, prec=fp.FMM_FP32) as plan:
+        u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+        info = plan.solve(dev(f), u)
+        ug = host(u)
+    say("  info", info)
+    assert info["converged"]
+    res = np.linalg.norm(f - o.stencil(n, ug)) / np.linalg.norm(f)
+    say("  CPU-recomputed true rel res %.3e" % res)
+    assert res <= 1e-8
