@@ -67,7 +67,8 @@ typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
 typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
 
 /* The problem the plan is built for.
- *   GRID:   n = interior points per side, n = 8 * 2^L (L >= 0); x, y unused.
+ *   GRID:   n = interior points per side, n = 8 * 2^L with 0 <= L <= 12 (n <= 32768,
+ *           so that n^2 < 2^32); x, y unused.
  *           The quadtree root is the square [h/2, 1-h/2]^2, whose leaves are
  *           the 8 x 8 blocks of the grid.
  *   POINTS: n = number of points N >= 1; x, y = DEVICE arrays of N

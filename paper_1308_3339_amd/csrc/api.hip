@@ -287,10 +287,10 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (prob->kind == FMM_GRID) {
         const int64_t n = prob->n;
         int L = 0;
-        while (((int64_t)8 << L) < n && L < 16) ++L;
+        while (((int64_t)8 << L) < n && L < 12) ++L;
         if (n < 8 || ((int64_t)8 << L) != n) {
             delete pl;
-            return fail(nullptr, FMM_ERR_ARG, "GRID n must be 8 * 2^L");
+            return fail(nullptr, FMM_ERR_ARG, "GRID n must be 8 * 2^L with n <= 32768");
         }
         pl->L = L;
         pl->nl = 1 << L;

@@ -1,17 +1,28 @@
 // Krylov solver around the FMM-BEM preconditioner: the 5-point stencil
-// (Sec. 2.1, eq. axb) and right-preconditioned FGMRES(m) with classical
-// Gram-Schmidt applied twice (GMRES is the Krylov method the paper cites in
-// Sec. 1; right preconditioning as in Sec. 3.1).
+// (Sec. 2.1, eq. axb) and right-preconditioned FGMRES(m) (GMRES is the
+// Krylov method the paper cites in Sec. 1; right preconditioning as in
+// Sec. 3.1).
 //
-// Every vector kernel is HBM bound.  The Arnoldi step is fused into three
-// passes over the basis:
-//   1. w = A z_j and the partial dots V^T w           (stencil + GEMV-T)
-//   2. w -= V h1 and the partial dots V^T w           (GEMV + GEMV-T)
-//   3. w -= V h2 and the partial sum of w^2           (GEMV + norm)
-// followed by v_{j+1} = w / ||w||.  Reductions are two-stage with a fixed
+// Orthogonalisation is classical Gram-Schmidt applied twice, with the second
+// pass and the normalisation of each new vector delayed by one step, so that
+// a step makes one reduction and two sweeps over the basis.  Step j holds
+// finished vectors v_0..v_{j-1} and a candidate u = V_j that has had one
+// projection; it computes z = P u, w = A z and then
+//   sweep A: a_i = v_i.u, b_i = v_i.w (i < j), c = u.u, d = u.w, e = w.w
+//   (small kernel) rho = sqrt(c - |a|^2), h_j = (d - a.b) / rho,
+//                  rt = sqrt(e - |b|^2 - h_j^2)
+//   sweep B: v_j = (u - sum a_i v_i) / rho           (second projection of u)
+//            u'  = (w - sum b_i v_i - h_j v_j) / rt   (first projection of w)
+// w is never stored: both sweeps evaluate the stencil of z on the fly.  The
+// host keeps the Hessenberg matrix unrotated; the second projection of u
+// corrects the previous column (rows i < j gain rt_prev a_i, the subdiagonal
+// becomes rt_prev rho) before the Givens rotations are rebuilt.  The Z
+// vectors of the flexible method are P applied to the candidates, which the
+// Arnoldi relation A Z = V H accounts for exactly.
+//
+// Every vector kernel is HBM bound.  Reductions are two-stage with a fixed
 // order (no atomics), so repeated solves are bitwise reproducible.  One
-// small device-to-host copy per inner iteration feeds the Givens rotations
-// on the host.
+// small device-to-host copy per inner iteration feeds the host.
 #include <cmath>
 #include <vector>
 
@@ -19,11 +30,15 @@
 
 namespace fmmprec {
 
-constexpr int kMaxBasis = 32;   // restart <= 32: at most 32 basis vectors in a dot
+constexpr int kMaxBasis = 32;   // restart <= 32
 constexpr int kRedBlocks = 4096;  // partial sums per reduction (coefficient-major)
+constexpr int kPartRows = 2 * kMaxBasis + 4;
 
 // layout of plan->dscal (device) / plan->hpin (host mirror)
-constexpr int kH1 = 0, kHsum = 32, kNrm = 64, kH2 = 96, kScal = 128;
+constexpr int kRaw = 0;     // a_0..a_{j-1}, b_0..b_{j-1}, c, d, e
+constexpr int kOut = 72;    // rho, h_j, rt
+constexpr int kCoef = 80;   // sweep-B coefficients: 1/rho, 1/rt, -h_j/(rho rt), -a_i/rho, -(b_i - h_j a_i/rho)/rt
+constexpr int kScal = 160;  // norms
 
 __global__ __launch_bounds__(256) void k_stencil(const double *__restrict__ v,
                                                  double *__restrict__ w, int n, double ih2)
@@ -40,121 +55,152 @@ __global__ __launch_bounds__(256) void k_stencil(const double *__restrict__ v,
     w[e] = c * ih2;
 }
 
-__device__ __forceinline__ double stencil_at(const double *__restrict__ v, int64_t e, int n)
+// unscaled stencil at element e of a row-major n x n grid, n = 2^ln
+__device__ __forceinline__ double stencil_at(const double *__restrict__ v, uint32_t e, int n, int ln)
 {
-    const int i = (int)(e % n), j = (int)(e / n);
+    const uint32_t i = e & (uint32_t)(n - 1), j = e >> ln;
     double c = 4.0 * v[e];
     if (i > 0) c -= v[e - 1];
-    if (i < n - 1) c -= v[e + 1];
+    if (i < (uint32_t)n - 1) c -= v[e + 1];
     if (j > 0) c -= v[e - n];
-    if (j < n - 1) c -= v[e + n];
+    if (j < (uint32_t)n - 1) c -= v[e + n];
     return c;
 }
 
 // block-level sum of NV per-thread values into part[i * kRedBlocks + blockIdx.x]
 template <int NV>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, double *part)
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *part)
 {
-    __shared__ double red[4][kMaxBasis];
+    __shared__ double red[4][NV];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        if (i < nv) {
-            double a = acc[i];
-            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-            if (lane == 0) red[wv][i] = a;
-        }
+        double a = acc[i];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if (lane == 0) red[wv][i] = a;
     }
     __syncthreads();
-    if (threadIdx.x < nv)
+    if (threadIdx.x < NV)
         part[(size_t)threadIdx.x * kRedBlocks + blockIdx.x] =
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-// w = A z (scaled by 1/h^2) and partial dots V_i . w, i < NV
-template <int NV>
-__global__ __launch_bounds__(256) void k_stencil_dots(const double *__restrict__ z,
-                                                      double *__restrict__ w,
+// sweep A of step NJ: partial sums of a_i, b_i (i < NJ), c, d, e with
+// u = V_NJ and w = A z (scaled by 1/h^2)
+template <int NJ>
+__global__ __launch_bounds__(256) void k_arnoldi_dots(const double *__restrict__ z,
                                                       const double *__restrict__ V, int64_t ldv,
-                                                      double *__restrict__ part, int n, double ih2)
+                                                      double *__restrict__ part, int n, int ln,
+                                                      double ih2)
 {
-    const int64_t N = (int64_t)n * n;
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-        double vv[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) vv[i] = V[i * ldv + e];
-        const double we = stencil_at(z, e, n) * ih2;
-        w[e] = we;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] = fma(vv[i], we, acc[i]);
-    }
-    block_reduce_store<NV>(acc, NV, part);
-}
-
-// w -= sum_i h_i V_i; then partial dots V_i . w (MODE 0) or partial w.w (MODE 1)
-template <int NV, int MODE>
-__global__ __launch_bounds__(256) void k_update(const double *__restrict__ V, int64_t ldv,
-                                                double *__restrict__ w,
-                                                const double *__restrict__ hc,
-                                                double *__restrict__ part, int64_t N)
-{
-    constexpr int NA = MODE == 0 ? NV : 1;
+    constexpr int NA = 2 * NJ + 3;
+    const uint32_t N = (uint32_t)n << ln;
     double acc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-    double hv[NV];
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < N; e += gridDim.x * 256u) {
+        double vv[NJ > 0 ? NJ : 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hv[i] = hc[i];
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-        double vv[NV];
+        for (int i = 0; i < NJ; ++i) vv[i] = V[i * ldv + e];
+        const double u = V[NJ * ldv + e];
+        const double w = stencil_at(z, e, n, ln) * ih2;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) vv[i] = V[i * ldv + e];
-        double we = w[e];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) we = fma(-hv[i], vv[i], we);
-        w[e] = we;
-        if (MODE == 0) {
-#pragma unroll
-            for (int i = 0; i < NA; ++i) acc[i] = fma(vv[i], we, acc[i]);
-        } else {
-            acc[0] = fma(we, we, acc[0]);
+        for (int i = 0; i < NJ; ++i) {
+            acc[i] = fma(vv[i], u, acc[i]);
+            acc[NJ + i] = fma(vv[i], w, acc[NJ + i]);
         }
+        acc[2 * NJ] = fma(u, u, acc[2 * NJ]);
+        acc[2 * NJ + 1] = fma(u, w, acc[2 * NJ + 1]);
+        acc[2 * NJ + 2] = fma(w, w, acc[2 * NJ + 2]);
     }
-    block_reduce_store<NA>(acc, NA, part);
+    block_reduce_store<NA>(acc, part);
 }
 
-#define KRY_NV_CASES(X) \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) \
-    X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
-
-static void launch_stencil_dots(int nv, dim3 g, hipStream_t s, const double *z, double *w,
-                                const double *V, int64_t ldv, double *part, int n, double ih2)
+// rho, h_j, rt and the sweep-B coefficients from the reduced sums of step nj
+__global__ void k_arnoldi_coef(double *__restrict__ d, int nj)
 {
-    switch (nv) {
-#define X(k) case k: hipLaunchKernelGGL(k_stencil_dots<k>, g, dim3(256), 0, s, z, w, V, ldv, part, n, ih2); break;
-        KRY_NV_CASES(X)
+    if (threadIdx.x != 0) return;
+    const double *a = d + kRaw, *b = d + kRaw + nj;
+    const double c = d[kRaw + 2 * nj], ud = d[kRaw + 2 * nj + 1], e = d[kRaw + 2 * nj + 2];
+    double sa = 0.0, sb = 0.0, sab = 0.0;
+    for (int i = 0; i < nj; ++i) {
+        sa = fma(a[i], a[i], sa);
+        sb = fma(b[i], b[i], sb);
+        sab = fma(a[i], b[i], sab);
+    }
+    const double rho2 = c - sa;
+    const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    const double irho = rho > 0.0 ? 1.0 / rho : 0.0;
+    const double hj = (ud - sab) * irho;
+    const double rt2 = e - sb - hj * hj;
+    const double rt = rt2 > 0.0 ? sqrt(rt2) : 0.0;
+    const double irt = rt > 0.0 ? 1.0 / rt : 0.0;
+    d[kOut] = rho;
+    d[kOut + 1] = hj;
+    d[kOut + 2] = rt;
+    double *cf = d + kCoef;
+    cf[0] = irho;
+    cf[1] = irt;
+    cf[2] = -hj * irho * irt;
+    for (int i = 0; i < nj; ++i) {
+        cf[3 + i] = -a[i] * irho;
+        cf[3 + nj + i] = -(b[i] - hj * a[i] * irho) * irt;
+    }
+}
+
+// sweep B of step NJ: V_NJ <- v_NJ (finished), V_NJ+1 <- next candidate
+template <int NJ>
+__global__ __launch_bounds__(256) void k_arnoldi_update(const double *__restrict__ z,
+                                                        double *__restrict__ V, int64_t ldv,
+                                                        const double *__restrict__ cf, int n,
+                                                        int ln, double ih2)
+{
+    const uint32_t N = (uint32_t)n << ln;
+    const double cu = cf[0], cw = cf[1], cuu = cf[2];
+    double cv[NJ > 0 ? NJ : 1], cn[NJ > 0 ? NJ : 1];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        cv[i] = cf[3 + i];
+        cn[i] = cf[3 + NJ + i];
+    }
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < N; e += gridDim.x * 256u) {
+        double vv[NJ > 0 ? NJ : 1];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) vv[i] = V[i * ldv + e];
+        const double u = V[NJ * ldv + e];
+        const double w = stencil_at(z, e, n, ln) * ih2;
+        double vj = cu * u, un = fma(cuu, u, cw * w);
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            vj = fma(cv[i], vv[i], vj);
+            un = fma(cn[i], vv[i], un);
+        }
+        V[NJ * ldv + e] = vj;
+        V[(NJ + 1) * ldv + e] = un;
+    }
+}
+
+#define KRY_NJ_CASES(X) \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
+    X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
+
+static void launch_arnoldi_dots(int nj, dim3 g, hipStream_t s, const double *z, const double *V,
+                                int64_t ldv, double *part, int n, int ln, double ih2)
+{
+    switch (nj) {
+#define X(k) case k: hipLaunchKernelGGL(k_arnoldi_dots<k>, g, dim3(256), 0, s, z, V, ldv, part, n, ln, ih2); break;
+        KRY_NJ_CASES(X)
 #undef X
     }
 }
 
-static void launch_update(int nv, int mode, dim3 g, hipStream_t s, const double *V, int64_t ldv,
-                          double *w, const double *hc, double *part, int64_t N)
+static void launch_arnoldi_update(int nj, dim3 g, hipStream_t s, const double *z, double *V,
+                                  int64_t ldv, const double *cf, int n, int ln, double ih2)
 {
-    if (mode == 0) {
-        switch (nv) {
-#define X(k) case k: hipLaunchKernelGGL((k_update<k, 0>), g, dim3(256), 0, s, V, ldv, w, hc, part, N); break;
-            KRY_NV_CASES(X)
+    switch (nj) {
+#define X(k) case k: hipLaunchKernelGGL(k_arnoldi_update<k>, g, dim3(256), 0, s, z, V, ldv, cf, n, ln, ih2); break;
+        KRY_NJ_CASES(X)
 #undef X
-        }
-    } else {
-        switch (nv) {
-#define X(k) case k: hipLaunchKernelGGL((k_update<k, 1>), g, dim3(256), 0, s, V, ldv, w, hc, part, N); break;
-            KRY_NV_CASES(X)
-#undef X
-        }
     }
 }
 
@@ -162,16 +208,17 @@ static void launch_update(int nv, int mode, dim3 g, hipStream_t s, const double 
 __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ r,
-                                                  double *__restrict__ part, int n, double ih2)
+                                                  double *__restrict__ part, int n, int ln,
+                                                  double ih2)
 {
-    const int64_t N = (int64_t)n * n;
+    const uint32_t N = (uint32_t)n << ln;
     double acc[1] = {0.0};
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256) {
-        const double re = b[e] - stencil_at(x, e, n) * ih2;
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < N; e += gridDim.x * 256u) {
+        const double re = b[e] - stencil_at(x, e, n, ln) * ih2;
         r[e] = re;
         acc[0] = fma(re, re, acc[0]);
     }
-    block_reduce_store<1>(acc, 1, part);
+    block_reduce_store<1>(acc, part);
 }
 
 // partial v.v
@@ -181,7 +228,7 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ v,
     double acc[1] = {0.0};
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < N; e += (int64_t)gridDim.x * 256)
         acc[0] = fma(v[e], v[e], acc[0]);
-    block_reduce_store<1>(acc, 1, part);
+    block_reduce_store<1>(acc, part);
 }
 
 // out[i] = sum_b part[i][b] (+ add[i]); mode 1: out[i] = sqrt(sum); out2, if
@@ -304,7 +351,7 @@ static int ensure_krylov(fmm_plan *pl, int m)
     if (pl->Z) { hipFree(pl->Z); pl->Z = nullptr; }
     if (!pl->w) FMM_HIP(pl, hipMalloc(&pl->w, N * sizeof(double)));
     if (!pl->b) FMM_HIP(pl, hipMalloc(&pl->b, N * sizeof(double)));
-    if (!pl->partial) FMM_HIP(pl, hipMalloc(&pl->partial, (size_t)kRedBlocks * kMaxBasis * sizeof(double)));
+    if (!pl->partial) FMM_HIP(pl, hipMalloc(&pl->partial, (size_t)kRedBlocks * kPartRows * sizeof(double)));
     if (!pl->dscal) FMM_HIP(pl, hipMalloc(&pl->dscal, 256 * sizeof(double)));
     if (!pl->hpin) FMM_HIP(pl, hipHostMalloc((void **)&pl->hpin, 256 * sizeof(double), hipHostMallocDefault));
     hipError_t e1 = hipMalloc(&pl->V, (size_t)(m + 1) * N * sizeof(double));
@@ -336,6 +383,7 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
     const int n = (int)pl->n;
     const int64_t N = (int64_t)n * n;
     const double ih2 = 1.0 / (pl->h * pl->h);
+    const int ln = pl->L + 3;      // n = 2^ln
     const int nblk = red_blocks(N);
     const dim3 gv(nblk), bv(256);
 
@@ -351,14 +399,16 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
         if (res) *res = r;
         return FMM_OK;
     }
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), gg(m + 1), y(m);
+    // Hr: unrotated Hessenberg matrix (row-major, (m + 1) x m); H, gg: its
+    // Givens-rotated copy and right-hand side, rebuilt after every step
+    std::vector<double> Hr((size_t)(m + 1) * m), H((size_t)(m + 1) * m), cs(m), sn(m), gg(m + 1), y(m);
     int iters = 0, status = FMM_NOT_CONVERGED;
     double est = 1.0;
     for (;;) {
         // true residual of the current iterate
         {
             StageTimer t(pl, FMM_STAGE_STENCIL, s);
-            hipLaunchKernelGGL(k_residual, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ih2);
+            hipLaunchKernelGGL(k_residual, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ln, ih2);
         }
         double beta = 0.0;
         if ((st = fetch_norm(pl, nblk, kScal, &beta, s)) != FMM_OK) return st;
@@ -367,53 +417,60 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
         if (beta / bnorm <= tol) { status = FMM_OK; break; }
         if (iters >= maxit) { status = FMM_NOT_CONVERGED; break; }
         hipLaunchKernelGGL(k_scale, gv, bv, 0, s, pl->w, pl->V, nullptr, 1.0 / beta, N);
-        std::fill(gg.begin(), gg.end(), 0.0);
-        gg[0] = beta;
+        std::fill(Hr.begin(), Hr.end(), 0.0);
+        double g0 = beta, rt_prev = 0.0;
         int k = 0;
         for (int j = 0; j < m && iters < maxit; ++j) {
-            double *vj = pl->V + (size_t)j * N, *zj = pl->Z + (size_t)j * N;
-            if ((st = precond_apply_one(pl, vj, zj, nullptr, nullptr, s)) != FMM_OK) return st;
-            const int nv = j + 1;
+            double *uj = pl->V + (size_t)j * N, *zj = pl->Z + (size_t)j * N;
+            if ((st = precond_apply_one(pl, uj, zj, nullptr, nullptr, s)) != FMM_OK) return st;
             StageTimer ta(pl, FMM_STAGE_ARNOLDI, s);
-            // pass 1: w = A z_j, h1 = V^T w
-            launch_stencil_dots(nv, gv, s, zj, pl->w, pl->V, N, pl->partial, n, ih2);
-            hipLaunchKernelGGL(k_finish, dim3(nv), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kH1,
-                               nullptr, nullptr, 0);
-            // pass 2: w -= V h1, h2 = V^T w, hsum = h1 + h2
-            launch_update(nv, 0, gv, s, pl->V, N, pl->w, pl->dscal + kH1, pl->partial, N);
-            hipLaunchKernelGGL(k_finish, dim3(nv), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kHsum,
-                               pl->dscal + kH1, pl->dscal + kH2, 0);
-            // pass 3: w -= V h2, ||w||
-            launch_update(nv, 1, gv, s, pl->V, N, pl->w, pl->dscal + kH2, pl->partial, N);
-            hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, pl->dscal + kNrm,
-                               nullptr, nullptr, 1);
-            hipLaunchKernelGGL(k_scale, gv, bv, 0, s, pl->w, pl->V + (size_t)(j + 1) * N, pl->dscal + kNrm, 0.0, N);
+            launch_arnoldi_dots(j, gv, s, zj, pl->V, N, pl->partial, n, ln, ih2);
+            hipLaunchKernelGGL(k_finish, dim3(2 * j + 3), dim3(256), 0, s, pl->partial, nblk,
+                               pl->dscal + kRaw, nullptr, nullptr, 0);
+            hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(64), 0, s, pl->dscal, j);
+            launch_arnoldi_update(j, gv, s, zj, pl->V, N, pl->dscal + kCoef, n, ln, ih2);
             ta.stop();
-            FMM_HIP(pl, hipMemcpyAsync(pl->hpin + kHsum, pl->dscal + kHsum, 33 * sizeof(double),
+            FMM_HIP(pl, hipMemcpyAsync(pl->hpin, pl->dscal, kCoef * sizeof(double),
                                        hipMemcpyDeviceToHost, s));
             FMM_HIP(pl, hipStreamSynchronize(s));
             FMM_HIP(pl, hipGetLastError());
-            const double hn = pl->hpin[kNrm];
-            if (!std::isfinite(hn)) return fail(pl, FMM_ERR_NUMERIC, "Arnoldi produced a non-finite norm");
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = pl->hpin[kHsum + i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            const double *a = pl->hpin + kRaw, *bb = pl->hpin + kRaw + j;
+            const double rho = pl->hpin[kOut], hj = pl->hpin[kOut + 1], rt = pl->hpin[kOut + 2];
+            if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(hj) || !std::isfinite(rt))
+                return fail(pl, FMM_ERR_NUMERIC, "Arnoldi produced a non-finite or zero norm");
+            if (j == 0) {
+                g0 = beta * rho;           // r = beta u_0 = beta rho v_0
+            } else {                       // second projection of u_j fixes column j - 1
+                for (int i = 0; i < j; ++i) Hr[(size_t)i * m + j - 1] += rt_prev * a[i];
+                Hr[(size_t)j * m + j - 1] = rt_prev * rho;
             }
-            const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-            const double rr = std::hypot(a, c);
-            cs[j] = a / rr;
-            sn[j] = c / rr;
-            H[(size_t)j * m + j] = rr;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            gg[j + 1] = -sn[j] * gg[j];
-            gg[j] = cs[j] * gg[j];
+            for (int i = 0; i < j; ++i) Hr[(size_t)i * m + j] = bb[i];
+            Hr[(size_t)j * m + j] = hj;
+            Hr[(size_t)(j + 1) * m + j] = rt;
+            rt_prev = rt;
+            // Givens QR of columns 0..j
+            H = Hr;
+            std::fill(gg.begin(), gg.end(), 0.0);
+            gg[0] = g0;
+            for (int c = 0; c <= j; ++c) {
+                for (int i = 0; i < c; ++i) {
+                    const double x0 = H[(size_t)i * m + c], x1 = H[(size_t)(i + 1) * m + c];
+                    H[(size_t)i * m + c] = cs[i] * x0 + sn[i] * x1;
+                    H[(size_t)(i + 1) * m + c] = -sn[i] * x0 + cs[i] * x1;
+                }
+                const double x0 = H[(size_t)c * m + c], x1 = H[(size_t)(c + 1) * m + c];
+                const double rr = std::hypot(x0, x1);
+                cs[c] = x0 / rr;
+                sn[c] = x1 / rr;
+                H[(size_t)c * m + c] = rr;
+                H[(size_t)(c + 1) * m + c] = 0.0;
+                gg[c + 1] = -sn[c] * gg[c];
+                gg[c] = cs[c] * gg[c];
+            }
             ++iters;
             k = j + 1;
             est = std::fabs(gg[j + 1]) / bnorm;
-            if (est <= tol || hn == 0.0) break;
+            if (est <= tol || rt == 0.0) break;
         }
         for (int i = k - 1; i >= 0; --i) {
             double sacc = gg[i];
