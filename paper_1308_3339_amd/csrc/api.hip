@@ -283,6 +283,13 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     pl->p = prm->p;
     pl->prec = prm->prec;
     pl->bem = prm->bem ? 1 : 0;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            ncu > 0)
+            pl->ncu = ncu;
+    }
     int st = FMM_OK;
     if (prob->kind == FMM_GRID) {
         const int64_t n = prob->n;

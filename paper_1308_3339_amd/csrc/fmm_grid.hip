@@ -55,6 +55,33 @@ __device__ __forceinline__ double wave_sum(double a)
     return a;
 }
 
+// Block-wide LDS staging for 256-thread blocks, split in two halves:
+// fetch() loads elements t = tid + 256 r (t < cnt) of a gather into
+// registers, put() hands them to a store functor.  Kernels fetch every table
+// and tile before storing any of them, so a block waits for one memory round
+// trip rather than one per loop trip.
+constexpr int rounds256(int cnt) { return (cnt + 255) / 256; }
+
+template <int R, typename T, typename F>
+__device__ __forceinline__ void fetch(T (&v)[R], int cnt, F src)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int t = threadIdx.x + 256 * r;
+        if (t < cnt) v[r] = src(t);
+    }
+}
+
+template <int R, typename T, typename F>
+__device__ __forceinline__ void put(const T (&v)[R], int cnt, F dst)
+{
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int t = threadIdx.x + 256 * r;
+        if (t < cnt) dst(t, v[r]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Upward pass.
 // m2m_tile: parents of a cw x cw child tile held in LDS as [k][cw*cw];
@@ -150,22 +177,21 @@ __global__ __launch_bounds__(256) void k_p2m_up(const double *__restrict__ q, do
     const int nl = 1 << L, tw = nl < 8 ? nl : 8, pw = tw * 8;
     const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw;
     const int tid = threadIdx.x;
-    for (int e = tid; e < P * 64; e += 256) sw[e] = W[e];
-    for (int e = tid; e < 4 * P * P; e += 256) sA[e] = A[e];
-    for (int e0 = tid; e0 < pw * pw; e0 += 256 * 8) {
-        double v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = e0 + 256 * i;
-            const int yy = e / pw, xx = e - yy * pw;
-            v[i] = (e < pw * pw) ? q[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = e0 + 256 * i;
-            const int yy = e / pw, xx = e - yy * pw;
-            if (e < pw * pw) sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = v[i];
-        }
+    const int lpw = __builtin_ctz(pw);   // pw = 8 tw is a power of two
+    {
+        double2 vw[rounds256(P * 64)], va[rounds256(4 * P * P)];
+        double vq[16];
+        fetch(vw, P * 64, [&](int t) { return W[t]; });
+        fetch(va, 4 * P * P, [&](int t) { return A[t]; });
+        fetch(vq, pw * pw, [&](int e) {
+            return q[(size_t)(ly0 * 8 + (e >> lpw)) * n + lx0 * 8 + (e & (pw - 1))];
+        });
+        put(vw, P * 64, [&](int t, double2 x) { sw[t] = x; });
+        put(va, 4 * P * P, [&](int t, double2 x) { sA[t] = x; });
+        put(vq, pw * pw, [&](int e, double x) {
+            const int yy = e >> lpw, xx = e & (pw - 1);
+            sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = x;
+        });
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -217,10 +243,16 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
     const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l_in];
-    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sA[e] = A[e];
-    for (int t = threadIdx.x; t < P * cnt; t += 256) {
-        const int k = t / cnt, c = t - k * cnt;
-        s0[t] = Ml[k * ncell + (int64_t)(y0 + c / tw) * nc + x0 + c % tw];
+    const int ltw = __builtin_ctz(tw);
+    {
+        double2 va[rounds256(4 * P * P)], vs[rounds256(P * 64)];
+        fetch(va, 4 * P * P, [&](int t) { return A[t]; });
+        fetch(vs, P * cnt, [&](int t) {
+            const int k = t >> (2 * ltw), c = t & (cnt - 1);
+            return Ml[k * ncell + (int64_t)(y0 + (c >> ltw)) * nc + x0 + (c & (tw - 1))];
+        });
+        put(va, 4 * P * P, [&](int t, double2 x) { sA[t] = x; });
+        put(vs, P * cnt, [&](int t, double2 x) { s0[t] = x; });
     }
     __syncthreads();
     m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, l_in, tw, x0, y0);
@@ -360,24 +392,42 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 // r, whose expansion is in buf0[0..P).  Levels r+1..r+m are built in LDS
 // (and stored to Lt when Lt != nullptr); returns the buffer that holds the
 // deepest level, laid out [k][tw*tw] with tw = 2^m.
+// The block's own expansion is read from top[k * top_stride] (k < P) in the
+// same round trip as the tables and M2L sums, and also stored to top_out when
+// that is not null.
 template <int P>
 __device__ __forceinline__ const double2 *down_levels(const double2 *__restrict__ Lm,
                                                       double2 *__restrict__ Lt,
                                                       const double2 *__restrict__ B,
                                                       const LevelInfo &lv, int r, int m, int rx,
                                                       int ry, double2 *sB, double2 *sm2l,
-                                                      double2 *buf0, double2 *buf1)
+                                                      double2 *buf0, double2 *buf1,
+                                                      const double2 *__restrict__ top,
+                                                      int64_t top_stride,
+                                                      double2 *__restrict__ top_out)
 {
-    for (int e = threadIdx.x; e < 4 * P * P; e += blockDim.x) sB[e] = B[e];
-    for (int st = 1; st <= m; ++st) {
-        const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
-        const int base = ((1 << (2 * st)) - 4) / 3;   // 0, 4, 20
-        const int64_t ncell = (int64_t)nc * nc;
-        for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
-            const int nn = t / cnt, c = t - nn * cnt;
-            sm2l[nn * 84 + base + c] =
-                Lm[lv.off[l] + nn * ncell + (int64_t)(ry * tw + c / tw) * nc + rx * tw + c % tw];
-        }
+    {
+        auto m2l_sum = [&](int st, int t) {
+            const int l = r + st, tw = 1 << st, nc = 1 << l;
+            const int nn = t >> (2 * st), c = t & (tw * tw - 1);
+            return Lm[lv.off[l] + nn * (int64_t)nc * nc + (int64_t)(ry * tw + (c >> st)) * nc +
+                      rx * tw + (c & (tw - 1))];
+        };
+        double2 vb[rounds256(4 * P * P)], vt[1], v1[rounds256(4 * P)], v2[rounds256(16 * P)],
+            v3[rounds256(64 * P)];
+        fetch(vb, 4 * P * P, [&](int t) { return B[t]; });
+        fetch(vt, P, [&](int t) { return top[t * top_stride]; });
+        fetch(v1, m >= 1 ? 4 * P : 0, [&](int t) { return m2l_sum(1, t); });
+        fetch(v2, m >= 2 ? 16 * P : 0, [&](int t) { return m2l_sum(2, t); });
+        fetch(v3, m >= 3 ? 64 * P : 0, [&](int t) { return m2l_sum(3, t); });
+        put(vb, 4 * P * P, [&](int t, double2 x) { sB[t] = x; });
+        put(vt, P, [&](int t, double2 x) {
+            buf0[t] = x;
+            if (top_out) top_out[t * top_stride] = x;
+        });
+        put(v1, m >= 1 ? 4 * P : 0, [&](int t, double2 x) { sm2l[(t >> 2) * 84 + (t & 3)] = x; });
+        put(v2, m >= 2 ? 16 * P : 0, [&](int t, double2 x) { sm2l[(t >> 4) * 84 + 4 + (t & 15)] = x; });
+        put(v3, m >= 3 ? 64 * P : 0, [&](int t, double2 x) { sm2l[(t >> 6) * 84 + 20 + (t & 63)] = x; });
     }
     __syncthreads();
     const double2 *prev = buf0;
@@ -417,25 +467,34 @@ __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
     __shared__ double2 sm2l[P * 84];          // M2L sums of the 4 + 16 + 64 descendants
     __shared__ double2 buf0[P * 64], buf1[P * 64];
     const int nr = 1 << r;
-    const int rx = blockIdx.x % nr, ry = blockIdx.x / nr;
-    if (threadIdx.x < P) {
-        const int64_t gi = lv.off[r] + (int64_t)threadIdx.x * nr * nr + (int64_t)ry * nr + rx;
-        const double2 v = top ? Lm[gi] : Lt[gi];
-        buf0[threadIdx.x] = v;
-        if (top) Lt[gi] = v;
-    }
-    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1);
+    const int rx = blockIdx.x & (nr - 1), ry = blockIdx.x >> r;
+    const int64_t gi = lv.off[r] + (int64_t)ry * nr + rx;
+    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1, (top ? Lm : Lt) + gi,
+                   (int64_t)nr * nr, top ? Lt + gi : nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // Fused leaf stage for grid plans:
 //   u = -(1/2pi) [ qscale * sum_{3x3 leaves} q_j T(d_ij) + Re sum_k L~_k tau^k ]
 // T(d) = log(h|d|) for lattice offsets d != 0 and log(eps h) for d = 0 (the
-// regularised self term).  Block = 8x8 leaves; lane = leaf; wave w serves
-// target rows 2w, 2w+1 of every leaf (16 targets per lane).  For a fixed
+// regularised self term).  Block = 8x8 leaves; lane = leaf; wave w of 8
+// serves target row w of every leaf (8 targets per lane).  For a fixed
 // source position all lanes need the same T values, so T rows are read with
 // scalar loads and broadcast, and the q tile sits in LDS as [pos][leaf].
 // ---------------------------------------------------------------------------
+// LDS layout of the 10x10-leaf q tile of the leaf kernels.  Source position
+// pos (0..63) of leaf (row r, col c) sits at
+//   (pos / 4) * 400 + r * 40 + (pos % 4) * 10 + c,
+// i.e. rows are 40 elements apart and hold the columns of four positions
+// side by side.  A wave reads one position of an 8x8 window of leaves;
+// with the row stride = 8 mod 32 doubles those 64 elements fall on distinct
+// banks (64 x 4-byte banks, FP64 in half-waves or FP32 in one pass), where
+// a stride of 10 left half the LDS cycles as bank conflicts.
+__device__ __forceinline__ constexpr int leaf_tile_idx(int pos, int r, int c)
+{
+    return (pos >> 2) * 400 + r * 40 + (pos & 3) * 10 + c;
+}
+
 struct LeafArgs {
     const double *q;
     double qscale;
@@ -449,71 +508,63 @@ struct LeafArgs {
 };
 
 template <int P>
-__global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
+__global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
 {
-    __shared__ double sq[64 * 100];
+    __shared__ double sq[6400];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
     const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
     const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
     {
-        // all 25 loads of a thread are issued before any LDS store
-        double v[25];
+        // all 13 loads of a thread are issued before any LDS store
+        double v[13];
 #pragma unroll
-        for (int i = 0; i < 25; ++i) {
-            const int e = tid + 256 * i;
+        for (int i = 0; i < 13; ++i) {
+            const int e = tid + 512 * i;
             const int yy = e / 80, xx = e - yy * 80;
             const int gx = X0 + xx, gy = Y0 + yy;
-            v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+            v[i] = (e < 6400 && gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < 25; ++i) {
-            const int e = tid + 256 * i;
+        for (int i = 0; i < 13; ++i) {
+            const int e = tid + 512 * i;
             const int yy = e / 80, xx = e - yy * 80;
-            sq[((yy & 7) * 8 + (xx & 7)) * 100 + (yy >> 3) * 10 + (xx >> 3)] = v[i];
+            if (e < 6400) sq[leaf_tile_idx((yy & 7) * 8 + (xx & 7), yy >> 3, xx >> 3)] = v[i];
         }
     }
     __syncthreads();
     const int lx = lane & 7, ly = lane >> 3;
     const int gLx = TX0 + lx, gLy = TY0 + ly;
     const bool active = gLx < nl && gLy < nl;
-    const int ty0 = 2 * wave;
-    const int cleaf = (ly + 1) * 10 + (lx + 1);
-    double acc[16];
+    const int ty = wave;
+    const int cleaf = leaf_tile_idx(0, ly + 1, lx + 1);
+    double acc[8];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
     const double *__restrict__ kt = a.ktab;
     for (int oy = -1; oy <= 1; ++oy) {
         for (int sy = 0; sy < 8; ++sy) {
-            const int dy0 = 8 * oy + sy - ty0;  // row ty0 sees dy0, row ty0+1 sees dy0-1
-            const double *T0 = kt + (dy0 + 15) * 31 + 8;
-            const double *T1 = kt + (dy0 + 14) * 31 + 8;
+            const double *T0 = kt + (8 * oy + sy - ty + 15) * 31 + 8;
 #pragma unroll
             for (int ox = -1; ox <= 1; ++ox) {
-                double w0[15], w1[15];
+                double w0[15];
 #pragma unroll
-                for (int c = 0; c < 15; ++c) {
-                    w0[c] = T0[8 * ox + c];
-                    w1[c] = T1[8 * ox + c];
-                }
-                const int sl = cleaf + oy * 10 + ox;
+                for (int c = 0; c < 15; ++c) w0[c] = T0[8 * ox + c];
+                const int sl = cleaf + oy * 40 + ox;
 #pragma unroll
                 for (int sx = 0; sx < 8; ++sx) {
-                    const double v = sq[(sy * 8 + sx) * 100 + sl];
+                    const double v = sq[leaf_tile_idx(sy * 8 + sx, 0, 0) + sl];
 #pragma unroll
-                    for (int tx = 0; tx < 8; ++tx) {
-                        acc[tx] = fma(w0[sx - tx + 7], v, acc[tx]);
-                        acc[8 + tx] = fma(w1[sx - tx + 7], v, acc[8 + tx]);
-                    }
+                    for (int tx = 0; tx < 8; ++tx) acc[tx] = fma(w0[sx - tx + 7], v, acc[tx]);
                 }
             }
         }
     }
     if (!active) return;
-    double far[16];
+    double far[8];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) far[t] = 0.0;
+    for (int t = 0; t < 8; ++t) far[t] = 0.0;
     if (a.far) {
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
         const double2 *Ll = a.Lt + a.lv.off[a.L];
@@ -521,8 +572,8 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
 #pragma unroll
         for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const double2 *tp = a.l2p + ((ty0 + (t >> 3)) * 8 + (t & 7)) * P;
+        for (int t = 0; t < 8; ++t) {
+            const double2 *tp = a.l2p + (ty * 8 + t) * P;
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < P; ++k) s = fma(Lc[k].x, tp[k].x, fma(-Lc[k].y, tp[k].y, s));
@@ -530,11 +581,9 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
         }
     }
     const double qs = a.qscale;
+    double *ur = a.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int gy = gLy * 8 + ty0 + (t >> 3), gx = gLx * 8 + (t & 7);
-        a.u[(size_t)gy * n + gx] = -(fma(qs, acc[t], far[t])) * kInv2Pi;
-    }
+    for (int t = 0; t < 8; ++t) ur[t] = -(fma(qs, acc[t], far[t])) * kInv2Pi;
 }
 
 // FP32 variant of the leaf stage (precision variant of the preconditioner):
@@ -545,7 +594,7 @@ __global__ __launch_bounds__(256) void k_leaf_grid(LeafArgs a)
 template <int P>
 __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__restrict__ kt32)
 {
-    __shared__ float sq[64 * 100];
+    __shared__ float sq[6400];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
@@ -564,7 +613,7 @@ __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__
         for (int i = 0; i < 25; ++i) {
             const int e = tid + 256 * i;
             const int yy = e / 80, xx = e - yy * 80;
-            sq[((yy & 7) * 8 + (xx & 7)) * 100 + (yy >> 3) * 10 + (xx >> 3)] = v[i];
+            sq[leaf_tile_idx((yy & 7) * 8 + (xx & 7), yy >> 3, xx >> 3)] = v[i];
         }
     }
     __syncthreads();
@@ -572,7 +621,7 @@ __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__
     const int gLx = TX0 + lx, gLy = TY0 + ly;
     const bool active = gLx < nl && gLy < nl;
     const int ty0 = 2 * wave;
-    const int cleaf = (ly + 1) * 10 + (lx + 1);
+    const int cleaf = leaf_tile_idx(0, ly + 1, lx + 1);
     double acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[t] = 0.0;
@@ -592,10 +641,10 @@ __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__
                     w0[c] = T0[8 * ox + c];
                     w1[c] = T1[8 * ox + c];
                 }
-                const int sl = cleaf + oy * 10 + ox;
+                const int sl = cleaf + oy * 40 + ox;
 #pragma unroll
                 for (int sx = 0; sx < 8; ++sx) {
-                    const float v = sq[(sy * 8 + sx) * 100 + sl];
+                    const float v = sq[leaf_tile_idx(sy * 8 + sx, 0, 0) + sl];
 #pragma unroll
                     for (int tx = 0; tx < 8; ++tx) {
                         pacc[tx] = fmaf(w0[sx - tx + 7], v, pacc[tx]);
@@ -746,7 +795,11 @@ __global__ __launch_bounds__(256) void k_m2m_up_ring(const double *__restrict__ 
     tile_of_block(blockIdx.x, nt, 1, tx, ty);
     const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
     const int64_t ncell = (int64_t)nl * nl;
-    for (int e = threadIdx.x; e < 4 * P * P; e += 256) sA[e] = A[e];
+    {
+        double2 va[rounds256(4 * P * P)];
+        fetch(va, 4 * P * P, [&](int t) { return A[t]; });
+        put(va, 4 * P * P, [&](int t, double2 x) { sA[t] = x; });
+    }
     for (int c = threadIdx.x; c < cnt; c += 256) {
         const int lx = x0 + c % tw, ly = y0 + c / tw;
         double2 m[P];
@@ -885,17 +938,19 @@ __global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a, const double2 *__
     const double2 *sL;
     if (chain) {
         const int r = a.L - 3, nr = 1 << r;
-        if (threadIdx.x < P)
-            buf0[threadIdx.x] = a.Lt[a.lv.off[r] + (int64_t)threadIdx.x * nr * nr +
-                                     (int64_t)blockIdx.y * nr + blockIdx.x];
-        sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1);
+        sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1,
+                            a.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x,
+                            (int64_t)nr * nr, nullptr);
     } else {
         const int64_t ncell = (int64_t)nl * nl;
         const double2 *Ll = a.Lt + a.lv.off[a.L];
-        for (int t = threadIdx.x; t < P * cnt; t += 256) {
-            const int k = t / cnt, c = t - k * cnt;
-            buf0[t] = Ll[k * ncell + (int64_t)(ly0 + c / tw) * nl + lx0 + c % tw];
-        }
+        const int ltw = __builtin_ctz(tw);
+        double2 v[rounds256(P * 64)];
+        fetch(v, P * cnt, [&](int t) {
+            const int k = t >> (2 * ltw), c = t & (cnt - 1);
+            return Ll[k * ncell + (int64_t)(ly0 + (c >> ltw)) * nl + lx0 + (c & (tw - 1))];
+        });
+        put(v, P * cnt, [&](int t, double2 x) { buf0[t] = x; });
         __syncthreads();
         sL = buf0;
     }
@@ -1072,10 +1127,11 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
-        if (pl->prec == FMM_FP32)
+        if (pl->prec == FMM_FP32) {
             hipLaunchKernelGGL(k_leaf_grid32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32);
-        else
-            hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(512), 0, s, a);
+        }
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);

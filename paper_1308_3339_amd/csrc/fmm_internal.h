@@ -77,6 +77,7 @@ struct fmm_plan {
     int nl = 1;           // leaves per side, 2^L
     int p = 10;
     int prec = FMM_FP64;  // FMM_FP32: P2P and M2L in FP32
+    int ncu = 256;        // compute units of the plan's device
     int bem = 1;
     double h = 0.0;       // GRID mesh width
     double self_eps = 0.0;
