@@ -972,9 +972,23 @@ __global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a, const double2 *__
 }
 
 // Pass 2 near field: u += -(1/2pi) sum over the ring nodes attached to the
-// 3x3 leaves around the target's leaf.  Only targets within two leaves of
-// the boundary have such neighbours: one thread per point of that band
-// (every point when n <= 32).
+// 3x3 leaves around the target's leaf.  Ring node k of a side attaches to
+// the boundary leaf it borders, so for each side the sum is a window of at
+// most 24 consecutive nodes (the three leaves along that side) with a kernel
+// value from the lattice table, and only targets within two leaves of a
+// side see it.  One thread per point of the 16-deep band (every point when
+// n <= 32).
+__device__ __forceinline__ double side_window(const double *__restrict__ rqs,
+                                              const double *__restrict__ trow, int k0, int k1,
+                                              int c, int sgn)
+{
+    // sum_{k0 <= k < k1} rqs[k] * trow[|c - sgn k|]
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) acc = fma(rqs[k], trow[abs(c - sgn * k)], acc);
+    return acc;
+}
+
 __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
                                                     const double *__restrict__ rq,
                                                     const double *__restrict__ rtab, int n, int nl)
@@ -1004,29 +1018,18 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
         }
     }
     const int lx = gx >> 3, ly = gy >> 3;
+    // lattice range [a, b) along a side covered by the leaves l-1..l+1
+    const int ax = 8 * max(lx - 1, 0), bx = 8 * min(lx + 1, nl - 1) + 8;
+    const int ay = 8 * max(ly - 1, 0), by = 8 * min(ly + 1, nl - 1) + 8;
     double near = 0.0;
-    for (int b = -1; b <= 1; ++b)
-        for (int c = -1; c <= 1; ++c) {
-            const int qx = lx + c, qy = ly + b;
-            if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
-            if (!(qx == 0 || qy == 0 || qx == nl - 1 || qy == nl - 1)) continue;
-            int sd[4], k0[4], runs, len;
-            if (nl == 1) {
-                for (int r = 0; r < 4; ++r) { sd[r] = r; k0[r] = 0; }
-                runs = 4;
-                len = n;
-            } else {
-                runs = attached_runs(qx, qy, n, nl, sd, k0);
-                len = 8;
-            }
-            for (int r = 0; r < runs; ++r)
-                for (int j = 0; j < len; ++j) {
-                    int Ix, Iy;
-                    side_node(sd[r], k0[r] + j, n, Ix, Iy);
-                    const int dx = abs(gx + 1 - Ix), dy = abs(gy + 1 - Iy);
-                    near = fma(rq[sd[r] * n + k0[r] + j], rtab[dy * 17 + dx], near);
-                }
-        }
+    if (ly <= 1)        // bottom: node k at (k+1, 0)
+        near += side_window(rq, rtab + (gy + 1) * 17, ax, bx, gx, 1);
+    if (lx >= nl - 2)   // right: node k at (n+1, k+1)
+        near += side_window(rq + n, rtab + (n - gx) * 17, ay, by, gy, 1);
+    if (ly >= nl - 2)   // top: node k at (n-k, n+1); Ix-1 = n-1-k in [ax, bx)
+        near += side_window(rq + 2 * n, rtab + (n - gy) * 17, n - bx, n - ax, gx - n + 1, -1);
+    if (lx <= 1)        // left: node k at (0, n-k); Iy-1 = n-1-k in [ay, by)
+        near += side_window(rq + 3 * n, rtab + (gx + 1) * 17, n - by, n - ay, gy - n + 1, -1);
     u[(size_t)gy * n + gx] += -near * kInv2Pi;
 }
 
