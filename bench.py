@@ -37,8 +37,8 @@ def log(*a):
 def leaf_kernel_flops(n, p):
     """Algorithmic flops of one k_leaf_grid launch on an n x n grid: every
     near-field pair (target, source in the 3x3 leaves) is one multiply-add
-    (2 flops); every target evaluates the real part of a p-term local
-    expansion (2 multiply-adds per coefficient, 4p flops)."""
+    (2 flops); every source point adds to the p complex coefficients of its
+    leaf's multipole expansion (2 multiply-adds per coefficient, 4p flops)."""
     nl = n // 8
     pairs = 4096 * (3 * nl - 2) ** 2
     return 2.0 * pairs + 4.0 * p * n * n

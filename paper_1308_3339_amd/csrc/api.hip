@@ -406,7 +406,7 @@ int fmm_apply(fmm_plan *pl, const double *q, double *u, int nrhs, void *stream)
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (pl->kind == FMM_GRID) ? (size_t)pl->n * pl->n : (size_t)pl->n;
     for (int r = 0; r < nrhs; ++r) {
-        int st = (pl->kind == FMM_GRID) ? grid_volume_fmm(pl, q + r * N, 1.0, u + r * N, nullptr, s)
+        int st = (pl->kind == FMM_GRID) ? grid_volume_fmm(pl, q + r * N, 1.0, u + r * N, nullptr, false, s)
                                         : points_fmm(pl, q + r * N, u + r * N, s);
         if (st != FMM_OK) return st;
     }

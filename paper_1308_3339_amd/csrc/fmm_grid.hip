@@ -396,7 +396,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 // same round trip as the tables and M2L sums, and also stored to top_out when
 // that is not null.
 template <int P>
-__device__ __forceinline__ const double2 *down_levels(const double2 *__restrict__ Lm,
+__device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
                                                       double2 *__restrict__ Lt,
                                                       const double2 *__restrict__ B,
                                                       const LevelInfo &lv, int r, int m, int rx,
@@ -430,7 +430,7 @@ __device__ __forceinline__ const double2 *down_levels(const double2 *__restrict_
         put(v3, m >= 3 ? 64 * P : 0, [&](int t, double2 x) { sm2l[(t >> 6) * 84 + 20 + (t & 63)] = x; });
     }
     __syncthreads();
-    const double2 *prev = buf0;
+    double2 *prev = buf0;
     int pw = 1;
     for (int st = 1; st <= m; ++st) {
         const int l = r + st, tw = 1 << st, nc = 1 << l, cnt = tw * tw;
@@ -474,10 +474,13 @@ __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
 }
 
 // ---------------------------------------------------------------------------
-// Fused leaf stage for grid plans:
-//   u = -(1/2pi) [ qscale * sum_{3x3 leaves} q_j T(d_ij) + Re sum_k L~_k tau^k ]
+// Leaf stage for grid plans, the first kernel of an application:
+//   u = -(1/2pi) qscale * sum_{3x3 leaves} q_j T(d_ij)     (P2P, Sec. 5.1)
+//   M~_k(leaf) = qscale * sum_{j in leaf} W[k][j] q_j       (P2M, Sec. 5.3)
 // T(d) = log(h|d|) for lattice offsets d != 0 and log(eps h) for d = 0 (the
-// regularised self term).  Block = 8x8 leaves; lane = leaf; wave w of 8
+// regularised self term); W[0][j] = 1, W[k][j] = -tau_j^k / k with tau_j the
+// point's offset from the leaf centre in leaf widths.  Both read the q tile
+// the block stages once.  The far field is added later by k_far_l2p.  Block = 8x8 leaves; lane = leaf; wave w of 8
 // serves target row w of every leaf (8 targets per lane).  For a fixed
 // source position all lanes need the same T values, so T rows are read with
 // scalar loads and broadcast, and the q tile sits in LDS as [pos][leaf].
@@ -503,6 +506,8 @@ struct LeafArgs {
     const double *ktab;   // [31][31]
     const double *rtab;   // [17][17]
     const double2 *l2p;   // [64][P]
+    double2 *M;           // leaf multipoles written by the FP64 leaf kernel (null: no P2M)
+    const double2 *p2m;   // [P][64]
     LevelInfo lv;
     int n, nl, L, far;
 };
@@ -561,36 +566,35 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
             }
         }
     }
-    if (!active) return;
-    double far[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) far[t] = 0.0;
-    if (a.far) {
+    if (a.M) {
+        // P2M: wave w computes coefficients w, w + 8, ... of the 64 leaves
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        const double2 *Ll = a.Lt + a.lv.off[a.L];
-        double2 Lc[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const double2 *tp = a.l2p + (ty * 8 + t) * P;
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) s = fma(Lc[k].x, tp[k].x, fma(-Lc[k].y, tp[k].y, s));
-            far[t] = s;
+        double2 *Ml = a.M + a.lv.off[a.L];
+        for (int k = wave; k < P; k += 8) {
+            const double2 *__restrict__ Wk = a.p2m + k * 64;
+            double mx = 0.0, my = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < 64; ++j) {
+                const double v = sq[leaf_tile_idx(j, 0, 0) + cleaf];
+                const double2 w = Wk[j];
+                mx = fma(w.x, v, mx);
+                my = fma(w.y, v, my);
+            }
+            if (active) Ml[k * ncell + cell] = make_double2(mx * a.qscale, my * a.qscale);
         }
     }
-    const double qs = a.qscale;
+    if (!active) return;
+    const double qs = -a.qscale * kInv2Pi;
     double *ur = a.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) ur[t] = -(fma(qs, acc[t], far[t])) * kInv2Pi;
+    for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
 }
 
 // FP32 variant of the leaf stage (precision variant of the preconditioner):
 // the q tile and the kernel table are FP32, every source row of the 3x3
 // leaves (24 sources) is summed in FP32 and folded into an FP64 accumulator,
-// so the FP32 rounding error stays at the level of one 24-term sum.  L2P and
-// the output are FP64.
+// so the FP32 rounding error stays at the level of one 24-term sum.  The
+// output is FP64; P2M for FP32 plans is done by k_p2m_up from the FP64 q.
 template <int P>
 __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__restrict__ kt32)
 {
@@ -657,29 +661,11 @@ __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__
         }
     }
     if (!active) return;
-    double far[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) far[t] = 0.0;
-    if (a.far) {
-        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        const double2 *Ll = a.Lt + a.lv.off[a.L];
-        double2 Lc[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const double2 *tp = a.l2p + ((ty0 + (t >> 3)) * 8 + (t & 7)) * P;
-            double sacc = 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) sacc = fma(Lc[k].x, tp[k].x, fma(-Lc[k].y, tp[k].y, sacc));
-            far[t] = sacc;
-        }
-    }
-    const double qs = a.qscale;
+    const double qs = -a.qscale * kInv2Pi;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int gy = gLy * 8 + ty0 + (t >> 3), gx = gLx * 8 + (t & 7);
-        a.u[(size_t)gy * n + gx] = -(fma(qs, acc[t], far[t])) * kInv2Pi;
+        a.u[(size_t)gy * n + gx] = qs * acc[t];
     }
 }
 
@@ -920,37 +906,62 @@ __global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items
     }
 }
 
-// Pass 2 far field at the interior nodes: u += -(1/2pi) Re sum_k L~_k tau^k.
-// Block = a tile of up to 8x8 leaves.  With chain = 1 the tile is one cell
-// of level L-3 and the block first builds the local expansions of levels
-// L-2..L in LDS from that cell's expansion (Lt) and the M2L sums (Lm);
-// otherwise the leaf expansions are read from Lt.  Threads walk rows of the
-// tile, so the read-modify-write of u is coalesced.
+// Far field at every grid point, the last stage of an application:
+//   u += -(1/2pi) Re sum_k (L~ring_k + L~vol_k) tau^k   (L2P, Sec. 5.3)
+// over the leaves of an 8x8 tile.  The boundary-source expansions L~ring
+// come from one of: none (a.Lt null), the leaf level of a.Lt, or (chain)
+// the three levels below a.Lt's level L-3 built in LDS from the M2L sums Lm.
+// The volume expansions Lvol (leaf level), when given, are added in LDS, so
+// the preconditioner's two passes share one sweep over u.
 template <int P>
-__global__ __launch_bounds__(256) void k_pass2_far(LeafArgs a, const double2 *__restrict__ Lm,
-                                                   const double2 *__restrict__ B, int chain)
+__global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__restrict__ Lm,
+                                                 const double2 *__restrict__ B, int chain,
+                                                 const double2 *__restrict__ Lvol)
 {
     __shared__ double2 sB[4 * P * P];
     __shared__ double2 sm2l[P * 84];
     __shared__ double2 buf0[P * 64], buf1[P * 64];
     const int n = a.n, nl = a.nl, tw = nl < 8 ? nl : 8, pw = tw * 8;
     const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw, cnt = tw * tw;
-    const double2 *sL;
+    const int ltw = __builtin_ctz(tw);
+    const int64_t ncell = (int64_t)nl * nl;
+    // coefficient k of tile leaf c = t & (cnt - 1), k = t / cnt, at the leaf level
+    auto leaf_coef = [&](const double2 *__restrict__ base, int t) {
+        const int k = t >> (2 * ltw), c = t & (cnt - 1);
+        return base[a.lv.off[a.L] + k * ncell + (int64_t)(ly0 + (c >> ltw)) * nl + lx0 +
+                    (c & (tw - 1))];
+    };
+    double2 vv[rounds256(P * 64)];
+    if (Lvol) fetch(vv, P * cnt, [&](int t) { return leaf_coef(Lvol, t); });
+    double2 *sL;
     if (chain) {
         const int r = a.L - 3, nr = 1 << r;
         sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1,
                             a.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x,
                             (int64_t)nr * nr, nullptr);
+        if (Lvol) {
+            put(vv, P * cnt, [&](int t, double2 x) {
+                sL[t].x += x.x;
+                sL[t].y += x.y;
+            });
+            __syncthreads();
+        }
     } else {
-        const int64_t ncell = (int64_t)nl * nl;
-        const double2 *Ll = a.Lt + a.lv.off[a.L];
-        const int ltw = __builtin_ctz(tw);
-        double2 v[rounds256(P * 64)];
-        fetch(v, P * cnt, [&](int t) {
-            const int k = t >> (2 * ltw), c = t & (cnt - 1);
-            return Ll[k * ncell + (int64_t)(ly0 + (c >> ltw)) * nl + lx0 + (c & (tw - 1))];
-        });
-        put(v, P * cnt, [&](int t, double2 x) { buf0[t] = x; });
+        constexpr int R = rounds256(P * 64);
+        double2 v[R];
+        if (a.Lt) fetch(v, P * cnt, [&](int t) { return leaf_coef(a.Lt, t); });
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = threadIdx.x + 256 * r;
+            if (t < P * cnt) {
+                double2 y = a.Lt ? v[r] : make_double2(0.0, 0.0);
+                if (Lvol) {
+                    y.x += vv[r].x;
+                    y.y += vv[r].y;
+                }
+                buf0[t] = y;
+            }
+        }
         __syncthreads();
         sL = buf0;
     }
@@ -1108,6 +1119,8 @@ static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *
     a.ktab = pl->tab.ktab;
     a.rtab = pl->tab.rtab;
     a.l2p = pl->tab.l2p;
+    a.M = nullptr;
+    a.p2m = pl->tab.p2m;
     a.lv = pl->lv;
     a.n = (int)pl->n;
     a.nl = pl->nl;
@@ -1118,35 +1131,48 @@ static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *
 
 template <int P>
 static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, double *u,
-                             double *ring_out, hipStream_t s)
+                             double *ring_out, bool defer_l2p, hipStream_t s)
 {
     const int nl = pl->nl;
     const bool far = pl->L >= 2;
-    if (far) {
-        run_upward<P>(pl, q, qscale, pl->ws.M, s);
-        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
-    }
-    const LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far);
+    const bool fp32 = pl->prec == FMM_FP32;
+    // FP32 plans stage q in FP32 for the near field, so their P2M is a pass of its own
+    if (far && fp32) run_upward<P>(pl, q, qscale, pl->ws.M, s);
+    LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far);
+    if (far && !fp32) a.M = pl->ws.M;
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
-        if (pl->prec == FMM_FP32) {
+        if (fp32)
             hipLaunchKernelGGL(k_leaf_grid32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32);
-        } else {
+        else
             hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(512), 0, s, a);
+    }
+    if (far) {
+        if (!fp32) {
+            StageTimer t(pl, FMM_STAGE_M2M, s);
+            run_m2m_from<P>(pl, pl->ws.M, pl->L, 0, s);
         }
+        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
         hipLaunchKernelGGL(k_ring_targets<P>, dim3((4 * pl->n + 3) / 4), dim3(256), 0, s, a,
                            ring_out);
     }
+    if (far && !defer_l2p) {
+        StageTimer t(pl, FMM_STAGE_L2L, s);
+        const int tw = std::min(nl, 8);
+        LeafArgs b = leaf_args(pl, nullptr, 1.0, u, nullptr, far);
+        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, b, nullptr,
+                           nullptr, 0, pl->ws.Lt);
+    }
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }
 
 template <int P>
-static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
+static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hipStream_t s)
 {
     const int L = pl->L, nl = pl->nl;
     const bool far = L >= 2;
@@ -1168,8 +1194,8 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
             hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, pl->ws.Lm2,
                                pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.top);
         const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far);
-        hipLaunchKernelGGL(k_pass2_far<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
-                           pl->tab.l2l, chain ? 1 : 0);
+        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
+                           pl->tab.l2l, chain ? 1 : 0, with_volume ? pl->ws.Lt : nullptr);
     }
     const int n = (int)pl->n;
     const int64_t nband = n <= 32 ? (int64_t)n * n : (int64_t)4 * 16 * n - 4 * 16 * 16;
@@ -1180,14 +1206,14 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, hipStream_t s)
 }
 
 int grid_volume_fmm(fmm_plan *pl, const double *q, double qscale, double *u, double *ring_out,
-                    hipStream_t s)
+                    bool defer_l2p, hipStream_t s)
 {
-    FMM_DISPATCH_P(pl->p, grid_volume_fmm_p, pl, q, qscale, u, ring_out, s);
+    FMM_DISPATCH_P(pl->p, grid_volume_fmm_p, pl, q, qscale, u, ring_out, defer_l2p, s);
 }
 
-int grid_ring_source_fmm(fmm_plan *pl, double *u, hipStream_t s)
+int grid_ring_source_fmm(fmm_plan *pl, double *u, bool with_volume, hipStream_t s)
 {
-    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, s);
+    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, s);
 }
 
 // level-generic stages reused by point-cloud plans

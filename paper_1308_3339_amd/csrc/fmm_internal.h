@@ -164,11 +164,13 @@ struct StageTimer {
 
 // ---- FMM stages (fmm_grid.hip / fmm_points.hip) ----
 // q -> u for grid plans: u = -(1/2pi) [ qscale * near(q) + far ], optionally
-// also the ring potential.  `accumulate` adds into u instead of storing.
+// also the ring potential.  With defer_l2p the far field is left in the
+// leaf-level local expansions (plan->ws.Lt) for grid_ring_source_fmm to add.
 int grid_volume_fmm(fmm_plan *plan, const double *q, double qscale, double *u,
-                    double *ring_out, hipStream_t s);
-// second pass: ring charges plan->ring_q, add their potential to u
-int grid_ring_source_fmm(fmm_plan *plan, double *u, hipStream_t s);
+                    double *ring_out, bool defer_l2p, hipStream_t s);
+// second pass: ring charges plan->ring_q, add their potential to u (and the
+// deferred far field of the volume pass when with_volume)
+int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, hipStream_t s);
 int m2l_kernel_setup(fmm_plan *plan);
 int points_fmm(fmm_plan *plan, const double *q, double *u, hipStream_t s);
 int points_setup(fmm_plan *plan, const double *dx, const double *dy, hipStream_t s);

@@ -329,7 +329,7 @@ int precond_apply_one(fmm_plan *pl, const double *r, double *z, double *phi_ring
 {
     const double h2 = pl->h * pl->h;
     const bool need_ring = pl->bem || phi_ring;
-    int st = grid_volume_fmm(pl, r, h2, z, need_ring ? pl->phi_ring : nullptr, s);
+    int st = grid_volume_fmm(pl, r, h2, z, need_ring ? pl->phi_ring : nullptr, pl->bem != 0, s);
     if (st != FMM_OK) return st;
     if (phi_ring)
         FMM_HIP(pl, hipMemcpyAsync(phi_ring, pl->phi_ring, 4 * (size_t)pl->n * sizeof(double),
@@ -337,7 +337,7 @@ int precond_apply_one(fmm_plan *pl, const double *r, double *z, double *phi_ring
     if (pl->bem) {
         st = bem_apply(pl, sigma, s);
         if (st != FMM_OK) return st;
-        st = grid_ring_source_fmm(pl, z, s);
+        st = grid_ring_source_fmm(pl, z, true, s);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;
