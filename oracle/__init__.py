@@ -5,3 +5,4 @@ CPU-baseline leg are its only users.  The product package never imports it.
 """
 from .oracle import *  # noqa: F401,F403
 from .oracle import _f64, _ip, _ptr  # noqa: F401  (raw-pointer helpers for tests)
+from . import adjoint  # noqa: F401  (differentiation workload: exact FD solve, bumps, gradients)

@@ -8,6 +8,7 @@ Recipes:
       f(x) = sum_k a_k exp(-|x - c_k|^2 / (2 w_k^2)); draws from
       numpy.random.default_rng(seed): centres (K x 2, U(0,1)), then widths
       (K, U(0.02, 0.1)), then amplitudes (K, U(-1, 1))
+  bump_params(K, seed)   the (cx, cy, w, a) of those bumps
   random_points(N, seed_xy, seed_q)
       points U(0,1)^2 from default_rng(seed_xy) (x then y), charges
       U(-1, 1) from default_rng(seed_q)
@@ -25,6 +26,10 @@ SEED_POINTS_XY = 2
 SEED_POINTS_Q = 3
 SEED_POINTS_TARGETS = 4
 SEED_BUMPS_2048 = 5
+# differentiation workload (1024 x 1024): target source, source, FD coordinates
+SEED_ADJ_TARGET = 6
+SEED_ADJ_SOURCE = 7
+SEED_ADJ_COORDS = 8
 
 
 def grid_nodes(n):
@@ -46,6 +51,15 @@ def manufactured_solution(n):
 
 def ones(n):
     return np.ones(n * n)
+
+
+def bump_params(K=16, seed=SEED_BUMPS_2048):
+    """(cx, cy, w, a) of the K seeded bumps, drawn in the order above."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.0, 1.0, (K, 2))
+    w = rng.uniform(0.02, 0.1, K)
+    a = rng.uniform(-1.0, 1.0, K)
+    return c[:, 0].copy(), c[:, 1].copy(), w, a
 
 
 def gaussian_bumps(n, K=16, seed=SEED_BUMPS_2048):
