@@ -88,6 +88,61 @@ def cpu_baseline(n, p, f, iters):
             "sample_seconds": t}
 
 
+def adjoint_block(fp, inputs, torch, steps, warmup):
+    """Differentiation workload on a 1024 x 1024 grid: L = 0.5 |u - u_t|^2 with
+    u the solve for a 16-bump source (seed 7) and u_t for an 8-bump source
+    (seed 6).  Times one gradient (bump source, forward solve, loss, adjoint
+    solve, bump-parameter gradients) and checks the centre gradients against
+    central differences (h = 1e-6) of the same GPU loss, each difference
+    evaluated as (u+ - u-) . ((u+ + u-)/2 - u_t)."""
+    from paper_1308_3339_amd.autograd import gaussian_bumps, poisson_solve
+    n, tol, h = 1024, 1e-10, 1e-6
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(a).to(dev)
+    tcx, tcy, tw, ta = (T(v) for v in inputs.bump_params(8, seed=inputs.SEED_ADJ_TARGET))
+    cx, cy, w, a = (T(v) for v in inputs.bump_params(16, seed=inputs.SEED_ADJ_SOURCE))
+    plan = fp.fmm_setup(n=n, p=10, bem=1)
+    with torch.no_grad():
+        u_t = poisson_solve(plan, gaussian_bumps(plan, tcx, tcy, tw, ta), tol=tol)
+
+    def gradient():
+        pcx, pcy = cx.clone().requires_grad_(True), cy.clone().requires_grad_(True)
+        u = poisson_solve(plan, gaussian_bumps(plan, pcx, pcy, w, a), tol=tol)
+        (0.5 * ((u - u_t) ** 2).sum()).backward()
+        return pcx.grad, pcy.grad
+
+    for _ in range(warmup):
+        gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gx, gy = gradient()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+
+    def u_of(cxv, cyv):
+        with torch.no_grad():
+            return poisson_solve(plan, gaussian_bumps(plan, cxv, cyv, w, a), tol=tol)
+
+    fd = torch.zeros(2, 16, dtype=torch.float64, device=dev)
+    for k in range(16):
+        for c, (base, other) in enumerate(((cx, cy), (cy, cx))):
+            bp, bm = base.clone(), base.clone()
+            bp[k] += h
+            bm[k] -= h
+            up, um = (u_of(bp, other), u_of(bm, other)) if c == 0 else (u_of(other, bp), u_of(other, bm))
+            fd[c, k] = torch.dot(up - um, 0.5 * (up + um) - u_t) / (2 * h)
+    g = torch.stack([gx, gy])
+    err = float((g - fd).abs().max() / g.abs().max())
+    plan.close()
+    return {"workload": "1024x1024 grid, L = 0.5|u - u_t|^2, u: 16-bump source (seed %d), "
+                        "u_t: 8-bump source (seed %d), solves to %.0e, p=10"
+                        % (inputs.SEED_ADJ_SOURCE, inputs.SEED_ADJ_TARGET, tol),
+            "gradients_per_s": round(1.0 / dt, 3), "ms_per_gradient": round(1000.0 * dt, 3),
+            "centre_grad_rel_err_vs_central_fd": err,
+            "fd": "central differences h=1e-6 of the GPU loss over the 32 centre coordinates"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +301,10 @@ def main():
                "iters": info32["iters"], "true_rel_res": rel32,
                "precond_max_rel_diff_vs_fp64": perr, "stages_ms_per_solve": stages32}
     log("fp32 variant %.2f solves/s" % variant["solves_per_s"])
+    log("adjoint (1024^2 gradients)")
+    adjoint = adjoint_block(fp, inputs, torch, args.steps, args.warmup)
+    log("adjoint %.2f gradients/s, fd err %.2e" % (adjoint["gradients_per_s"],
+                                                   adjoint["centre_grad_rel_err_vs_central_fd"]))
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -282,6 +341,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variant_fp32": variant,
+        "adjoint": adjoint,
     }
     plan.close()
     print(json.dumps(res), flush=True)

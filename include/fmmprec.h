@@ -166,11 +166,43 @@ int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void
 int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                         const gmres_params *prm, gmres_result *res, void *stream);
 
+/* Adjoint solve for gradients through precond_gmres_solve: lambda solves
+ * A^T lambda = g (GRID plans only).  A is the symmetric 5-point matrix of
+ * Sec. 2.1, and b depends on f through the identity, so for a loss L(u)
+ * with u = A^{-1} b(f): dL/df = lambda with g = dL/du.  The call runs the
+ * same right-preconditioned FGMRES as precond_gmres_solve on the right-hand
+ * side g (zero ring data); lambda is the initial guess on entry and the
+ * result on exit.  prm, res: as for precond_gmres_solve. */
+int precond_gmres_solve_adjoint(fmm_plan *plan, const double *g, double *lambda,
+                                const gmres_params *prm, gmres_result *res, void *stream);
+
+/* Gaussian-bump source on the plan's grid (GRID plans only; the source model
+ * of the differentiation workload, not part of the paper):
+ *   f_i = sum_{k < K} a_k exp(-|x_i - c_k|^2 / (2 w_k^2)),
+ * x_i the interior nodes ((i+1)h, (j+1)h).  cx, cy, w, a: K device doubles
+ * (1 <= K <= 256, w_k > 0 is the caller's to ensure); f: n*n device doubles. */
+int fmm_bumps_eval(fmm_plan *plan, int32_t K, const double *cx, const double *cy,
+                   const double *w, const double *a, double *f, void *stream);
+
+/* Gradients of sum_i g_i f_i (f as in fmm_bumps_eval) with respect to the
+ * bump parameters, given g = dL/df (n*n device doubles):
+ *   gcx_k = a_k / w_k^2 sum_i g_i e_ik (x_i - cx_k), gcy_k likewise,
+ *   gw_k  = a_k / w_k^3 sum_i g_i e_ik |x_i - c_k|^2,  ga_k = sum_i g_i e_ik,
+ * e_ik = exp(-|x_i - c_k|^2 / (2 w_k^2)).  Outputs: K device doubles each
+ * (any of them may be NULL).  Sums run in a fixed order (bitwise
+ * reproducible).  The plan keeps a small reduction workspace. */
+int fmm_bumps_grad(fmm_plan *plan, int32_t K, const double *cx, const double *cy,
+                   const double *w, const double *a, const double *g, double *gcx,
+                   double *gcy, double *gw, double *ga, void *stream);
+
 /* Per-stage device timing (tracing support).  Stages of an apply or solve:
- * P2M, M2M, M2L, L2L (Sec. 5.3 items 1-4), LEAF (fused L2P + P2P of the
- * volume pass, items 5 and Sec. 5.1), RING (potential at the ring nodes),
- * BEM (boundary solve, Sec. 4.3), PASS2 (boundary-source FMM pass), STENCIL
- * (A v and residuals), ARNOLDI (orthogonalisation and updates). */
+ * P2M (a pass of its own in FMM_FP32 plans), M2M, M2L, L2L (Sec. 5.3 items
+ * 1-4; L2L also covers the far-field L2P sweep when no boundary pass
+ * follows), LEAF (P2P near field of Sec. 5.1 and, in FMM_FP64 plans, the
+ * P2M of item 1), RING (potential at the ring nodes), BEM (boundary solve,
+ * Sec. 4.3), PASS2 (boundary-source FMM pass and the far-field L2P sweep of
+ * both passes), STENCIL (A v and residuals), ARNOLDI (orthogonalisation and
+ * updates). */
 enum {
     FMM_STAGE_P2M = 0, FMM_STAGE_M2M, FMM_STAGE_M2L, FMM_STAGE_L2L, FMM_STAGE_LEAF,
     FMM_STAGE_RING, FMM_STAGE_BEM, FMM_STAGE_PASS2, FMM_STAGE_STENCIL, FMM_STAGE_ARNOLDI,

@@ -19,7 +19,7 @@ FMM_FP64, FMM_FP32 = 0, 1
 exported_symbols = (
     "fmm_setup", "fmm_apply", "fmm_precond_apply", "fmm_precond_stages", "fmm_stencil_apply",
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
-    "fmm_profile_read",
+    "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -86,6 +86,13 @@ def load_library():
     L.precond_gmres_solve.argtypes = [vp, dp, dp, dp, ctypes.POINTER(gmres_params),
                                       ctypes.POINTER(gmres_result), vp]
     L.precond_gmres_solve.restype = i32
+    L.precond_gmres_solve_adjoint.argtypes = [vp, dp, dp, ctypes.POINTER(gmres_params),
+                                              ctypes.POINTER(gmres_result), vp]
+    L.precond_gmres_solve_adjoint.restype = i32
+    L.fmm_bumps_eval.argtypes = [vp, i32, dp, dp, dp, dp, dp, vp]
+    L.fmm_bumps_eval.restype = i32
+    L.fmm_bumps_grad.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
+    L.fmm_bumps_grad.restype = i32
     L.fmm_destroy.argtypes = [vp]
     L.fmm_destroy.restype = i32
     L.fmm_last_error.argtypes = [vp]
@@ -198,6 +205,45 @@ def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, str
             "true_rel_res": res.true_rel_res}
 
 
+def precond_gmres_solve_adjoint(plan, g, lam, tol=1e-8, restart=30, maxit=600, stream=None):
+    """lambda = A^{-T} g (A^T = A); lam holds the initial guess on entry."""
+    N = plan.npts
+    prm = gmres_params(tol, restart, maxit)
+    res = gmres_result()
+    code = load_library().precond_gmres_solve_adjoint(plan._ptr, _dptr(g, "g", N),
+                                                      _dptr(lam, "lam", N), ctypes.byref(prm),
+                                                      ctypes.byref(res), _stream(stream))
+    _check(code, plan._ptr)
+    return {"status": code, "converged": code == FMM_OK, "iters": res.iters,
+            "restarts": res.restarts, "est_rel_res": res.est_rel_res,
+            "true_rel_res": res.true_rel_res}
+
+
+def _bump_args(cx, cy, w, a):
+    K = cx.numel()
+    for t, nm in ((cy, "cy"), (w, "w"), (a, "a")):
+        if t.numel() != K:
+            raise ValueError("%s has %d elements, cx has %d" % (nm, t.numel(), K))
+    return K, [_dptr(t, nm, K) for t, nm in ((cx, "cx"), (cy, "cy"), (w, "w"), (a, "a"))]
+
+
+def fmm_bumps_eval(plan, cx, cy, w, a, f, stream=None):
+    """f_i = sum_k a_k exp(-|x_i - c_k|^2 / (2 w_k^2)) on the plan's grid."""
+    K, ptrs = _bump_args(cx, cy, w, a)
+    code = load_library().fmm_bumps_eval(plan._ptr, K, *ptrs, _dptr(f, "f", plan.npts),
+                                         _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def fmm_bumps_grad(plan, cx, cy, w, a, g, gcx=None, gcy=None, gw=None, ga=None, stream=None):
+    """Gradients of sum_i g_i f_i with respect to the bump parameters."""
+    K, ptrs = _bump_args(cx, cy, w, a)
+    outs = [_dptr(t, nm, K) for t, nm in ((gcx, "gcx"), (gcy, "gcy"), (gw, "gw"), (ga, "ga"))]
+    code = load_library().fmm_bumps_grad(plan._ptr, K, *ptrs, _dptr(g, "g", plan.npts), *outs,
+                                         _stream(stream))
+    return _check(code, plan._ptr)
+
+
 def fmm_profile(plan, stages=()):
     """Enable hipEvent timing of the named stages (empty: disable)."""
     mask = 0
@@ -234,6 +280,9 @@ class Plan:
     precond_stages = fmm_precond_stages
     stencil_apply = fmm_stencil_apply
     solve = precond_gmres_solve
+    solve_adjoint = precond_gmres_solve_adjoint
+    bumps_eval = fmm_bumps_eval
+    bumps_grad = fmm_bumps_grad
     profile = fmm_profile
     profile_read = fmm_profile_read
 

@@ -241,7 +241,7 @@ static void release(fmm_plan *pl)
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->ring_cells, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
                     pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
-                    pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal};
+                    pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal, pl->bump_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (pl->hpin) (void)hipHostFree(pl->hpin);
@@ -463,6 +463,34 @@ int precond_gmres_solve(fmm_plan *pl, const double *f, const double *g, double *
     if (q.restart < 1 || q.restart > 32) return fail(pl, FMM_ERR_ARG, "restart must be in [1, 32]");
     if (q.maxit < 1) return fail(pl, FMM_ERR_ARG, "maxit must be >= 1");
     return gmres_solve(pl, f, g, u, &q, res, (hipStream_t)stream);
+}
+
+int precond_gmres_solve_adjoint(fmm_plan *pl, const double *g, double *lambda,
+                                const gmres_params *prm, gmres_result *res, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (!g || !lambda) return fail(pl, FMM_ERR_ARG, "g or lambda is NULL");
+    // A^T = A: the adjoint system is the forward one with zero ring data
+    return precond_gmres_solve(pl, g, nullptr, lambda, prm, res, stream);
+}
+
+int fmm_bumps_eval(fmm_plan *pl, int32_t K, const double *cx, const double *cy, const double *w,
+                   const double *a, double *f, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "bumps need a GRID plan");
+    if (!cx || !cy || !w || !a || !f) return fail(pl, FMM_ERR_ARG, "NULL bump parameter or output");
+    return bumps_eval(pl, K, cx, cy, w, a, f, (hipStream_t)stream);
+}
+
+int fmm_bumps_grad(fmm_plan *pl, int32_t K, const double *cx, const double *cy, const double *w,
+                   const double *a, const double *g, double *gcx, double *gcy, double *gw,
+                   double *ga, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "bumps need a GRID plan");
+    if (!cx || !cy || !w || !a || !g) return fail(pl, FMM_ERR_ARG, "NULL bump parameter or g");
+    return bumps_grad(pl, K, cx, cy, w, a, g, gcx, gcy, gw, ga, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -117,6 +117,9 @@ struct fmm_plan {
     double *dscal = nullptr;      // small device scalars / coefficient vectors
     double *hpin = nullptr;       // pinned host mirror of dscal
 
+    // bump-gradient reduction partials (allocated on first use)
+    double *bump_part = nullptr;
+
     // stage timing (fmm_profile)
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;          // created on first enable
@@ -173,6 +176,12 @@ int grid_volume_fmm(fmm_plan *plan, const double *q, double qscale, double *u,
 int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, hipStream_t s);
 int m2l_kernel_setup(fmm_plan *plan);
 int points_fmm(fmm_plan *plan, const double *q, double *u, hipStream_t s);
+// Gaussian-bump source model and its parameter gradients (adjoint.hip)
+int bumps_eval(fmm_plan *plan, int K, const double *cx, const double *cy, const double *w,
+               const double *a, double *f, hipStream_t s);
+int bumps_grad(fmm_plan *plan, int K, const double *cx, const double *cy, const double *w,
+               const double *a, const double *g, double *gcx, double *gcy, double *gw,
+               double *ga, hipStream_t s);
 int points_setup(fmm_plan *plan, const double *dx, const double *dy, hipStream_t s);
 
 // ---- boundary correction (bem.hip) ----
