@@ -13,6 +13,8 @@ Recipes:
       points U(0,1)^2 from default_rng(seed_xy) (x then y), charges
       U(-1, 1) from default_rng(seed_q)
   target_subset(N, m, seed)   m distinct indices drawn by default_rng(seed)
+  var_faces(n, mu, mx, my)    face values of a = 1 + mu sin(mx pi X) sin(my pi Y),
+      X = 2x - 1, Y = 2y - 1, for the variable-coefficient problem
 """
 from __future__ import annotations
 
@@ -72,6 +74,26 @@ def gaussian_bumps(n, K=16, seed=SEED_BUMPS_2048):
     for k in range(K):
         f += a[k] * np.exp(-((x - c[k, 0]) ** 2 + (y - c[k, 1]) ** 2) / (2.0 * w[k] ** 2))
     return f
+
+
+def var_coefficient(x, y, mu, mx, my):
+    """a = 1 + mu sin(mx pi X) sin(my pi Y) with X = 2x - 1, Y = 2y - 1 (the
+    coefficient of the variable-coefficient problem, written in the
+    coordinates of the square [-1, 1]^2 and mapped onto the unit square)."""
+    return 1.0 + mu * np.sin(mx * math.pi * (2.0 * x - 1.0)) * np.sin(my * math.pi * (2.0 * y - 1.0))
+
+
+def var_faces(n, mu, mx, my):
+    """Face values of the coefficient for the 5-point flux stencil:
+    ax[j, i] = a((i + 1/2) h, (j + 1) h), i = 0..n (n x (n+1), between nodes
+    i-1 and i in x), ay[j, i] = a((i + 1) h, (j + 1/2) h), j = 0..n
+    ((n+1) x n, between rows j-1 and j); h = 1/(n+1), flattened row-major."""
+    h = 1.0 / (n + 1)
+    xf = (np.arange(n + 1) + 0.5) * h
+    xn = (np.arange(n) + 1.0) * h
+    ax = var_coefficient(xf[None, :], xn[:, None], mu, mx, my)
+    ay = var_coefficient(xn[None, :], xf[:, None], mu, mx, my)
+    return ax.reshape(-1).copy(), ay.reshape(-1).copy()
 
 
 def random_points(N, seed_xy=SEED_POINTS_XY, seed_q=SEED_POINTS_Q):
