@@ -166,6 +166,25 @@ int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void
 int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                         const gmres_params *prm, gmres_result *res, void *stream);
 
+/* Variable-coefficient operator of Sec. 6.4, -div(a grad u), in flux form
+ * on the plan's grid (GRID plans only), zero Dirichlet data:
+ *   h^2 (A v)_ij = ax[j][i+1] (v_ij - v_{i+1,j}) + ax[j][i] (v_ij - v_{i-1,j})
+ *                + ay[j+1][i] (v_ij - v_{i,j+1}) + ay[j][i] (v_ij - v_{i,j-1}),
+ * v = 0 outside the grid.  ax: n x (n+1) face values, row-major, ax[j][i] =
+ * a((i + 1/2) h, (j + 1) h) between nodes i-1 and i of row j; ay: (n+1) x n,
+ * ay[j][i] = a((i + 1) h, (j + 1/2) h) between rows j-1 and j.  Device
+ * arrays, caller-owned; a > 0 is the caller's to ensure. */
+int fmm_stencil_var_apply(fmm_plan *plan, const double *ax, const double *ay, const double *v,
+                          double *w, void *stream);
+
+/* Solves A u = f for the variable-coefficient A above (zero Dirichlet
+ * data) with right-preconditioned FGMRES(restart), preconditioned by the
+ * plan's constant-coefficient FMM-BEM operator: for smooth a the two are
+ * spectrally equivalent (Sec. 6.4).  Arguments, stopping rule and return
+ * codes as for precond_gmres_solve. */
+int precond_gmres_solve_var(fmm_plan *plan, const double *ax, const double *ay, const double *f,
+                            double *u, const gmres_params *prm, gmres_result *res, void *stream);
+
 /* Adjoint solve for gradients through precond_gmres_solve: lambda solves
  * A^T lambda = g (GRID plans only).  A is the symmetric 5-point matrix of
  * Sec. 2.1, and b depends on f through the identity, so for a loss L(u)

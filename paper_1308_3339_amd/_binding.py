@@ -20,6 +20,7 @@ exported_symbols = (
     "fmm_setup", "fmm_apply", "fmm_precond_apply", "fmm_precond_stages", "fmm_stencil_apply",
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
+    "fmm_stencil_var_apply", "precond_gmres_solve_var",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -86,6 +87,11 @@ def load_library():
     L.precond_gmres_solve.argtypes = [vp, dp, dp, dp, ctypes.POINTER(gmres_params),
                                       ctypes.POINTER(gmres_result), vp]
     L.precond_gmres_solve.restype = i32
+    L.fmm_stencil_var_apply.argtypes = [vp, dp, dp, dp, dp, vp]
+    L.fmm_stencil_var_apply.restype = i32
+    L.precond_gmres_solve_var.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(gmres_params),
+                                          ctypes.POINTER(gmres_result), vp]
+    L.precond_gmres_solve_var.restype = i32
     L.precond_gmres_solve_adjoint.argtypes = [vp, dp, dp, ctypes.POINTER(gmres_params),
                                               ctypes.POINTER(gmres_result), vp]
     L.precond_gmres_solve_adjoint.restype = i32
@@ -205,6 +211,30 @@ def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, str
             "true_rel_res": res.true_rel_res}
 
 
+def fmm_stencil_var_apply(plan, ax, ay, v, w, stream=None):
+    """w = A v for the variable-coefficient flux stencil (face values ax, ay)."""
+    n, N = plan.n, plan.npts
+    code = load_library().fmm_stencil_var_apply(plan._ptr, _dptr(ax, "ax", n * (n + 1)),
+                                                _dptr(ay, "ay", n * (n + 1)), _dptr(v, "v", N),
+                                                _dptr(w, "w", N), _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def precond_gmres_solve_var(plan, ax, ay, f, u, tol=1e-8, restart=30, maxit=600, stream=None):
+    """Variable-coefficient solve, constant-coefficient FMM-BEM preconditioner."""
+    n, N = plan.n, plan.npts
+    prm = gmres_params(tol, restart, maxit)
+    res = gmres_result()
+    code = load_library().precond_gmres_solve_var(plan._ptr, _dptr(ax, "ax", n * (n + 1)),
+                                                  _dptr(ay, "ay", n * (n + 1)), _dptr(f, "f", N),
+                                                  _dptr(u, "u", N), ctypes.byref(prm),
+                                                  ctypes.byref(res), _stream(stream))
+    _check(code, plan._ptr)
+    return {"status": code, "converged": code == FMM_OK, "iters": res.iters,
+            "restarts": res.restarts, "est_rel_res": res.est_rel_res,
+            "true_rel_res": res.true_rel_res}
+
+
 def precond_gmres_solve_adjoint(plan, g, lam, tol=1e-8, restart=30, maxit=600, stream=None):
     """lambda = A^{-T} g (A^T = A); lam holds the initial guess on entry."""
     N = plan.npts
@@ -281,6 +311,8 @@ class Plan:
     stencil_apply = fmm_stencil_apply
     solve = precond_gmres_solve
     solve_adjoint = precond_gmres_solve_adjoint
+    stencil_var_apply = fmm_stencil_var_apply
+    solve_var = precond_gmres_solve_var
     bumps_eval = fmm_bumps_eval
     bumps_grad = fmm_bumps_grad
     profile = fmm_profile

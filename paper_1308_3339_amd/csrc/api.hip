@@ -465,6 +465,31 @@ int precond_gmres_solve(fmm_plan *pl, const double *f, const double *g, double *
     return gmres_solve(pl, f, g, u, &q, res, (hipStream_t)stream);
 }
 
+int fmm_stencil_var_apply(fmm_plan *pl, const double *ax, const double *ay, const double *v,
+                          double *w, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "stencil needs a GRID plan");
+    if (!ax || !ay || !v || !w) return fail(pl, FMM_ERR_ARG, "ax, ay, v or w is NULL");
+    if (v == w) return fail(pl, FMM_ERR_ARG, "w must not alias v");
+    return stencil_var_apply(pl, ax, ay, v, w, (hipStream_t)stream);
+}
+
+int precond_gmres_solve_var(fmm_plan *pl, const double *ax, const double *ay, const double *f,
+                            double *u, const gmres_params *prm, gmres_result *res, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "solve needs a GRID plan");
+    if (!ax || !ay || !f || !u) return fail(pl, FMM_ERR_ARG, "ax, ay, f or u is NULL");
+    if (f == u) return fail(pl, FMM_ERR_ARG, "u must not alias f");
+    gmres_params q{1e-8, 30, 600};
+    if (prm) q = *prm;
+    if (!(q.tol > 0.0) || !std::isfinite(q.tol)) return fail(pl, FMM_ERR_ARG, "tol must be > 0");
+    if (q.restart < 1 || q.restart > 32) return fail(pl, FMM_ERR_ARG, "restart must be in [1, 32]");
+    if (q.maxit < 1) return fail(pl, FMM_ERR_ARG, "maxit must be >= 1");
+    return gmres_solve(pl, f, nullptr, u, &q, res, (hipStream_t)stream, ax, ay);
+}
+
 int precond_gmres_solve_adjoint(fmm_plan *pl, const double *g, double *lambda,
                                 const gmres_params *prm, gmres_result *res, void *stream)
 {

@@ -191,7 +191,10 @@ int bem_apply(fmm_plan *plan, double *sigma_out, hipStream_t s);
 // ---- Krylov (krylov.hip) ----
 int stencil_apply(fmm_plan *plan, const double *v, double *w, hipStream_t s);
 int gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
-                const gmres_params *prm, gmres_result *res, hipStream_t s);
+                const gmres_params *prm, gmres_result *res, hipStream_t s,
+                const double *ax = nullptr, const double *ay = nullptr);
+int stencil_var_apply(fmm_plan *plan, const double *ax, const double *ay, const double *v,
+                      double *w, hipStream_t s);
 int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
                       double *sigma, hipStream_t s);
 

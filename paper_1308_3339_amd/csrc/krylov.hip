@@ -55,16 +55,28 @@ __global__ __launch_bounds__(256) void k_stencil(const double *__restrict__ v,
     w[e] = c * ih2;
 }
 
-// unscaled stencil at element e of a row-major n x n grid, n = 2^ln
-__device__ __forceinline__ double stencil_at(const double *__restrict__ v, uint32_t e, int n, int ln)
+// Face coefficients of the variable-coefficient operator (null: constant
+// coefficient 1): ax[j (n+1) + i] sits between nodes i-1 and i of row j,
+// ay[j n + i] between rows j-1 and j of column i.
+struct Faces {
+    const double *ax, *ay;
+};
+
+// h^2 (A v)_e at element e of a row-major n x n grid, n = 2^ln; VAR selects
+// the flux form sum_faces a_f (v_e - v_neighbour) (Sec. 6.4), otherwise the
+// plain 5-point stencil (Sec. 2.1); values outside the grid are zero.
+template <bool VAR>
+__device__ __forceinline__ double stencil_at(const double *__restrict__ v, uint32_t e, int n, int ln,
+                                             Faces fc)
 {
     const uint32_t i = e & (uint32_t)(n - 1), j = e >> ln;
-    double c = 4.0 * v[e];
-    if (i > 0) c -= v[e - 1];
-    if (i < (uint32_t)n - 1) c -= v[e + 1];
-    if (j > 0) c -= v[e - n];
-    if (j < (uint32_t)n - 1) c -= v[e + n];
-    return c;
+    const double ve = v[e];
+    const double vw = i > 0 ? v[e - 1] : 0.0, vE = i < (uint32_t)n - 1 ? v[e + 1] : 0.0;
+    const double vs = j > 0 ? v[e - n] : 0.0, vn = j < (uint32_t)n - 1 ? v[e + n] : 0.0;
+    if (!VAR) return 4.0 * ve - vw - vE - vs - vn;
+    const double *axr = fc.ax + (size_t)j * (n + 1) + i;
+    const double *ayc = fc.ay + (size_t)j * n + i;
+    return axr[1] * (ve - vE) + axr[0] * (ve - vw) + ayc[n] * (ve - vn) + ayc[0] * (ve - vs);
 }
 
 // block-level sum of NV per-thread values into part[i * kRedBlocks + blockIdx.x]
@@ -87,11 +99,11 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double *pa
 
 // sweep A of step NJ: partial sums of a_i, b_i (i < NJ), c, d, e with
 // u = V_NJ and w = A z (scaled by 1/h^2)
-template <int NJ>
+template <int NJ, bool VAR>
 __global__ __launch_bounds__(256) void k_arnoldi_dots(const double *__restrict__ z,
                                                       const double *__restrict__ V, int64_t ldv,
                                                       double *__restrict__ part, int n, int ln,
-                                                      double ih2)
+                                                      double ih2, Faces fc)
 {
     constexpr int NA = 2 * NJ + 3;
     const uint32_t N = (uint32_t)n << ln;
@@ -103,7 +115,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_dots(const double *__restrict__
 #pragma unroll
         for (int i = 0; i < NJ; ++i) vv[i] = V[i * ldv + e];
         const double u = V[NJ * ldv + e];
-        const double w = stencil_at(z, e, n, ln) * ih2;
+        const double w = stencil_at<VAR>(z, e, n, ln, fc) * ih2;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
             acc[i] = fma(vv[i], u, acc[i]);
@@ -149,11 +161,11 @@ __global__ void k_arnoldi_coef(double *__restrict__ d, int nj)
 }
 
 // sweep B of step NJ: V_NJ <- v_NJ (finished), V_NJ+1 <- next candidate
-template <int NJ>
+template <int NJ, bool VAR>
 __global__ __launch_bounds__(256) void k_arnoldi_update(const double *__restrict__ z,
                                                         double *__restrict__ V, int64_t ldv,
                                                         const double *__restrict__ cf, int n,
-                                                        int ln, double ih2)
+                                                        int ln, double ih2, Faces fc)
 {
     const uint32_t N = (uint32_t)n << ln;
     const double cu = cf[0], cw = cf[1], cuu = cf[2];
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const double *__restrict
 #pragma unroll
         for (int i = 0; i < NJ; ++i) vv[i] = V[i * ldv + e];
         const double u = V[NJ * ldv + e];
-        const double w = stencil_at(z, e, n, ln) * ih2;
+        const double w = stencil_at<VAR>(z, e, n, ln, fc) * ih2;
         double vj = cu * u, un = fma(cuu, u, cw * w);
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
@@ -184,41 +196,54 @@ __global__ __launch_bounds__(256) void k_arnoldi_update(const double *__restrict
     X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
     X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
 
+template <bool VAR>
 static void launch_arnoldi_dots(int nj, dim3 g, hipStream_t s, const double *z, const double *V,
-                                int64_t ldv, double *part, int n, int ln, double ih2)
+                                int64_t ldv, double *part, int n, int ln, double ih2, Faces fc)
 {
     switch (nj) {
-#define X(k) case k: hipLaunchKernelGGL(k_arnoldi_dots<k>, g, dim3(256), 0, s, z, V, ldv, part, n, ln, ih2); break;
+#define X(k) case k: hipLaunchKernelGGL((k_arnoldi_dots<k, VAR>), g, dim3(256), 0, s, z, V, ldv, part, n, ln, ih2, fc); break;
         KRY_NJ_CASES(X)
 #undef X
     }
 }
 
+template <bool VAR>
 static void launch_arnoldi_update(int nj, dim3 g, hipStream_t s, const double *z, double *V,
-                                  int64_t ldv, const double *cf, int n, int ln, double ih2)
+                                  int64_t ldv, const double *cf, int n, int ln, double ih2, Faces fc)
 {
     switch (nj) {
-#define X(k) case k: hipLaunchKernelGGL(k_arnoldi_update<k>, g, dim3(256), 0, s, z, V, ldv, cf, n, ln, ih2); break;
+#define X(k) case k: hipLaunchKernelGGL((k_arnoldi_update<k, VAR>), g, dim3(256), 0, s, z, V, ldv, cf, n, ln, ih2, fc); break;
         KRY_NJ_CASES(X)
 #undef X
     }
 }
 
 // r = b - A x, partial r.r
+template <bool VAR>
 __global__ __launch_bounds__(256) void k_residual(const double *__restrict__ b,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ r,
                                                   double *__restrict__ part, int n, int ln,
-                                                  double ih2)
+                                                  double ih2, Faces fc)
 {
     const uint32_t N = (uint32_t)n << ln;
     double acc[1] = {0.0};
     for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < N; e += gridDim.x * 256u) {
-        const double re = b[e] - stencil_at(x, e, n, ln) * ih2;
+        const double re = b[e] - stencil_at<VAR>(x, e, n, ln, fc) * ih2;
         r[e] = re;
         acc[0] = fma(re, re, acc[0]);
     }
     block_reduce_store<1>(acc, part);
+}
+
+// w = A v with face coefficients
+__global__ __launch_bounds__(256) void k_stencil_var(const double *__restrict__ v,
+                                                     double *__restrict__ w, int n, int ln,
+                                                     double ih2, Faces fc)
+{
+    const uint32_t N = (uint32_t)n << ln;
+    for (uint32_t e = blockIdx.x * 256u + threadIdx.x; e < N; e += gridDim.x * 256u)
+        w[e] = stencil_at<true>(v, e, n, ln, fc) * ih2;
 }
 
 // partial v.v
@@ -314,6 +339,18 @@ static int red_blocks(int64_t N)
     return (int)b;
 }
 
+int stencil_var_apply(fmm_plan *pl, const double *ax, const double *ay, const double *v, double *w,
+                      hipStream_t s)
+{
+    const int n = (int)pl->n;
+    const double ih2 = 1.0 / (pl->h * pl->h);
+    StageTimer t(pl, FMM_STAGE_STENCIL, s);
+    hipLaunchKernelGGL(k_stencil_var, dim3(red_blocks((int64_t)n * n)), dim3(256), 0, s, v, w, n,
+                       pl->L + 3, ih2, Faces{ax, ay});
+    FMM_HIP(pl, hipGetLastError());
+    return FMM_OK;
+}
+
 int stencil_apply(fmm_plan *pl, const double *v, double *w, hipStream_t s)
 {
     const int n = (int)pl->n;
@@ -373,8 +410,9 @@ static int fetch_norm(fmm_plan *pl, int nblk, int slot, double *out, hipStream_t
     return FMM_OK;
 }
 
-int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params *prm,
-                gmres_result *res, hipStream_t s)
+template <bool VAR>
+static int gmres_solve_t(fmm_plan *pl, const double *f, const double *g, double *u,
+                         const gmres_params *prm, gmres_result *res, hipStream_t s, Faces fc)
 {
     const double tol = prm->tol;
     const int m = prm->restart, maxit = prm->maxit;
@@ -408,7 +446,7 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
         // true residual of the current iterate
         {
             StageTimer t(pl, FMM_STAGE_STENCIL, s);
-            hipLaunchKernelGGL(k_residual, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ln, ih2);
+            hipLaunchKernelGGL(k_residual<VAR>, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ln, ih2, fc);
         }
         double beta = 0.0;
         if ((st = fetch_norm(pl, nblk, kScal, &beta, s)) != FMM_OK) return st;
@@ -424,11 +462,11 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
             double *uj = pl->V + (size_t)j * N, *zj = pl->Z + (size_t)j * N;
             if ((st = precond_apply_one(pl, uj, zj, nullptr, nullptr, s)) != FMM_OK) return st;
             StageTimer ta(pl, FMM_STAGE_ARNOLDI, s);
-            launch_arnoldi_dots(j, gv, s, zj, pl->V, N, pl->partial, n, ln, ih2);
+            launch_arnoldi_dots<VAR>(j, gv, s, zj, pl->V, N, pl->partial, n, ln, ih2, fc);
             hipLaunchKernelGGL(k_finish, dim3(2 * j + 3), dim3(256), 0, s, pl->partial, nblk,
                                pl->dscal + kRaw, nullptr, nullptr, 0);
             hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(64), 0, s, pl->dscal, j);
-            launch_arnoldi_update(j, gv, s, zj, pl->V, N, pl->dscal + kCoef, n, ln, ih2);
+            launch_arnoldi_update<VAR>(j, gv, s, zj, pl->V, N, pl->dscal + kCoef, n, ln, ih2, fc);
             ta.stop();
             FMM_HIP(pl, hipMemcpyAsync(pl->hpin, pl->dscal, kCoef * sizeof(double),
                                        hipMemcpyDeviceToHost, s));
@@ -487,6 +525,13 @@ int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const
     FMM_HIP(pl, hipGetLastError());
     if (res) *res = r;
     return status;
+}
+
+int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params *prm,
+                gmres_result *res, hipStream_t s, const double *ax, const double *ay)
+{
+    if (ax) return gmres_solve_t<true>(pl, f, g, u, prm, res, s, Faces{ax, ay});
+    return gmres_solve_t<false>(pl, f, g, u, prm, res, s, Faces{nullptr, nullptr});
 }
 
 }  // namespace fmmprec
