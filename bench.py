@@ -322,7 +322,7 @@ def main():
     plan32.solve(f, u)
     stages32 = {k: round(v[0], 4) for k, v in plan32.profile_read().items()}
     plan32.close()
-    variant = {"prec": "P2P and M2L in FP32; tree, boundary, stencil, Arnoldi FP64",
+    variant = {"prec": "P2P and P2M as FP32 MFMA contractions, M2L in FP32; M2M, L2L, L2P, boundary, stencil, Arnoldi FP64",
                "solves_per_s": round(args.steps / t32, 4),
                "ms_per_step": round(1000.0 * t32 / args.steps, 4),
                "speedup_vs_fp64": round((args.steps / t32) / solves_per_s, 3),

@@ -60,10 +60,11 @@ enum {
 typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
 
 /* Arithmetic of the FMM.  FMM_FP64: everything in FP64.  FMM_FP32 (GRID
- * plans): the near field (P2P) and the multipole-to-local translations run
- * in FP32 (the preconditioner's tunable accuracy, Sec. 6.2); tree passes,
- * boundary correction, stencil and Krylov stay FP64.  The flexible outer
- * iteration reaches the same FP64 residual either way. */
+ * plans): the near field (P2P) and P2M run as FP32 matrix-core contractions
+ * (each 64-term FP32 partial folded into FP64) and the multipole-to-local
+ * translations in FP32 (the preconditioner's tunable accuracy, Sec. 6.2);
+ * M2M, L2L, L2P, boundary correction, stencil and Krylov stay FP64.  The
+ * flexible outer iteration reaches the same FP64 residual either way. */
 typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
 
 /* The problem the plan is built for.

@@ -153,10 +153,17 @@ static int build_tables(fmm_plan *pl)
         for (int dx = 0; dx <= 16; ++dx)
             if (dx || dy) rt[dy * 17 + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
     std::vector<float> kt32(kt.begin(), kt.end());
+    const int prow = 16 * ((2 * p + 15) / 16);
+    std::vector<float> p2m32((size_t)prow * 64, 0.0f);
+    for (int k = 0; k < p; ++k)
+        for (int j = 0; j < 64; ++j) {
+            p2m32[(size_t)(2 * k) * 64 + j] = (float)p2m[(size_t)k * 64 + j].x;
+            p2m32[(size_t)(2 * k + 1) * 64 + j] = (float)p2m[(size_t)k * 64 + j].y;
+        }
     std::vector<float2> hank32(hank.size());
     for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
     int st;
-    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
+    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
         (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
         (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
@@ -236,7 +243,7 @@ static int build_levels_and_work(fmm_plan *pl)
 
 static void release(fmm_plan *pl)
 {
-    void *ptrs[] = {pl->tab.ktab32, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+    void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->ring_cells, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,

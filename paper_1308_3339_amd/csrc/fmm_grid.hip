@@ -2,20 +2,23 @@
 //
 // The grid is uniform, so every leaf holds the same 8 x 8 point pattern and
 // every translation operator depends only on a small integer offset.  The
-// stages are:
-//   P2M + M2M (Sec. 5.3 items 1-2)  one block per 8x8 tile of cells builds the
-//                             tile's multipoles and those of its ancestors
-//                             three levels up (LDS), so the upward pass is
-//                             ceil((L-1)/3) launches
+// stages of one application are:
+//   P2P + P2M (Sec. 5.1; 5.3 item 1)  the first kernel: one block per 8x8
+//                             leaves stages the q tile once for the near
+//                             field (a 3x3-leaf restricted convolution whose
+//                             kernel values log(h|d|) are wave-uniform, or an
+//                             MFMA contraction in FP32 plans) and the leaf
+//                             multipoles
+//   M2M    (item 2)           one block per 8x8 tile of cells builds the
+//                             multipoles three levels up in LDS, so the
+//                             upward pass is ceil((L-2)/3) launches
 //   M2L    (item 3)           one launch for all levels; a block is a 16x16
 //                             tile of target cells and a third of their
 //                             27-entry lists, sources staged in LDS
 //   L2L    (item 4)           one block per cell three levels up builds the
 //                             local expansions of its 2x2, 4x4, 8x8 descendants
-//   L2P + P2P (item 5, Sec. 5.1)  one fused leaf kernel; the near field is a
-//                             3x3-leaf restricted convolution whose kernel
-//                             values log(h|d|) are wave-uniform (scalar
-//                             registers) because lanes map to leaves
+//   L2P    (item 5)           the last sweep over u; in the preconditioner it
+//                             also carries the boundary-source pass
 //
 // Expansions are scaled by the cell width w of their level (M~_k = M_k/w^k,
 // L~_k = L_k w^k), which makes M2M, M2L and L2L level independent.
@@ -158,74 +161,6 @@ __device__ __forceinline__ void m2m_chain(const double2 *sA, double2 *s0, double
     }
 }
 
-// P2M at the leaves of an 8x8-leaf tile, then M2M three levels up:
-// M~_k = qscale sum_j W[k][j] q_j, W[0][j] = 1, W[k][j] = -tau_j^k / k,
-// tau_j = ((a-3.5) + i(b-3.5)) / 8, j = 8b + a.  Lane = leaf; wave w
-// computes coefficients w, w+4, ...  The 64x64 point tile sits in LDS at
-// y*73 + (x/8)*9 + x%8: 9 doubles per leaf and 73 per row put the 32 lanes
-// of each half-wave on 32 distinct bank pairs.
-template <int P>
-__global__ __launch_bounds__(256) void k_p2m_up(const double *__restrict__ q, double qscale,
-                                                const double2 *__restrict__ W,
-                                                const double2 *__restrict__ A,
-                                                double2 *__restrict__ M, LevelInfo lv, int n, int L)
-{
-    __shared__ double sq[64 * 73];
-    __shared__ double2 sw[P * 64];
-    __shared__ double2 sA[4 * P * P];
-    __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
-    const int nl = 1 << L, tw = nl < 8 ? nl : 8, pw = tw * 8;
-    const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw;
-    const int tid = threadIdx.x;
-    const int lpw = __builtin_ctz(pw);   // pw = 8 tw is a power of two
-    {
-        double2 vw[rounds256(P * 64)], va[rounds256(4 * P * P)];
-        double vq[16];
-        fetch(vw, P * 64, [&](int t) { return W[t]; });
-        fetch(va, 4 * P * P, [&](int t) { return A[t]; });
-        fetch(vq, pw * pw, [&](int e) {
-            return q[(size_t)(ly0 * 8 + (e >> lpw)) * n + lx0 * 8 + (e & (pw - 1))];
-        });
-        put(vw, P * 64, [&](int t, double2 x) { sw[t] = x; });
-        put(va, 4 * P * P, [&](int t, double2 x) { sA[t] = x; });
-        put(vq, pw * pw, [&](int e, double x) {
-            const int yy = e >> lpw, xx = e & (pw - 1);
-            sq[yy * 73 + (xx >> 3) * 9 + (xx & 7)] = x;
-        });
-    }
-    __syncthreads();
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int nleaf = tw * tw;
-    constexpr int KW = (P + 3) / 4;
-    if (lane < nleaf) {
-        const int lx = lane % tw, ly = lane / tw;
-        const double *base = sq + ly * 8 * 73 + lx * 9;
-        double ax[KW], ay[KW];
-#pragma unroll
-        for (int i = 0; i < KW; ++i) ax[i] = ay[i] = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < 64; ++j) {
-            const double v = base[(j >> 3) * 73 + (j & 7)];
-#pragma unroll
-            for (int i = 0; i < KW; ++i) {
-                const int k = w + 4 * i;
-                if (k < P) {
-                    const double2 wk = sw[k * 64 + j];
-                    ax[i] = fma(wk.x, v, ax[i]);
-                    ay[i] = fma(wk.y, v, ay[i]);
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < KW; ++i) {
-            const int k = w + 4 * i;
-            if (k < P) s0[k * nleaf + lane] = make_double2(ax[i] * qscale, ay[i] * qscale);
-        }
-    }
-    __syncthreads();
-    store_tile<P>(s0, M + lv.off[L], nl, lx0, ly0, tw);
-    m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, L, tw, lx0, ly0);
-}
 
 // M2M from level l_in three levels up, one 8x8 tile of level-l_in cells per
 // block (only the border tiles when edge_only: the boundary-source pass has
@@ -590,22 +525,41 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
     for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
 }
 
-// FP32 variant of the leaf stage (precision variant of the preconditioner):
-// the q tile and the kernel table are FP32, every source row of the 3x3
-// leaves (24 sources) is summed in FP32 and folded into an FP64 accumulator,
-// so the FP32 rounding error stays at the level of one 24-term sum.  The
-// output is FP64; P2M for FP32 plans is done by k_p2m_up from the FP64 q.
-template <int P>
-__global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__restrict__ kt32)
+// FP32 variant of the leaf stage (precision variant of the preconditioner) on
+// the matrix cores.  On the grid the near field is a Toeplitz contraction:
+// for each of the 9 leaf offsets o, U(target pos t, leaf) += K_o[t][s] *
+// Q(source pos s, leaf + o) with K_o[t][s] = T(8 o + s_xy - t_xy), so it maps
+// onto v_mfma_f32_16x16x4f32: M = 64 target positions (4 tiles), N = 16
+// leaves per wave, K = 64 source positions per offset (16 steps).  The FP32
+// products of one offset are summed in the matrix core (64 terms) and folded
+// into FP64 accumulators, so FP32 rounding stays at the level of one 64-term
+// sum.  P2M is the same contraction with the P2M weights as A rows (2k: Re,
+// 2k+1: Im) and the centre leaves as B.  Block = 8x8 target leaves, wave w =
+// leaves 16w..16w+15 (rows 2w, 2w+1).  LDS: the 10x10-leaf q tile in FP32 at
+// (pos/4)*453 + row*136 + (pos%4)*80 + col, which puts the 64 lanes of a B
+// read (4 positions x 16 leaves) on distinct banks, and T with rows 48 apart.
+// MFMA lane layout (16x16x4f32): A[l%16][l/16], B[l/16][l%16],
+// D[4(l/16)+i][l%16].
+__device__ __forceinline__ constexpr int mq_idx(int pos, int r, int c)
 {
-    __shared__ float sq[6400];
+    return (pos >> 2) * 453 + r * 136 + (pos & 3) * 80 + c;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__restrict__ kt32,
+                                                     const float *__restrict__ w32)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int MTP = (2 * P + 15) / 16;      // P2M row tiles
+    __shared__ float sq[mq_idx(63, 9, 9) + 1];
+    __shared__ float st[31 * 48];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
     const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
     const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
     {
-        float v[25];
+        float v[25], tv[4];
 #pragma unroll
         for (int i = 0; i < 25; ++i) {
             const int e = tid + 256 * i;
@@ -614,58 +568,94 @@ __global__ __launch_bounds__(256) void k_leaf_grid32(LeafArgs a, const float *__
             v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)a.q[(size_t)gy * n + gx] : 0.0f;
         }
 #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            tv[i] = e < 961 ? kt32[e] : 0.0f;
+        }
+#pragma unroll
         for (int i = 0; i < 25; ++i) {
             const int e = tid + 256 * i;
             const int yy = e / 80, xx = e - yy * 80;
-            sq[leaf_tile_idx((yy & 7) * 8 + (xx & 7), yy >> 3, xx >> 3)] = v[i];
+            sq[mq_idx((yy & 7) * 8 + (xx & 7), yy >> 3, xx >> 3)] = v[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            if (e < 961) st[(e / 31) * 48 + e % 31] = tv[i];
         }
     }
     __syncthreads();
-    const int lx = lane & 7, ly = lane >> 3;
-    const int gLx = TX0 + lx, gLy = TY0 + ly;
-    const bool active = gLx < nl && gLy < nl;
-    const int ty0 = 2 * wave;
-    const int cleaf = leaf_tile_idx(0, ly + 1, lx + 1);
-    double acc[16];
+    const int g = lane >> 4, m16 = lane & 15;
+    const int nloc = 16 * wave + m16;              // target leaf of this lane's B column
+    const int lx = nloc & 7, ly = nloc >> 3;
+    // A operand of lane: target t = 16 mt + m16 -> tx = lane & 7, ty = 2 mt + ((lane >> 3) & 1);
+    // source s = 4 kk + g -> sx = 4 (kk & 1) + g, sy = kk >> 1
+    const int abase = (15 - ((lane >> 3) & 1)) * 48 + 15 + g - (lane & 7);
+    const int bbase = (ly + 1) * 136 + g * 80 + lx + 1;
+    double acc[4][4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
-    for (int oy = -1; oy <= 1; ++oy) {
-        for (int sy = 0; sy < 8; ++sy) {
-            const int dy0 = 8 * oy + sy - ty0;
-            const float *T0 = kt32 + (dy0 + 15) * 31 + 8;
-            const float *T1 = kt32 + (dy0 + 14) * 31 + 8;
-            float pacc[16];
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-            for (int t = 0; t < 16; ++t) pacc[t] = 0.0f;
+        for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
+#pragma unroll 1
+    for (int o = 0; o < 9; ++o) {
+        const int oy = o / 3 - 1, ox = o % 3 - 1;
+        f4 c[4];
 #pragma unroll
-            for (int ox = -1; ox <= 1; ++ox) {
-                float w0[15], w1[15];
+        for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        const float *Ab = st + abase + 8 * oy * 48 + 8 * ox;
+        const float *Bb = sq + bbase + oy * 136 + ox;
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const float b = Bb[kk * 453];
 #pragma unroll
-                for (int c = 0; c < 15; ++c) {
-                    w0[c] = T0[8 * ox + c];
-                    w1[c] = T1[8 * ox + c];
-                }
-                const int sl = cleaf + oy * 40 + ox;
+            for (int mt = 0; mt < 4; ++mt)
+                c[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    Ab[((kk >> 1) - 2 * mt) * 48 + 4 * (kk & 1)], b, c[mt], 0, 0, 0);
+        }
 #pragma unroll
-                for (int sx = 0; sx < 8; ++sx) {
-                    const float v = sq[leaf_tile_idx(sy * 8 + sx, 0, 0) + sl];
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                    for (int tx = 0; tx < 8; ++tx) {
-                        pacc[tx] = fmaf(w0[sx - tx + 7], v, pacc[tx]);
-                        pacc[8 + tx] = fmaf(w1[sx - tx + 7], v, pacc[8 + tx]);
-                    }
-                }
-            }
+            for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+    }
+    // P2M: rows of w32 against the centre leaves
+    f4 pm[MTP];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) acc[t] += (double)pacc[t];
+    for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.M) {
+        const float *Bb = sq + bbase;
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const float b = Bb[kk * 453];
+#pragma unroll
+            for (int mt = 0; mt < MTP; ++mt)
+                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w32[(16 * mt + m16) * 64 + 4 * kk + g], b,
+                                                              pm[mt], 0, 0, 0);
         }
     }
-    if (!active) return;
+    const int gLx = TX0 + lx, gLy = TY0 + ly;
+    if (gLx >= nl || gLy >= nl) return;
     const double qs = -a.qscale * kInv2Pi;
+    // D row m = 4 g + i of tile mt is target t = 16 mt + 4 g + i: ty = 2 mt + g / 2, tx = 4 (g & 1) + i
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int gy = gLy * 8 + ty0 + (t >> 3), gx = gLx * 8 + (t & 7);
-        a.u[(size_t)gy * n + gx] = qs * acc[t];
+    for (int mt = 0; mt < 4; ++mt) {
+        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
+    }
+    if (a.M) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        double2 *Ml = a.M + a.lv.off[a.L];
+        // D rows 16 mt + 4 g + {0,1} and {2,3} are (Re, Im) of coefficients 8 mt + 2 g + {0, 1}
+#pragma unroll
+        for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int k = 8 * mt + 2 * g + j;
+                if (k < P)
+                    Ml[k * ncell + cell] = make_double2(a.qscale * (double)pm[mt][2 * j],
+                                                        a.qscale * (double)pm[mt][2 * j + 1]);
+            }
     }
 }
 
@@ -1059,19 +1049,6 @@ static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, int edge_only, hipS
     }
 }
 
-template <int P>
-static int run_upward(fmm_plan *pl, const double *q, double qscale, double2 *M, hipStream_t s)
-{
-    const int L = pl->L, nl = pl->nl;
-    StageTimer t(pl, FMM_STAGE_P2M, s);
-    const int tw = std::min(nl, 8);
-    hipLaunchKernelGGL(k_p2m_up<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, q, qscale,
-                       pl->tab.p2m, pl->tab.m2m, M, pl->lv, (int)pl->n, L);
-    t.stop();
-    StageTimer t2(pl, FMM_STAGE_M2M, s);
-    run_m2m_from<P>(pl, M, L - 3, 0, s);
-    return FMM_OK;
-}
 
 // downward launches: (root level, levels below it, root is a level-2 cell)
 struct DownChunk {
@@ -1136,20 +1113,19 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     const int nl = pl->nl;
     const bool far = pl->L >= 2;
     const bool fp32 = pl->prec == FMM_FP32;
-    // FP32 plans stage q in FP32 for the near field, so their P2M is a pass of its own
-    if (far && fp32) run_upward<P>(pl, q, qscale, pl->ws.M, s);
     LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far);
-    if (far && !fp32) a.M = pl->ws.M;
+    if (far) a.M = pl->ws.M;
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
         if (fp32)
-            hipLaunchKernelGGL(k_leaf_grid32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32);
+            hipLaunchKernelGGL(k_leaf_mfma32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32,
+                               pl->tab.p2m32);
         else
             hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(512), 0, s, a);
     }
     if (far) {
-        if (!fp32) {
+        {
             StageTimer t(pl, FMM_STAGE_M2M, s);
             run_m2m_from<P>(pl, pl->ws.M, pl->L, 0, s);
         }

@@ -55,6 +55,7 @@ struct FmmTables {
     double *ktab;     // [31][31] log(h |d|), d in [-15, 15]^2, self entry log(eps h)
     double *rtab;     // [17][17] log(h |d|), |dx|, |dy| <= 16: ring node to interior node
     float *ktab32;    // FP32 copy of ktab (precision variant)
+    float *p2m32;     // [16 ceil(2p/16)][64] P2M weights as real rows (2k: Re, 2k+1: Im), FP32
     float2 *hank32;   // FP32 copy of hank (precision variant)
 };
 
