@@ -167,6 +167,31 @@ int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void
 int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                         const gmres_params *prm, gmres_result *res, void *stream);
 
+/* Many independent solves at once (GRID plans, sizes may differ): instance
+ * i solves A u[i] = f[i] on plans[i] (zero ring data) with the settings of
+ * precond_gmres_solve.  plans, f, u, res and elapsed_ms are HOST arrays of
+ * count entries (f[i], u[i] device arrays as for precond_gmres_solve; res
+ * and elapsed_ms may be NULL); the plans must be distinct (each owns the
+ * workspace of its solve).  Every plan runs on a stream of its own, created
+ * on first use, after the work already on `stream`; a host loop advances
+ * whichever solve's last chunk has completed, so small and large grids
+ * overlap on the GPU.  elapsed_ms[i] = host time from the call to the end of
+ * solve i.  flags: FMM_BATCH_GRAPHS replays each Arnoldi step (the whole
+ * preconditioner, both orthogonalisation sweeps and the scalar copy) from a
+ * HIP graph captured on the plan the first time that step runs.  `stream`
+ * waits for every instance before later work.  Returns FMM_OK when every
+ * instance converged, FMM_NOT_CONVERGED when one did not, or an error. */
+enum { FMM_BATCH_GRAPHS = 1 };
+int precond_gmres_solve_batch(fmm_plan *const *plans, int32_t count, const double *const *f,
+                              double *const *u, const gmres_params *prm, gmres_result *res,
+                              double *elapsed_ms, int32_t flags, void *stream);
+
+/* Autotuner: times the Krylov sweeps of this plan's grid with candidate
+ * block counts (64 .. 4096) and keeps the fastest for later solves; the
+ * choice is returned in *vec_blocks (HOST, may be NULL).  Synchronises
+ * `stream`.  GRID plans only. */
+int fmm_tune(fmm_plan *plan, void *stream, int32_t *vec_blocks);
+
 /* Variable-coefficient operator of Sec. 6.4, -div(a grad u), in flux form
  * on the plan's grid (GRID plans only), zero Dirichlet data:
  *   h^2 (A v)_ij = ax[j][i+1] (v_ij - v_{i+1,j}) + ax[j][i] (v_ij - v_{i-1,j})

@@ -14,13 +14,14 @@ FMM_OK, FMM_NOT_CONVERGED = 0, 1
 FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_ALLOC, FMM_ERR_NUMERIC, FMM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 FMM_GRID, FMM_POINTS = 0, 1
 FMM_FP64, FMM_FP32 = 0, 1
+FMM_BATCH_GRAPHS = 1
 
 # every symbol include/fmmprec.h declares
 exported_symbols = (
     "fmm_setup", "fmm_apply", "fmm_precond_apply", "fmm_precond_stages", "fmm_stencil_apply",
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
-    "fmm_stencil_var_apply", "precond_gmres_solve_var",
+    "fmm_stencil_var_apply", "precond_gmres_solve_var", "precond_gmres_solve_batch", "fmm_tune",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -87,6 +88,12 @@ def load_library():
     L.precond_gmres_solve.argtypes = [vp, dp, dp, dp, ctypes.POINTER(gmres_params),
                                       ctypes.POINTER(gmres_result), vp]
     L.precond_gmres_solve.restype = i32
+    L.precond_gmres_solve_batch.argtypes = [vp, i32, vp, vp, ctypes.POINTER(gmres_params),
+                                            ctypes.POINTER(gmres_result),
+                                            ctypes.POINTER(ctypes.c_double), i32, vp]
+    L.precond_gmres_solve_batch.restype = i32
+    L.fmm_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+    L.fmm_tune.restype = i32
     L.fmm_stencil_var_apply.argtypes = [vp, dp, dp, dp, dp, vp]
     L.fmm_stencil_var_apply.restype = i32
     L.precond_gmres_solve_var.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(gmres_params),
@@ -211,6 +218,41 @@ def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, str
             "true_rel_res": res.true_rel_res}
 
 
+def precond_gmres_solve_batch(plans, fs, us, tol=1e-8, restart=30, maxit=600, graphs=True,
+                              stream=None):
+    """Solves A u_i = f_i on plans[i] for every i at once (distinct GRID plans).
+    Returns {"status", "results": [per-instance dict], "elapsed_ms": [...]}."""
+    count = len(plans)
+    if not (len(fs) == len(us) == count):
+        raise ValueError("plans, fs and us must have the same length")
+    arr = ctypes.c_void_p * count
+    P = arr(*[p._ptr.value for p in plans])
+    F = arr(*[_dptr(f, "f", p.npts).value for f, p in zip(fs, plans)])
+    U = arr(*[_dptr(u, "u", p.npts).value for u, p in zip(us, plans)])
+    prm = gmres_params(tol, restart, maxit)
+    res = (gmres_result * count)()
+    el = (ctypes.c_double * count)()
+    L = load_library()
+    code = L.precond_gmres_solve_batch(P, count, F, U, ctypes.byref(prm), res, el,
+                                       FMM_BATCH_GRAPHS if graphs else 0, _stream(stream))
+    if code < 0:
+        msgs = [L.fmm_last_error(p._ptr) for p in plans] + [L.fmm_last_error(None)]
+        msg = next((m.decode() for m in msgs if m), "")
+        raise FmmError(code, msg)
+    return {"status": code,
+            "results": [{"converged": r.true_rel_res <= tol, "iters": r.iters,
+                         "restarts": r.restarts, "est_rel_res": r.est_rel_res,
+                         "true_rel_res": r.true_rel_res} for r in res],
+            "elapsed_ms": list(el)}
+
+
+def fmm_tune(plan, stream=None):
+    """Autotunes the plan's Krylov vector-kernel block count; returns it."""
+    out = ctypes.c_int32(0)
+    _check(load_library().fmm_tune(plan._ptr, _stream(stream), ctypes.byref(out)), plan._ptr)
+    return out.value
+
+
 def fmm_stencil_var_apply(plan, ax, ay, v, w, stream=None):
     """w = A v for the variable-coefficient flux stencil (face values ax, ay)."""
     n, N = plan.n, plan.npts
@@ -312,6 +354,7 @@ class Plan:
     solve = precond_gmres_solve
     solve_adjoint = precond_gmres_solve_adjoint
     stencil_var_apply = fmm_stencil_var_apply
+    tune = fmm_tune
     solve_var = precond_gmres_solve_var
     bumps_eval = fmm_bumps_eval
     bumps_grad = fmm_bumps_grad

@@ -252,6 +252,9 @@ static void release(fmm_plan *pl)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (pl->hpin) (void)hipHostFree(pl->hpin);
+    drop_step_graphs(pl);
+    if (pl->bevent) (void)hipEventDestroy(pl->bevent);
+    if (pl->bstream) (void)hipStreamDestroy(pl->bstream);
 }
 
 
@@ -495,6 +498,44 @@ int precond_gmres_solve_var(fmm_plan *pl, const double *ax, const double *ay, co
     if (q.restart < 1 || q.restart > 32) return fail(pl, FMM_ERR_ARG, "restart must be in [1, 32]");
     if (q.maxit < 1) return fail(pl, FMM_ERR_ARG, "maxit must be >= 1");
     return gmres_solve(pl, f, nullptr, u, &q, res, (hipStream_t)stream, ax, ay);
+}
+
+int precond_gmres_solve_batch(fmm_plan *const *plans, int32_t count, const double *const *f,
+                              double *const *u, const gmres_params *prm, gmres_result *res,
+                              double *elapsed_ms, int32_t flags, void *stream)
+{
+    if (!plans || !f || !u) return fail(nullptr, FMM_ERR_ARG, "plans, f or u is NULL");
+    if (count < 1 || count > 1024) return fail(nullptr, FMM_ERR_ARG, "count must be in [1, 1024]");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) return fail(nullptr, FMM_ERR_ARG, "a plan is NULL");
+        plans[i]->err.clear();   // a failure leaves its message on the plan that failed
+    }
+    for (int i = 0; i < count; ++i) {
+        fmm_plan *pl = plans[i];
+        if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "batched solves need GRID plans");
+        if (!f[i] || !u[i]) return fail(pl, FMM_ERR_ARG, "f[i] or u[i] is NULL");
+        if (f[i] == u[i]) return fail(pl, FMM_ERR_ARG, "u[i] must not alias f[i]");
+        for (int k = 0; k < i; ++k)
+            if (plans[k] == pl) return fail(pl, FMM_ERR_ARG, "a plan appears twice in the batch");
+    }
+    if (flags & ~FMM_BATCH_GRAPHS) return fail(plans[0], FMM_ERR_ARG, "unknown flags");
+    gmres_params q{1e-8, 30, 600};
+    if (prm) q = *prm;
+    if (!(q.tol > 0.0) || !std::isfinite(q.tol)) return fail(plans[0], FMM_ERR_ARG, "tol must be > 0");
+    if (q.restart < 1 || q.restart > 32) return fail(plans[0], FMM_ERR_ARG, "restart must be in [1, 32]");
+    if (q.maxit < 1) return fail(plans[0], FMM_ERR_ARG, "maxit must be >= 1");
+    return gmres_solve_batch(plans, count, f, u, &q, res, elapsed_ms, (flags & FMM_BATCH_GRAPHS) != 0,
+                             (hipStream_t)stream);
+}
+
+int fmm_tune(fmm_plan *pl, void *stream, int32_t *vec_blocks)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "tuning needs a GRID plan");
+    int chosen = 0;
+    const int st = tune_vector_blocks(pl, (hipStream_t)stream, &chosen);
+    if (st == FMM_OK && vec_blocks) *vec_blocks = chosen;
+    return st;
 }
 
 int precond_gmres_solve_adjoint(fmm_plan *pl, const double *g, double *lambda,

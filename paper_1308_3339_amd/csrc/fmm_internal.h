@@ -121,6 +121,14 @@ struct fmm_plan {
     // bump-gradient reduction partials (allocated on first use)
     double *bump_part = nullptr;
 
+    // Krylov vector kernels: tuned block count (0: one block per 1024 elements)
+    int vec_blocks = 0;
+    // batched solves: the plan's own stream and completion event, and the
+    // captured Arnoldi steps (graph j replays step j on this plan's buffers)
+    hipStream_t bstream = nullptr;
+    hipEvent_t bevent = nullptr;
+    std::vector<hipGraphExec_t> step_exec;
+
     // stage timing (fmm_profile)
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;          // created on first enable
@@ -196,6 +204,11 @@ int gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                 const double *ax = nullptr, const double *ay = nullptr);
 int stencil_var_apply(fmm_plan *plan, const double *ax, const double *ay, const double *v,
                       double *w, hipStream_t s);
+int gmres_solve_batch(fmm_plan *const *plans, int count, const double *const *f, double *const *u,
+                      const gmres_params *prm, gmres_result *res, double *elapsed_ms, bool graphs,
+                      hipStream_t caller);
+int tune_vector_blocks(fmm_plan *plan, hipStream_t s, int *chosen);
+void drop_step_graphs(fmm_plan *plan);
 int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
                       double *sigma, hipStream_t s);
 

@@ -23,7 +23,10 @@
 // Every vector kernel is HBM bound.  Reductions are two-stage with a fixed
 // order (no atomics), so repeated solves are bitwise reproducible.  One
 // small device-to-host copy per inner iteration feeds the host.
+#include <chrono>
 #include <cmath>
+#include <memory>
+#include <thread>
 #include <vector>
 
 #include "fmm_internal.h"
@@ -331,8 +334,10 @@ __global__ void k_make_rhs(const double *__restrict__ f, const double *__restric
     }
 }
 
-static int red_blocks(int64_t N)
+// blocks of the vector kernels: the plan's tuned count, else one per 1024 elements
+static int red_blocks(const fmm_plan *pl, int64_t N)
 {
+    if (pl && pl->vec_blocks > 0) return pl->vec_blocks;
     int64_t b = (N + 1023) / 1024;
     if (b < 1) b = 1;
     if (b > kRedBlocks) b = kRedBlocks;
@@ -345,7 +350,7 @@ int stencil_var_apply(fmm_plan *pl, const double *ax, const double *ay, const do
     const int n = (int)pl->n;
     const double ih2 = 1.0 / (pl->h * pl->h);
     StageTimer t(pl, FMM_STAGE_STENCIL, s);
-    hipLaunchKernelGGL(k_stencil_var, dim3(red_blocks((int64_t)n * n)), dim3(256), 0, s, v, w, n,
+    hipLaunchKernelGGL(k_stencil_var, dim3(red_blocks(pl, (int64_t)n * n)), dim3(256), 0, s, v, w, n,
                        pl->L + 3, ih2, Faces{ax, ay});
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
@@ -380,9 +385,17 @@ int precond_apply_one(fmm_plan *pl, const double *r, double *z, double *phi_ring
     return FMM_OK;
 }
 
+void drop_step_graphs(fmm_plan *pl)
+{
+    for (auto &ex : pl->step_exec)
+        if (ex) (void)hipGraphExecDestroy(ex);
+    pl->step_exec.clear();
+}
+
 static int ensure_krylov(fmm_plan *pl, int m)
 {
     if (pl->kry_m >= m) return FMM_OK;
+    drop_step_graphs(pl);   // the captured steps hold the old basis addresses
     const size_t N = (size_t)pl->n * pl->n;
     if (pl->V) { hipFree(pl->V); pl->V = nullptr; }
     if (pl->Z) { hipFree(pl->Z); pl->Z = nullptr; }
@@ -399,139 +412,401 @@ static int ensure_krylov(fmm_plan *pl, int m)
     return FMM_OK;
 }
 
-// reduce partials of a norm kernel into dscal[slot] = sqrt(sum) and fetch it
-static int fetch_norm(fmm_plan *pl, int nblk, int slot, double *out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, pl->partial, nblk, pl->dscal + slot,
-                       nullptr, nullptr, 1);
-    FMM_HIP(pl, hipMemcpyAsync(pl->hpin + slot, pl->dscal + slot, sizeof(double), hipMemcpyDeviceToHost, s));
-    FMM_HIP(pl, hipStreamSynchronize(s));
-    *out = pl->hpin[slot];
-    return FMM_OK;
-}
 
-template <bool VAR>
-static int gmres_solve_t(fmm_plan *pl, const double *f, const double *g, double *u,
-                         const gmres_params *prm, gmres_result *res, hipStream_t s, Faces fc)
-{
-    const double tol = prm->tol;
-    const int m = prm->restart, maxit = prm->maxit;
-    int st = ensure_krylov(pl, m);
-    if (st != FMM_OK) return st;
-    const int n = (int)pl->n;
-    const int64_t N = (int64_t)n * n;
-    const double ih2 = 1.0 / (pl->h * pl->h);
-    const int ln = pl->L + 3;      // n = 2^ln
-    const int nblk = red_blocks(N);
-    const dim3 gv(nblk), bv(256);
+// Resumable FGMRES(m) on one plan.  Each issue_*() enqueues a chunk of GPU
+// work on the solve's stream that ends with a device-to-host copy into the
+// plan's pinned buffer; advance() is called once that work has completed,
+// consumes the copied scalars on the host and enqueues the next chunk:
+//   INIT  b and |b|
+//   RES   true residual r = b - A u and |r| (start of a cycle)
+//   STEP  one Arnoldi step j (preconditioner, both sweeps, coefficients)
+// A single solve drives it with a stream synchronisation per chunk; the
+// batch driver interleaves many solves on their own streams.  With graphs,
+// step j of a plan is captured once into a HIP graph and replayed.
+class Fgmres {
+  public:
+    Fgmres(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params &prm,
+           hipStream_t s, Faces fc, bool graphs)
+        : pl_(pl), f_(f), g_(g), u_(u), tol_(prm.tol), m_(prm.restart), maxit_(prm.maxit), s_(s),
+          fc_(fc), var_(fc.ax != nullptr), graphs_(graphs)
+    {
+    }
 
-    hipLaunchKernelGGL(k_make_rhs, gv, bv, 0, s, f, g, pl->b, n, ih2);
-    hipLaunchKernelGGL(k_sumsq, gv, bv, 0, s, pl->b, pl->partial, N);
-    double bnorm = 0.0;
-    if ((st = fetch_norm(pl, nblk, kScal, &bnorm, s)) != FMM_OK) return st;
-    gmres_result r{};
-    if (!std::isfinite(bnorm)) return fail(pl, FMM_ERR_NUMERIC, "right-hand side is not finite");
-    if (bnorm == 0.0) {
-        FMM_HIP(pl, hipMemsetAsync(u, 0, N * sizeof(double), s));
-        FMM_HIP(pl, hipStreamSynchronize(s));
-        if (res) *res = r;
+    int begin()
+    {
+        int st = ensure_krylov(pl_, m_);
+        if (st != FMM_OK) return st;
+        n_ = (int)pl_->n;
+        N_ = (int64_t)n_ * n_;
+        ih2_ = 1.0 / (pl_->h * pl_->h);
+        ln_ = pl_->L + 3;
+        nblk_ = red_blocks(pl_, N_);
+        Hr_.assign((size_t)(m_ + 1) * m_, 0.0);
+        H_ = Hr_;
+        cs_.assign(m_, 0.0);
+        sn_.assign(m_, 0.0);
+        gg_.assign(m_ + 1, 0.0);
+        y_.assign(m_, 0.0);
+        hipLaunchKernelGGL(k_make_rhs, dim3(nblk_), dim3(256), 0, s_, f_, g_, pl_->b, n_, ih2_);
+        hipLaunchKernelGGL(k_sumsq, dim3(nblk_), dim3(256), 0, s_, pl_->b, pl_->partial, N_);
+        phase_ = INIT;
+        return fetch_scalar();
+    }
+
+    int advance()
+    {
+        FMM_HIP(pl_, hipGetLastError());
+        switch (phase_) {
+        case INIT:
+            bnorm_ = pl_->hpin[kScal];
+            if (!std::isfinite(bnorm_)) return fail(pl_, FMM_ERR_NUMERIC, "right-hand side is not finite");
+            if (bnorm_ == 0.0) {
+                FMM_HIP(pl_, hipMemsetAsync(u_, 0, N_ * sizeof(double), s_));
+                status_ = FMM_OK;
+                phase_ = DONE;
+                return FMM_OK;
+            }
+            return issue_residual();
+        case RES: {
+            const double beta = pl_->hpin[kScal];
+            if (!std::isfinite(beta)) return fail(pl_, FMM_ERR_NUMERIC, "residual is not finite");
+            r_.true_rel_res = beta / bnorm_;
+            if (beta / bnorm_ <= tol_ || iters_ >= maxit_) {
+                status_ = beta / bnorm_ <= tol_ ? FMM_OK : FMM_NOT_CONVERGED;
+                phase_ = DONE;
+                return FMM_OK;
+            }
+            hipLaunchKernelGGL(k_scale, dim3(nblk_), dim3(256), 0, s_, pl_->w, pl_->V, nullptr,
+                               1.0 / beta, N_);
+            std::fill(Hr_.begin(), Hr_.end(), 0.0);
+            beta_ = beta;
+            rt_prev_ = 0.0;
+            j_ = 0;
+            return issue_step();
+        }
+        case STEP: {
+            int st = consume_step();
+            if (st != FMM_OK) return st;
+            if (est_ <= tol_ || rt_last_ == 0.0 || j_ + 1 == m_ || iters_ >= maxit_) {
+                finish_cycle();
+                return issue_residual();
+            }
+            ++j_;
+            return issue_step();
+        }
+        case DONE:
+            break;
+        }
         return FMM_OK;
     }
-    // Hr: unrotated Hessenberg matrix (row-major, (m + 1) x m); H, gg: its
-    // Givens-rotated copy and right-hand side, rebuilt after every step
-    std::vector<double> Hr((size_t)(m + 1) * m), H((size_t)(m + 1) * m), cs(m), sn(m), gg(m + 1), y(m);
-    int iters = 0, status = FMM_NOT_CONVERGED;
-    double est = 1.0;
-    for (;;) {
-        // true residual of the current iterate
+
+    bool done() const { return phase_ == DONE; }
+    int status() const { return status_; }
+    gmres_result result() const
+    {
+        gmres_result r = r_;
+        r.iters = iters_;
+        r.est_rel_res = est_;
+        return r;
+    }
+
+  private:
+    enum Phase { INIT, RES, STEP, DONE };
+
+    int fetch_scalar()
+    {
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s_, pl_->partial, nblk_, pl_->dscal + kScal,
+                           nullptr, nullptr, 1);
+        FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin + kScal, pl_->dscal + kScal, sizeof(double),
+                                    hipMemcpyDeviceToHost, s_));
+        return FMM_OK;
+    }
+
+    int issue_residual()
+    {
         {
-            StageTimer t(pl, FMM_STAGE_STENCIL, s);
-            hipLaunchKernelGGL(k_residual<VAR>, gv, bv, 0, s, pl->b, u, pl->w, pl->partial, n, ln, ih2, fc);
+            StageTimer t(pl_, FMM_STAGE_STENCIL, s_);
+            if (var_)
+                hipLaunchKernelGGL(k_residual<true>, dim3(nblk_), dim3(256), 0, s_, pl_->b, u_, pl_->w,
+                                   pl_->partial, n_, ln_, ih2_, fc_);
+            else
+                hipLaunchKernelGGL(k_residual<false>, dim3(nblk_), dim3(256), 0, s_, pl_->b, u_, pl_->w,
+                                   pl_->partial, n_, ln_, ih2_, fc_);
         }
-        double beta = 0.0;
-        if ((st = fetch_norm(pl, nblk, kScal, &beta, s)) != FMM_OK) return st;
-        if (!std::isfinite(beta)) return fail(pl, FMM_ERR_NUMERIC, "residual is not finite");
-        r.true_rel_res = beta / bnorm;
-        if (beta / bnorm <= tol) { status = FMM_OK; break; }
-        if (iters >= maxit) { status = FMM_NOT_CONVERGED; break; }
-        hipLaunchKernelGGL(k_scale, gv, bv, 0, s, pl->w, pl->V, nullptr, 1.0 / beta, N);
-        std::fill(Hr.begin(), Hr.end(), 0.0);
-        double g0 = beta, rt_prev = 0.0;
-        int k = 0;
-        for (int j = 0; j < m && iters < maxit; ++j) {
-            double *uj = pl->V + (size_t)j * N, *zj = pl->Z + (size_t)j * N;
-            if ((st = precond_apply_one(pl, uj, zj, nullptr, nullptr, s)) != FMM_OK) return st;
-            StageTimer ta(pl, FMM_STAGE_ARNOLDI, s);
-            launch_arnoldi_dots<VAR>(j, gv, s, zj, pl->V, N, pl->partial, n, ln, ih2, fc);
-            hipLaunchKernelGGL(k_finish, dim3(2 * j + 3), dim3(256), 0, s, pl->partial, nblk,
-                               pl->dscal + kRaw, nullptr, nullptr, 0);
-            hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(64), 0, s, pl->dscal, j);
-            launch_arnoldi_update<VAR>(j, gv, s, zj, pl->V, N, pl->dscal + kCoef, n, ln, ih2, fc);
-            ta.stop();
-            FMM_HIP(pl, hipMemcpyAsync(pl->hpin, pl->dscal, kCoef * sizeof(double),
-                                       hipMemcpyDeviceToHost, s));
-            FMM_HIP(pl, hipStreamSynchronize(s));
-            FMM_HIP(pl, hipGetLastError());
-            const double *a = pl->hpin + kRaw, *bb = pl->hpin + kRaw + j;
-            const double rho = pl->hpin[kOut], hj = pl->hpin[kOut + 1], rt = pl->hpin[kOut + 2];
-            if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(hj) || !std::isfinite(rt))
-                return fail(pl, FMM_ERR_NUMERIC, "Arnoldi produced a non-finite or zero norm");
-            if (j == 0) {
-                g0 = beta * rho;           // r = beta u_0 = beta rho v_0
-            } else {                       // second projection of u_j fixes column j - 1
-                for (int i = 0; i < j; ++i) Hr[(size_t)i * m + j - 1] += rt_prev * a[i];
-                Hr[(size_t)j * m + j - 1] = rt_prev * rho;
+        phase_ = RES;
+        return fetch_scalar();
+    }
+
+    // the launches of Arnoldi step j (identical on every call, so capturable)
+    int launch_step(int j)
+    {
+        double *uj = pl_->V + (size_t)j * N_, *zj = pl_->Z + (size_t)j * N_;
+        int st = precond_apply_one(pl_, uj, zj, nullptr, nullptr, s_);
+        if (st != FMM_OK) return st;
+        StageTimer ta(pl_, FMM_STAGE_ARNOLDI, s_);
+        const dim3 gv(nblk_);
+        if (var_)
+            launch_arnoldi_dots<true>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
+        else
+            launch_arnoldi_dots<false>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
+        hipLaunchKernelGGL(k_finish, dim3(2 * j + 3), dim3(256), 0, s_, pl_->partial, nblk_,
+                           pl_->dscal + kRaw, nullptr, nullptr, 0);
+        hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(64), 0, s_, pl_->dscal, j);
+        if (var_)
+            launch_arnoldi_update<true>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
+        else
+            launch_arnoldi_update<false>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
+        ta.stop();
+        FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin, pl_->dscal, kCoef * sizeof(double),
+                                    hipMemcpyDeviceToHost, s_));
+        return FMM_OK;
+    }
+
+    int issue_step()
+    {
+        phase_ = STEP;
+        if (!graphs_) return launch_step(j_);
+        if ((int)pl_->step_exec.size() < m_) pl_->step_exec.resize(m_, nullptr);
+        hipGraphExec_t &ex = pl_->step_exec[j_];
+        if (!ex) {
+            hipGraph_t gr = nullptr;
+            FMM_HIP(pl_, hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed));
+            const int st = launch_step(j_);
+            const hipError_t ec = hipStreamEndCapture(s_, &gr);
+            if (st != FMM_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return st;
             }
-            for (int i = 0; i < j; ++i) Hr[(size_t)i * m + j] = bb[i];
-            Hr[(size_t)j * m + j] = hj;
-            Hr[(size_t)(j + 1) * m + j] = rt;
-            rt_prev = rt;
-            // Givens QR of columns 0..j
-            H = Hr;
-            std::fill(gg.begin(), gg.end(), 0.0);
-            gg[0] = g0;
-            for (int c = 0; c <= j; ++c) {
-                for (int i = 0; i < c; ++i) {
-                    const double x0 = H[(size_t)i * m + c], x1 = H[(size_t)(i + 1) * m + c];
-                    H[(size_t)i * m + c] = cs[i] * x0 + sn[i] * x1;
-                    H[(size_t)(i + 1) * m + c] = -sn[i] * x0 + cs[i] * x1;
-                }
-                const double x0 = H[(size_t)c * m + c], x1 = H[(size_t)(c + 1) * m + c];
-                const double rr = std::hypot(x0, x1);
-                cs[c] = x0 / rr;
-                sn[c] = x1 / rr;
-                H[(size_t)c * m + c] = rr;
-                H[(size_t)(c + 1) * m + c] = 0.0;
-                gg[c + 1] = -sn[c] * gg[c];
-                gg[c] = cs[c] * gg[c];
-            }
-            ++iters;
-            k = j + 1;
-            est = std::fabs(gg[j + 1]) / bnorm;
-            if (est <= tol || rt == 0.0) break;
+            FMM_HIP(pl_, ec);
+            const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            FMM_HIP(pl_, ei);
         }
+        FMM_HIP(pl_, hipGraphLaunch(ex, s_));
+        return FMM_OK;
+    }
+
+    int consume_step()
+    {
+        const int j = j_, m = m_;
+        const double *a = pl_->hpin + kRaw, *bb = pl_->hpin + kRaw + j;
+        const double rho = pl_->hpin[kOut], hj = pl_->hpin[kOut + 1], rt = pl_->hpin[kOut + 2];
+        if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(hj) || !std::isfinite(rt))
+            return fail(pl_, FMM_ERR_NUMERIC, "Arnoldi produced a non-finite or zero norm");
+        if (j == 0) {
+            g0_ = beta_ * rho;             // r = beta u_0 = beta rho v_0
+        } else {                           // second projection of u_j fixes column j - 1
+            for (int i = 0; i < j; ++i) Hr_[(size_t)i * m + j - 1] += rt_prev_ * a[i];
+            Hr_[(size_t)j * m + j - 1] = rt_prev_ * rho;
+        }
+        for (int i = 0; i < j; ++i) Hr_[(size_t)i * m + j] = bb[i];
+        Hr_[(size_t)j * m + j] = hj;
+        Hr_[(size_t)(j + 1) * m + j] = rt;
+        rt_prev_ = rt;
+        rt_last_ = rt;
+        // Givens QR of columns 0..j
+        H_ = Hr_;
+        std::fill(gg_.begin(), gg_.end(), 0.0);
+        gg_[0] = g0_;
+        for (int c = 0; c <= j; ++c) {
+            for (int i = 0; i < c; ++i) {
+                const double x0 = H_[(size_t)i * m + c], x1 = H_[(size_t)(i + 1) * m + c];
+                H_[(size_t)i * m + c] = cs_[i] * x0 + sn_[i] * x1;
+                H_[(size_t)(i + 1) * m + c] = -sn_[i] * x0 + cs_[i] * x1;
+            }
+            const double x0 = H_[(size_t)c * m + c], x1 = H_[(size_t)(c + 1) * m + c];
+            const double rr = std::hypot(x0, x1);
+            cs_[c] = x0 / rr;
+            sn_[c] = x1 / rr;
+            H_[(size_t)c * m + c] = rr;
+            H_[(size_t)(c + 1) * m + c] = 0.0;
+            gg_[c + 1] = -sn_[c] * gg_[c];
+            gg_[c] = cs_[c] * gg_[c];
+        }
+        ++iters_;
+        est_ = std::fabs(gg_[j + 1]) / bnorm_;
+        return FMM_OK;
+    }
+
+    // least squares of the cycle and u += Z y
+    void finish_cycle()
+    {
+        const int k = j_ + 1, m = m_;
         for (int i = k - 1; i >= 0; --i) {
-            double sacc = gg[i];
-            for (int t = i + 1; t < k; ++t) sacc -= H[(size_t)i * m + t] * y[t];
-            y[i] = sacc / H[(size_t)i * m + i];
+            double sacc = gg_[i];
+            for (int t = i + 1; t < k; ++t) sacc -= H_[(size_t)i * m + t] * y_[t];
+            y_[i] = sacc / H_[(size_t)i * m + i];
         }
         Coef cy{};
-        for (int i = 0; i < k; ++i) cy.c[i] = y[i];
-        hipLaunchKernelGGL(k_axpy_multi, gv, bv, 0, s, pl->Z, N, k, cy, u, N);
-        r.restarts++;
+        for (int i = 0; i < k; ++i) cy.c[i] = y_[i];
+        hipLaunchKernelGGL(k_axpy_multi, dim3(nblk_), dim3(256), 0, s_, pl_->Z, N_, k, cy, u_, N_);
+        r_.restarts++;
     }
-    r.iters = iters;
-    r.est_rel_res = est;
-    FMM_HIP(pl, hipGetLastError());
-    if (res) *res = r;
-    return status;
-}
+
+    fmm_plan *pl_;
+    const double *f_, *g_;
+    double *u_;
+    double tol_;
+    int m_, maxit_;
+    hipStream_t s_;
+    Faces fc_;
+    bool var_, graphs_;
+    int n_ = 0, ln_ = 0, nblk_ = 1;
+    int64_t N_ = 0;
+    double ih2_ = 0.0;
+    std::vector<double> Hr_, H_, cs_, sn_, gg_, y_;
+    Phase phase_ = INIT;
+    int iters_ = 0, j_ = 0, status_ = FMM_NOT_CONVERGED;
+    double bnorm_ = 0.0, beta_ = 0.0, g0_ = 0.0, rt_prev_ = 0.0, rt_last_ = 0.0, est_ = 1.0;
+    gmres_result r_{};
+};
 
 int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params *prm,
                 gmres_result *res, hipStream_t s, const double *ax, const double *ay)
 {
-    if (ax) return gmres_solve_t<true>(pl, f, g, u, prm, res, s, Faces{ax, ay});
-    return gmres_solve_t<false>(pl, f, g, u, prm, res, s, Faces{nullptr, nullptr});
+    Fgmres sol(pl, f, g, u, *prm, s, Faces{ax, ay}, false);
+    int st = sol.begin();
+    while (st == FMM_OK && !sol.done()) {
+        FMM_HIP(pl, hipStreamSynchronize(s));
+        st = sol.advance();
+    }
+    if (st != FMM_OK) return st;
+    FMM_HIP(pl, hipStreamSynchronize(s));
+    if (res) *res = sol.result();
+    return sol.status();
+}
+
+int gmres_solve_batch(fmm_plan *const *plans, int count, const double *const *f, double *const *u,
+                      const gmres_params *prm, gmres_result *res, double *elapsed_ms, bool graphs,
+                      hipStream_t caller)
+{
+    std::vector<std::unique_ptr<Fgmres>> sv(count);
+    std::vector<char> fin(count, 0);
+    hipEvent_t start = nullptr;
+    fmm_plan *p0 = plans[0];
+    FMM_HIP(p0, hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    FMM_HIP(p0, hipEventRecord(start, caller));
+    int st = FMM_OK;
+    for (int i = 0; i < count && st == FMM_OK; ++i) {
+        fmm_plan *pl = plans[i];
+        if (!pl->bstream && hipStreamCreateWithFlags(&pl->bstream, hipStreamNonBlocking) != hipSuccess)
+            st = fail(pl, FMM_ERR_DEVICE, "stream creation failed");
+        if (st == FMM_OK && !pl->bevent &&
+            hipEventCreateWithFlags(&pl->bevent, hipEventDisableTiming) != hipSuccess)
+            st = fail(pl, FMM_ERR_DEVICE, "event creation failed");
+        if (st == FMM_OK && hipStreamWaitEvent(pl->bstream, start, 0) != hipSuccess)
+            st = fail(pl, FMM_ERR_DEVICE, "stream wait failed");
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < count && st == FMM_OK; ++i) {
+        fmm_plan *pl = plans[i];
+        sv[i].reset(new Fgmres(pl, f[i], nullptr, u[i], *prm, pl->bstream, Faces{nullptr, nullptr},
+                               graphs && pl->prof_mask == 0));
+        st = sv[i]->begin();
+        if (st == FMM_OK && hipEventRecord(pl->bevent, pl->bstream) != hipSuccess)
+            st = fail(pl, FMM_ERR_DEVICE, "event record failed");
+    }
+    int active = count, failed_at = -1;
+    while (st == FMM_OK && active > 0) {
+        bool moved = false;
+        for (int i = 0; i < count && st == FMM_OK; ++i) {
+            if (fin[i]) continue;
+            fmm_plan *pl = plans[i];
+            const hipError_t q = hipEventQuery(pl->bevent);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                st = fail(pl, FMM_ERR_DEVICE, hipGetErrorString(q));
+                failed_at = i;
+                break;
+            }
+            moved = true;
+            st = sv[i]->advance();
+            if (st != FMM_OK) {
+                failed_at = i;
+                break;
+            }
+            if (hipEventRecord(pl->bevent, pl->bstream) != hipSuccess) {
+                st = fail(pl, FMM_ERR_DEVICE, "event record failed");
+                failed_at = i;
+                break;
+            }
+            if (sv[i]->done()) {
+                fin[i] = 1;
+                --active;
+                if (elapsed_ms)
+                    elapsed_ms[i] = std::chrono::duration<double, std::milli>(
+                                        std::chrono::steady_clock::now() - t0).count();
+                if (res) res[i] = sv[i]->result();
+            }
+        }
+        if (!moved) std::this_thread::yield();
+    }
+    // every instance stream drains before the caller's stream goes on
+    int overall = FMM_OK;
+    for (int i = 0; i < count; ++i) {
+        fmm_plan *pl = plans[i];
+        if (!pl->bstream) continue;
+        if (pl->bevent) {
+            (void)hipEventRecord(pl->bevent, pl->bstream);
+            (void)hipStreamWaitEvent(caller, pl->bevent, 0);
+        }
+        if (st != FMM_OK) (void)hipStreamSynchronize(pl->bstream);
+        if (st == FMM_OK && sv[i] && sv[i]->status() != FMM_OK) overall = FMM_NOT_CONVERGED;
+    }
+    (void)hipEventDestroy(start);
+    if (st != FMM_OK) {
+        if (failed_at > 0) p0->err = plans[failed_at]->err;
+        return st;
+    }
+    return overall;
+}
+
+// Tunes the block count of the Krylov vector kernels for this plan's grid:
+// times sweep A and B of an Arnoldi step (j = 4) for each candidate and
+// keeps the fastest (small grids want more blocks than elements / 1024).
+int tune_vector_blocks(fmm_plan *pl, hipStream_t s, int *chosen)
+{
+    int st = ensure_krylov(pl, 8);
+    if (st != FMM_OK) return st;
+    const int n = (int)pl->n, ln = pl->L + 3;
+    const int64_t N = (int64_t)n * n;
+    const double ih2 = 1.0 / (pl->h * pl->h);
+    const int cands[] = {64, 128, 256, 512, 1024, 2048, 4096};
+    hipEvent_t e0, e1;
+    FMM_HIP(pl, hipEventCreate(&e0));
+    FMM_HIP(pl, hipEventCreate(&e1));
+    // a finite basis to sweep over (values do not affect the timing)
+    hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->V, pl->V, nullptr, 0.0, N * 6);
+    hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->Z, pl->Z, nullptr, 0.0, N);
+    float best_ms = 1e30f;
+    int best = red_blocks(nullptr, N);
+    for (int c : cands) {
+        if ((int64_t)c * 256 > 4 * N && c > 64) continue;   // under 4 elements per thread
+        const int nb = c > kRedBlocks ? kRedBlocks : c;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {
+            FMM_HIP(pl, hipEventRecord(e0, s));
+            launch_arnoldi_dots<false>(4, dim3(nb), s, pl->Z, pl->V, N, pl->partial, n, ln, ih2,
+                                       Faces{nullptr, nullptr});
+            launch_arnoldi_update<false>(4, dim3(nb), s, pl->Z, pl->V, N, pl->dscal + kCoef, n, ln,
+                                         ih2, Faces{nullptr, nullptr});
+            FMM_HIP(pl, hipEventRecord(e1, s));
+            FMM_HIP(pl, hipEventSynchronize(e1));
+            float t = 0.0f;
+            FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms += t;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = nb;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (pl->vec_blocks != best) drop_step_graphs(pl);
+    pl->vec_blocks = best;
+    if (chosen) *chosen = best;
+    return FMM_OK;
 }
 
 }  // namespace fmmprec

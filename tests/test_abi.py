@@ -71,6 +71,10 @@ def test_null_arguments():
     assert lib.fmm_stencil_apply(None, None, None, 1, None) == fp.FMM_ERR_ARG
     assert lib.precond_gmres_solve(None, None, None, None, None, None, None) == fp.FMM_ERR_ARG
     assert lib.fmm_destroy(None) == fp.FMM_OK
+    assert lib.precond_gmres_solve_batch(None, 1, None, None, None, None, None, 0, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_tune(None, None, None) == fp.FMM_ERR_ARG
+    assert lib.precond_gmres_solve_var(None, None, None, None, None, None, None, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_bumps_eval(None, 1, None, None, None, None, None, None) == fp.FMM_ERR_ARG
 
 
 @pytest.mark.parametrize("n", [0, 100])
