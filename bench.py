@@ -357,37 +357,53 @@ def main():
 
     iters = infos[-1]["iters"]
 
-    # precision variant: P2P and M2L in FP32, the rest FP64, same solve and tolerance
-    log("precision variant (FP32 P2P + M2L)")
-    plan32 = fp.fmm_setup(n=n, p=p, bem=1, prec=fp.FMM_FP32)
-    for _ in range(args.warmup):
+    # precision variants: same solve and tolerance, reduced-precision P2P/P2M/M2L
+    def variant_block(prec, label, peak, mfma_per_flop):
+        pl = fp.fmm_setup(n=n, p=p, bem=1, prec=prec)
+        for _ in range(args.warmup):
+            u.zero_()
+            pl.solve(f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u.zero_()
+            inf = pl.solve(f, u)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t0
+        pl.stencil_apply(u, w)
+        relv = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
+        z64, zv = torch.empty_like(q), torch.empty_like(q)
+        plan.precond_apply(q, z64)
+        pl.precond_apply(q, zv)
+        perr = float((zv - z64).abs().max() / z64.abs().max())
+        pl.profile(fp.STAGES)
         u.zero_()
-        plan32.solve(f, u)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        u.zero_()
-        info32 = plan32.solve(f, u)
-    torch.cuda.synchronize()
-    t32 = time.perf_counter() - t0
-    plan32.stencil_apply(u, w)
-    rel32 = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
-    z64, z32 = torch.empty_like(q), torch.empty_like(q)
-    plan.precond_apply(q, z64)
-    plan32.precond_apply(q, z32)
-    perr = float((z32 - z64).abs().max() / z64.abs().max())
-    plan32.profile(fp.STAGES)
-    u.zero_()
-    plan32.solve(f, u)
-    stages32 = {k: round(v[0], 4) for k, v in plan32.profile_read().items()}
-    plan32.close()
-    variant = {"prec": "P2P and P2M as FP32 MFMA contractions, M2L in FP32; M2M, L2L, L2P, boundary, stencil, Arnoldi FP64",
-               "solves_per_s": round(args.steps / t32, 4),
-               "ms_per_step": round(1000.0 * t32 / args.steps, 4),
-               "speedup_vs_fp64": round((args.steps / t32) / solves_per_s, 3),
-               "iters": info32["iters"], "true_rel_res": rel32,
-               "precond_max_rel_diff_vs_fp64": perr, "stages_ms_per_solve": stages32}
-    log("fp32 variant %.2f solves/s" % variant["solves_per_s"])
+        pl.solve(f, u)
+        prof = pl.profile_read()
+        pl.close()
+        stg = {k: round(v[0], 4) for k, v in prof.items()}
+        leaf_ms_v, leaf_n_v = prof.get("LEAF", (0.0, 0))
+        avg = leaf_ms_v / max(leaf_n_v, 1)
+        ach = flops / (avg * 1e-3) / 1e12
+        return {"prec": label, "solves_per_s": round(args.steps / tv, 4),
+                "ms_per_step": round(1000.0 * tv / args.steps, 4),
+                "speedup_vs_fp64": round((args.steps / tv) / solves_per_s, 3),
+                "iters": inf["iters"], "true_rel_res": relv,
+                "precond_max_rel_diff_vs_fp64": perr, "stages_ms_per_solve": stg,
+                "leaf_roofline": {"bound": "mfma", "kernel": "near field + P2M",
+                                  "avg_launch_ms": round(avg, 5),
+                                  "achieved": round(ach, 3), "unit": "TFLOP/s",
+                                  "mfma_flops_per_algorithmic_flop": mfma_per_flop,
+                                  "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)}}
+
+    log("precision variants")
+    variant = variant_block(fp.FMM_FP32, "P2P and P2M as FP32 MFMA contractions, M2L in FP32; "
+                            "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1)
+    variant16 = variant_block(fp.FMM_SPLIT_FP16, "P2P and P2M as FP16 hi+lo MFMA products "
+                              "(hi*hi + hi*lo + lo*hi, FP32 accumulation), M2L in FP32; M2M, L2L, "
+                              "L2P, boundary, stencil, Arnoldi FP64", 2500.0, 3)
+    log("fp32 variant %.2f solves/s, split-fp16 %.2f" % (variant["solves_per_s"],
+                                                         variant16["solves_per_s"]))
     log("variable coefficient")
     varcoef = varcoef_block(fp, inputs, torch, plan, f, args.steps, args.warmup)
     log("variable coefficient %.2f solves/s, %d iterations" % (varcoef["solves_per_s"],
@@ -436,6 +452,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variant_fp32": variant,
+        "variant_split_fp16": variant16,
         "adjoint": adjoint,
         "variable_coefficient": varcoef,
         "batched": batched,

@@ -62,10 +62,14 @@ typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
 /* Arithmetic of the FMM.  FMM_FP64: everything in FP64.  FMM_FP32 (GRID
  * plans): the near field (P2P) and P2M run as FP32 matrix-core contractions
  * (each 64-term FP32 partial folded into FP64) and the multipole-to-local
- * translations in FP32 (the preconditioner's tunable accuracy, Sec. 6.2);
- * M2M, L2L, L2P, boundary correction, stencil and Krylov stay FP64.  The
- * flexible outer iteration reaches the same FP64 residual either way. */
-typedef enum { FMM_FP64 = 0, FMM_FP32 = 1 } fmm_precision;
+ * translations in FP32 (the preconditioner's tunable accuracy, Sec. 6.2).
+ * FMM_SPLIT_FP16 (GRID plans): as FMM_FP32, but the near field and P2M take
+ * each operand as an FP16 pair x = hi + lo (charges scaled per tile by a
+ * power of two) and sum hi*hi + hi*lo + lo*hi on the FP16 matrix cores with
+ * FP32 accumulation.  In every precision M2M, L2L, L2P, the boundary
+ * correction, the stencil and Krylov stay FP64, and the flexible outer
+ * iteration reaches the same FP64 residual. */
+typedef enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_SPLIT_FP16 = 2 } fmm_precision;
 
 /* The problem the plan is built for.
  *   GRID:   n = interior points per side, n = 8 * 2^L with 0 <= L <= 12 (n <= 32768,

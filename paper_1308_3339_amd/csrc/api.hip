@@ -155,15 +155,34 @@ static int build_tables(fmm_plan *pl)
     std::vector<float> kt32(kt.begin(), kt.end());
     const int prow = 16 * ((2 * p + 15) / 16);
     std::vector<float> p2m32((size_t)prow * 64, 0.0f);
+    std::vector<_Float16> p2m16((size_t)2 * prow * 64, (_Float16)0.0f);
     for (int k = 0; k < p; ++k)
         for (int j = 0; j < 64; ++j) {
             p2m32[(size_t)(2 * k) * 64 + j] = (float)p2m[(size_t)k * 64 + j].x;
             p2m32[(size_t)(2 * k + 1) * 64 + j] = (float)p2m[(size_t)k * 64 + j].y;
         }
+    // split x = hi + lo with hi = fp16(x), lo = fp16(x - hi)
+    auto split16 = [](double x, _Float16 &hi, _Float16 &lo) {
+        hi = (_Float16)x;
+        lo = (_Float16)(x - (double)hi);
+    };
+    for (int r = 0; r < 2 * p; ++r)
+        for (int j = 0; j < 64; ++j) {
+            const double2 w = p2m[(size_t)(r / 2) * 64 + j];
+            split16(r & 1 ? w.y : w.x, p2m16[(size_t)r * 64 + j], p2m16[(size_t)(prow + r) * 64 + j]);
+        }
+    // kernel table in 8 column-shifted copies: copy c, row r, entry j = T[r][j + c]
+    std::vector<_Float16> kt16((size_t)2 * 8 * 31 * 40, (_Float16)0.0f);
+    for (int c = 0; c < 8; ++c)
+        for (int r = 0; r < 31; ++r)
+            for (int j = 0; j + c <= 30 && j < 40; ++j)
+                split16(kt[(size_t)r * 31 + j + c], kt16[((size_t)c * 31 + r) * 40 + j],
+                        kt16[((size_t)(8 + c) * 31 + r) * 40 + j]);
     std::vector<float2> hank32(hank.size());
     for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
     int st;
-    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
+    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) ||
+        (st = upload(pl, &pl->tab.ktab16, kt16)) || (st = upload(pl, &pl->tab.p2m16, p2m16)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
         (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
         (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
@@ -243,7 +262,7 @@ static int build_levels_and_work(fmm_plan *pl)
 
 static void release(fmm_plan *pl)
 {
-    void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+    void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->ring_cells, pl->X0, pl->X2, pl->X1, pl->phi_ring, pl->ring_q,
@@ -279,10 +298,10 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (prm->p < kPMin || prm->p > kPMax)
         return fail(nullptr, FMM_ERR_ARG, "p must be in [2, 20]");
     if (prm->leaf != 64) return fail(nullptr, FMM_ERR_ARG, "leaf must be 64");
-    if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32)
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "prec must be FMM_FP64 or FMM_FP32");
-    if (prm->prec == FMM_FP32 && prob->kind != FMM_GRID)
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "FMM_FP32 is built for GRID plans");
+    if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32 && prm->prec != FMM_SPLIT_FP16)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "prec must be FMM_FP64, FMM_FP32 or FMM_SPLIT_FP16");
+    if (prm->prec != FMM_FP64 && prob->kind != FMM_GRID)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "reduced precision is built for GRID plans");
     if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
         return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
     hipStream_t s = (hipStream_t)stream;

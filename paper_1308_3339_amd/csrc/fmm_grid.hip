@@ -659,6 +659,155 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
     }
 }
 
+// Split-FP16 variant of the leaf stage: the contraction of k_leaf_mfma32 on
+// the FP16 matrix cores (v_mfma_f32_16x16x32_f16, K = 32 source positions =
+// four source rows per product).  Each operand is an FP16 pair x = hi + lo:
+// the kernel table T and the P2M weights were split at setup, the charges
+// are scaled per block by a power of two (so that |q| <= 1 over the staged
+// tile) and split here; hi*hi + hi*lo + lo*hi is summed in FP32 and folded
+// into FP64 per leaf offset.  The A fragment of a lane is 8 consecutive
+// entries of one T row starting at column 8 ox - tx + 15; T sits in LDS in
+// 8 copies shifted by c = 7 - tx columns so that this start is 16-byte
+// aligned, rows 20 dwords apart and copies 648 dwords apart (= 8 mod 64),
+// which spreads a 16-lane read over distinct banks.  The q tile is
+// [leaf][pos] with 72 halves per leaf.  MFMA lane layout (16x16x32 f16):
+// A[l%16][8(l/16)+i], B[8(l/16)+i][l%16], D[4(l/16)+i][l%16].
+constexpr int kT16Row = 40, kT16Copy = 31 * 40, kT16Pitch = 1296, kQ16Leaf = 72;
+
+template <int P>
+__global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const _Float16 *__restrict__ kt16,
+                                                     const _Float16 *__restrict__ w16)
+{
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int MTP = (2 * P + 15) / 16;
+    __shared__ __align__(16) _Float16 st[2][8 * kT16Pitch];
+    __shared__ __align__(16) _Float16 sqh[100 * kQ16Leaf], sql[100 * kQ16Leaf];
+    __shared__ double smax[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, nl = a.nl;
+    const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
+    const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
+    double v[25];
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < 25; ++i) {
+        const int e = tid + 256 * i;
+        const int yy = e / 80, xx = e - yy * 80;
+        const int gx = X0 + xx, gy = Y0 + yy;
+        v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+        mx = fmax(mx, fabs(v[i]));
+    }
+    // kernel table: 2 x 8 copies of 31 rows x 40 halves, copied in 16-byte units
+    for (int e = tid; e < 2 * 8 * 31 * 5; e += 256) {
+        const int part = e / (8 * 31 * 5), rem = e - part * (8 * 31 * 5);
+        const int c = rem / (31 * 5), r = (rem / 5) % 31, q8 = rem % 5;
+        *(h8 *)&st[part][c * kT16Pitch + r * kT16Row + 8 * q8] =
+            *(const h8 *)&kt16[((size_t)(part * 8 + c) * 31 + r) * kT16Row + 8 * q8];
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (lane == 0) smax[wave] = mx;
+    __syncthreads();
+    const double tmax = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+    int ex = 0;
+    if (tmax > 0.0) (void)frexp(tmax, &ex);          // tmax < 2^ex
+    const double scale = ldexp(1.0, -ex), iscale = ldexp(1.0, ex);
+#pragma unroll
+    for (int i = 0; i < 25; ++i) {
+        const int e = tid + 256 * i;
+        const int yy = e / 80, xx = e - yy * 80;
+        const int at = ((yy >> 3) * 10 + (xx >> 3)) * kQ16Leaf + (yy & 7) * 8 + (xx & 7);
+        const double x = v[i] * scale;
+        const _Float16 hi = (_Float16)x;
+        sqh[at] = hi;
+        sql[at] = (_Float16)(x - (double)hi);
+    }
+    __syncthreads();
+    const int g = lane >> 4, m16 = lane & 15;
+    const int nloc = 16 * wave + m16;
+    const int lx = nloc & 7, ly = nloc >> 3;
+    // A: target t = 16 mt + m16 (tx = lane & 7, ty = 2 mt + ((lane >> 3) & 1)),
+    //    source rows sy = 4 ks + g, columns from 8 ox - tx + 15 in copy 7 - tx
+    const int tx = lane & 7, tyb = (lane >> 3) & 1;
+    const int abase = (7 - tx) * kT16Pitch + (15 - tyb + g) * kT16Row + 8;
+    const int bbase = ((ly + 1) * 10 + lx + 1) * kQ16Leaf + 8 * g;
+    double acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
+#pragma unroll 1
+    for (int o = 0; o < 9; ++o) {
+        const int oy = o / 3 - 1, ox = o % 3 - 1;
+        f4 c[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        const int boff = bbase + (oy * 10 + ox) * kQ16Leaf;
+        const int aoff = abase + 8 * oy * kT16Row + 8 * ox;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const h8 bh = *(const h8 *)&sqh[boff + 32 * ks];
+            const h8 bl = *(const h8 *)&sql[boff + 32 * ks];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int ai = aoff + (4 * ks - 2 * mt) * kT16Row;
+                const h8 ah = *(const h8 *)&st[0][ai];
+                const h8 al = *(const h8 *)&st[1][ai];
+                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c[mt], 0, 0, 0);
+                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c[mt], 0, 0, 0);
+                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c[mt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+    }
+    f4 pm[MTP];
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.M) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const h8 bh = *(const h8 *)&sqh[bbase + 32 * ks];
+            const h8 bl = *(const h8 *)&sql[bbase + 32 * ks];
+#pragma unroll
+            for (int mt = 0; mt < MTP; ++mt) {
+                const size_t wi = (size_t)(16 * mt + m16) * 64 + 32 * ks + 8 * g;
+                const h8 wh = *(const h8 *)&w16[wi];
+                const h8 wl = *(const h8 *)&w16[(size_t)16 * MTP * 64 + wi];
+                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bl, pm[mt], 0, 0, 0);
+                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl, bh, pm[mt], 0, 0, 0);
+                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bh, pm[mt], 0, 0, 0);
+            }
+        }
+    }
+    const int gLx = TX0 + lx, gLy = TY0 + ly;
+    if (gLx >= nl || gLy >= nl) return;
+    const double qs = -a.qscale * iscale * kInv2Pi;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
+    }
+    if (a.M) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        double2 *Ml = a.M + a.lv.off[a.L];
+        const double ms = a.qscale * iscale;
+#pragma unroll
+        for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int k = 8 * mt + 2 * g + j;
+                if (k < P)
+                    Ml[k * ncell + cell] = make_double2(ms * (double)pm[mt][2 * j],
+                                                        ms * (double)pm[mt][2 * j + 1]);
+            }
+    }
+}
+
 // Lattice coordinates (in units of h) of ring node t (counter-clockwise).
 __device__ __forceinline__ void ring_node(int t, int n, int &Ix, int &Iy)
 {
@@ -1069,7 +1218,7 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
     const size_t shm = (size_t)P * 400 * sizeof(double2);
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
-        if (pl->prec == FMM_FP32)
+        if (pl->prec != FMM_FP64)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems), dim3(768), shm / 2, s, items, M, Lm,
                                pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b);
@@ -1118,7 +1267,10 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
-        if (fp32)
+        if (pl->prec == FMM_SPLIT_FP16)
+            hipLaunchKernelGGL(k_leaf_mfma16<P>, gl, dim3(256), 0, s, a, pl->tab.ktab16,
+                               pl->tab.p2m16);
+        else if (fp32)
             hipLaunchKernelGGL(k_leaf_mfma32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32,
                                pl->tab.p2m32);
         else

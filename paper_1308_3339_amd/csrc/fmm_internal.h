@@ -56,6 +56,8 @@ struct FmmTables {
     double *rtab;     // [17][17] log(h |d|), |dx|, |dy| <= 16: ring node to interior node
     float *ktab32;    // FP32 copy of ktab (precision variant)
     float *p2m32;     // [16 ceil(2p/16)][64] P2M weights as real rows (2k: Re, 2k+1: Im), FP32
+    _Float16 *ktab16; // [hi, lo][8 shifted copies][31 rows][40]: ktab split in two FP16 halves
+    _Float16 *p2m16;  // [hi, lo][16 ceil(2p/16)][64]: p2m32 split in two FP16 halves
     float2 *hank32;   // FP32 copy of hank (precision variant)
 };
 

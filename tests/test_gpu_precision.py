@@ -1,5 +1,6 @@
-"""Precision variant (P2P and M2L in FP32, everything else FP64) against the
-FP64 oracle.
+"""Precision variants against the FP64 oracle: FMM_FP32 (P2P and P2M as FP32
+matrix-core contractions, M2L in FP32) and FMM_SPLIT_FP16 (P2P and P2M as
+FP16 hi+lo products on the matrix cores, M2L in FP32); everything else FP64.
 
 The variant changes the preconditioner only by rounding, so:
   * per-stage error against the FP64 oracle (volume potential, ring
@@ -41,15 +42,19 @@ def relmax(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
+PRECS = ("FMM_FP32", "FMM_SPLIT_FP16")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [32, 128, 256])
-def test_fp32_stages_against_fp64_oracle(n):
+def test_fp32_stages_against_fp64_oracle(n, prec):
     import torch
 
     import paper_1308_3339_amd as fp
-    say("case fp32 stages n=%d" % n)
+    say("case %s stages n=%d" % (prec, n))
     p = 10
     r = inputs.random_charges(n * n, seed=600 + n)
-    with fp.fmm_setup(n=n, p=p, bem=1, prec=fp.FMM_FP32) as plan:
+    with fp.fmm_setup(n=n, p=p, bem=1, prec=getattr(fp, prec)) as plan:
         u = torch.empty(n * n, dtype=torch.float64, device="cuda")
         plan.apply(dev(r), u)
         z, phi, sig = (torch.empty(m, dtype=torch.float64, device="cuda") for m in (n * n, 4 * n, 4 * n))
@@ -64,37 +69,40 @@ def test_fp32_stages_against_fp64_oracle(n):
         assert v <= 1e-5, k
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [64, 256])
-def test_fp32_solve_reaches_fp64_residual(n):
+def test_fp32_solve_reaches_fp64_residual(n, prec):
     import torch
 
     import paper_1308_3339_amd as fp
-    say("case fp32 solve n=%d" % n)
+    say("case %s solve n=%d" % (prec, n))
     f = inputs.gaussian_bumps(n, 16, seed=700 + n)
     its = {}
     sols = {}
-    for prec in (fp.FMM_FP64, fp.FMM_FP32):
+    low = getattr(fp, prec)
+    for prec in (fp.FMM_FP64, low):
         with fp.fmm_setup(n=n, p=10, prec=prec) as plan:
             u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
             info = plan.solve(dev(f), u)
             assert info["converged"]
             sols[prec], its[prec] = host(u), info["iters"]
-    say("  iterations fp64 %d fp32 %d" % (its[fp.FMM_FP64], its[fp.FMM_FP32]))
-    res = np.linalg.norm(f - o.stencil(n, sols[fp.FMM_FP32])) / np.linalg.norm(f)
+    say("  iterations fp64 %d reduced %d" % (its[fp.FMM_FP64], its[low]))
+    res = np.linalg.norm(f - o.stencil(n, sols[low])) / np.linalg.norm(f)
     assert res <= 1e-8
-    assert its[fp.FMM_FP32] <= its[fp.FMM_FP64] + 2
+    assert its[low] <= its[fp.FMM_FP64] + 2
     xo, _ = o.fgmres(n, f, o.Preconditioner(n, p=10))
-    assert np.linalg.norm(sols[fp.FMM_FP32] - xo) <= 1e-6 * np.linalg.norm(xo)
+    assert np.linalg.norm(sols[low] - xo) <= 1e-6 * np.linalg.norm(xo)
 
 
-def test_fp32_full_size_solve():
+@pytest.mark.parametrize("prec", PRECS)
+def test_fp32_full_size_solve(prec):
     import torch
 
     import paper_1308_3339_amd as fp
     n = 2048
-    say("case fp32 solve n=2048")
+    say("case %s solve n=2048" % prec)
     f = inputs.gaussian_bumps(n, 16, seed=inputs.SEED_BUMPS_2048)
-    with fp.fmm_setup(n=n, p=10, prec=fp.FMM_FP32) as plan:
+    with fp.fmm_setup(n=n, p=10, prec=getattr(fp, prec)) as plan:
         u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
         info = plan.solve(dev(f), u)
         ug = host(u)
