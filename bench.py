@@ -273,6 +273,8 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log("setup %.3f s" % setup_s)
+    vec_blocks = plan.tune()     # autotuned Krylov vector-kernel grid (part of setup)
+    log("tuned vector blocks %d" % vec_blocks)
 
     if args.probe:
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
@@ -360,6 +362,7 @@ def main():
     # precision variants: same solve and tolerance, reduced-precision P2P/P2M/M2L
     def variant_block(prec, label, peak, mfma_per_flop):
         pl = fp.fmm_setup(n=n, p=p, bem=1, prec=prec)
+        pl.tune()
         for _ in range(args.warmup):
             u.zero_()
             pl.solve(f, u)
@@ -448,6 +451,7 @@ def main():
         "iters": iters,
         "true_rel_res": rel_res,
         "setup_s": round(setup_s, 3),
+        "tuned_vector_blocks": vec_blocks,
         "stages_ms_per_solve": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -54,7 +54,7 @@ def relmax(a, b):
 
 
 @pytest.mark.parametrize("n,p", [(8, 6), (16, 10), (32, 6), (32, 10), (64, 10), (64, 14),
-                                 (128, 8), (128, 10), (256, 12)])
+                                 (128, 8), (128, 10), (256, 12), (128, 2), (256, 19), (256, 20)])
 def test_fmm_apply_matches_oracle(n, p):
     say("case fmm_apply grid n=%d p=%d" % (n, p))
     fp = _fp()
