@@ -171,7 +171,7 @@ def varcoef_block(fp, inputs, torch, plan, f, steps, warmup):
             "iters": info["iters"], "true_rel_res": rel}
 
 
-def batched_block(fp, inputs, torch, steps, warmup):
+def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     """64 independent solves of uneven sizes (16 each of 128^2, 256^2, 512^2,
     1024^2; instance k has 16 bumps seeded 1000 + k), p = 10, FGMRES(30) to
     1e-8.  Each plan's vector kernels are autotuned first; the batch runs with
@@ -181,7 +181,8 @@ def batched_block(fp, inputs, torch, steps, warmup):
     the batch without graphs."""
     sizes = [s for s in (128, 256, 512, 1024) for _ in range(16)]
     dev = torch.device("cuda:0")
-    plans = [fp.fmm_setup(n=n, p=10, bem=1) for n in sizes]
+    plans = [fp.fmm_setup(n=n, p=10, bem=1, prec=fp.FMM_FP64 if prec is None else prec)
+             for n in sizes]
     fs = [torch.from_numpy(inputs.gaussian_bumps(n, 16, seed=1000 + k)).to(dev)
           for k, n in enumerate(sizes)]
     us = [torch.zeros_like(f) for f in fs]
@@ -415,6 +416,10 @@ def main():
     batched = batched_block(fp, inputs, torch, args.steps, args.warmup)
     log("batched %.1f instances/s (sequential %.1f)" % (batched["instances_per_s"],
                                                         batched["sequential_instances_per_s"]))
+    batched16 = batched_block(fp, inputs, torch, args.steps, args.warmup, prec=fp.FMM_SPLIT_FP16)
+    batched["split_fp16"] = {k: batched16[k] for k in ("instances_per_s", "batch_ms", "p50_ms",
+                                                       "p99_ms", "all_converged", "iters_min_max")}
+    log("batched split-fp16 %.1f instances/s" % batched16["instances_per_s"])
     log("adjoint (1024^2 gradients)")
     adjoint = adjoint_block(fp, inputs, torch, args.steps, args.warmup)
     log("adjoint %.2f gradients/s, fd err %.2e" % (adjoint["gradients_per_s"],

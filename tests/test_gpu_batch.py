@@ -8,7 +8,9 @@
   * the tuned vector-kernel block count is one of the candidates and keeps
     solutions within rounding of the untuned ones;
   * the 64-instance workload (16 each of 128^2, 256^2, 512^2, 1024^2,
-    bumps seeded 1000 + k) converges to a true residual <= 1e-8 everywhere.
+    bumps seeded 1000 + k) converges to a true residual <= 1e-8 everywhere;
+  * FP64, FP32 and split-FP16 plans of the 2048^2 workload in one batch all
+    reach the FP64 true residual and agree with the FP64 solution.
 """
 import sys
 
@@ -157,6 +159,36 @@ def test_batch_64_uneven_instances():
             (worst, sorted(set(r["iters"] for r in out["results"])), np.percentile(el, 50),
              np.percentile(el, 99)))
         assert worst <= 1e-8
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+def test_reduced_precision_batch_at_2048_reaches_fp64_residual():
+    """The split-FP16 and FP32 plans in one batch with an FP64 plan on 2048^2
+    grids: every instance reaches the FP64 true residual 1e-8 and the reduced
+    solutions agree with the FP64 one within the 1e-6 solution bar."""
+    import torch
+
+    import paper_1308_3339_amd as fp
+    n = 2048
+    say("case batch 2048 fp64 + fp32 + split-fp16")
+    precs = (fp.FMM_FP64, fp.FMM_FP32, fp.FMM_SPLIT_FP16)
+    plans = [fp.fmm_setup(n=n, p=10, prec=pr) for pr in precs]
+    try:
+        f = dev(inputs.gaussian_bumps(n, 16, seed=inputs.SEED_BUMPS_2048))
+        fs = [f, f.clone(), f.clone()]
+        us = [torch.zeros_like(f) for _ in precs]
+        out = fp.precond_gmres_solve_batch(plans, fs, us)
+        assert out["status"] == fp.FMM_OK
+        ref = us[0]
+        for pl, u, r in zip(plans, us, out["results"]):
+            w = torch.empty_like(u)
+            pl.stencil_apply(u, w)
+            res = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
+            diff = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+            say("  iters %d true rel res %.2e  rel diff vs fp64 %.2e" % (r["iters"], res, diff))
+            assert res <= 1e-8 and diff <= 1e-6
     finally:
         for pl in plans:
             pl.close()
