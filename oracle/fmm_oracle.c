@@ -31,6 +31,10 @@
  *     the parent's 3x3 neighbourhood that are not adjacent (edge or corner)
  *     to the target cell, at levels 2..L.  Near field: the 3x3 leaves around
  *     the target's leaf, self leaf included.
+ *   - With a MAC theta (Sec. 5.2, dual tree traversal): a cell pair of one
+ *     level is well separated when the two cell radii (half diagonals) sum
+ *     to less than theta times the centre distance; pairs that fail are
+ *     split together, leaf pairs that fail are P2P.
  *   - Operators P2M, M2M, M2L, L2L, L2P exactly as listed in Sec. 5.3
  *     (items 1-5), unscaled, powers by repeated multiplication.
  *   - Boundary correction (Sec. 4.1, eqs. ubound/uinter with zero Dirichlet
@@ -396,6 +400,205 @@ int orc_fmm(int L, double x0, double y0, double side, int p,
 }
 
 /* ======================================================================== */
+/* Dual tree traversal with a multipole acceptance criterion (Sec. 5.2).     */
+/* Target and source trees are the same uniform quadtree.  A pair of cells  */
+/* (A, B) of one level is well separated when r_A + r_B < theta |c_A - c_B|, */
+/* r the cell radius (half the diagonal), c the geometric centres; such a   */
+/* pair is one M2L.  A pair that fails the test is one P2P pair if both     */
+/* cells are leaves; otherwise both cells are split (they have the same     */
+/* size on a uniform tree, so the rule "split the larger cell" ties and     */
+/* both are split) and the traversal recurses on the 16 child pairs.  It    */
+/* starts at (root, root).  theta in (0, 1]; theta in (1/sqrt2, 1] gives    */
+/* back the interaction lists above.                                        */
+/* ======================================================================== */
+typedef struct { int l, t, s; } orc_pair;   /* level, target cell, source cell (row-major) */
+typedef struct { orc_pair *v; size_t n, cap; } orc_pairs;
+
+static void pairs_push(orc_pairs *a, int l, int t, int s)
+{
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 1024;
+        a->v = (orc_pair *)realloc(a->v, a->cap * sizeof(orc_pair));
+    }
+    a->v[a->n].l = l; a->v[a->n].t = t; a->v[a->n].s = s;
+    a->n++;
+}
+
+typedef struct { int L; double side, theta; orc_pairs m2l, p2p; } dtt_ctx;
+
+static void dtt_visit(dtt_ctx *c, int l, int ax, int ay, int bx, int by)
+{
+    int nc = 1 << l;
+    double w = c->side / (double)nc;
+    double r = 0.5 * sqrt(2.0) * w;
+    double dx = (double)(ax - bx) * w, dy = (double)(ay - by) * w;
+    if (r + r < c->theta * sqrt(dx * dx + dy * dy)) {
+        pairs_push(&c->m2l, l, ay * nc + ax, by * nc + bx);
+        return;
+    }
+    if (l == c->L) {
+        pairs_push(&c->p2p, l, ay * nc + ax, by * nc + bx);
+        return;
+    }
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            dtt_visit(c, l + 1, 2 * ax + (a & 1), 2 * ay + (a >> 1), 2 * bx + (b & 1),
+                      2 * by + (b >> 1));
+}
+
+static int dtt_run(int L, double side, double theta, dtt_ctx *c)
+{
+    if (L < 0 || !(theta > 0.0) || theta > 1.0) return -1;
+    memset(c, 0, sizeof(*c));
+    c->L = L; c->side = side; c->theta = theta;
+    dtt_visit(c, 0, 0, 0, 0, 0);
+    return 0;
+}
+
+/* Interaction pairs of the traversal on a tree with L levels (unit root;
+ * the lists do not depend on the root's size).  counts[0] = M2L pairs,
+ * counts[1] = P2P leaf pairs.  When m2l / p2p are not null they receive
+ * (level, target cell, source cell) triples and (target leaf, source leaf)
+ * pairs, in traversal order. */
+int orc_dtt_lists(int L, double theta, int64_t *counts, int *m2l, int *p2p)
+{
+    dtt_ctx c;
+    if (dtt_run(L, 1.0, theta, &c) != 0) return -1;
+    counts[0] = (int64_t)c.m2l.n;
+    counts[1] = (int64_t)c.p2p.n;
+    for (size_t i = 0; m2l && i < c.m2l.n; ++i) {
+        m2l[3 * i] = c.m2l.v[i].l; m2l[3 * i + 1] = c.m2l.v[i].t; m2l[3 * i + 2] = c.m2l.v[i].s;
+    }
+    for (size_t i = 0; p2p && i < c.p2p.n; ++i) {
+        p2p[2 * i] = c.p2p.v[i].t; p2p[2 * i + 1] = c.p2p.v[i].s;
+    }
+    free(c.m2l.v); free(c.p2p.v);
+    return 0;
+}
+
+/* pairs grouped by target: start[t] .. start[t+1] index src[] (stable) */
+static void group_by_target(const orc_pairs *a, int level, int ncell, int **start, int **src)
+{
+    int *st = (int *)calloc((size_t)ncell + 1, sizeof(int));
+    for (size_t i = 0; i < a->n; ++i)
+        if (a->v[i].l == level) st[a->v[i].t + 1]++;
+    for (int t = 0; t < ncell; ++t) st[t + 1] += st[t];
+    int *sr = (int *)malloc(sizeof(int) * (size_t)(st[ncell] > 0 ? st[ncell] : 1));
+    int *fill = (int *)calloc((size_t)ncell, sizeof(int));
+    for (size_t i = 0; i < a->n; ++i)
+        if (a->v[i].l == level) sr[st[a->v[i].t] + fill[a->v[i].t]++] = a->v[i].s;
+    free(fill);
+    *start = st;
+    *src = sr;
+}
+
+/* The FMM of orc_fmm with the interactions of the dual tree traversal:
+ * P2M at the leaves, M2M up to the root, the traversal's M2L pairs at every
+ * level, L2L down, L2P at the targets' leaves, and the traversal's P2P leaf
+ * pairs for the near field. */
+int orc_fmm_theta(int L, double x0, double y0, double side, int p, double theta,
+                  int ns, const double *sx, const double *sy, const double *sq,
+                  int nt, const double *tx, const double *ty, double self_log,
+                  double *u)
+{
+    if (L < 0 || p < 1) return -1;
+    dtt_ctx c;
+    if (dtt_run(L, side, theta, &c) != 0) return -1;
+    int nl = 1 << L, nleaf = nl * nl;
+
+    int *scount = (int *)calloc((size_t)nleaf + 1, sizeof(int));
+    int *sleaf = (int *)malloc(sizeof(int) * (size_t)(ns > 0 ? ns : 1));
+    for (int j = 0; j < ns; ++j) {
+        int lx = leaf_coord(sx[j], x0, side, nl), ly = leaf_coord(sy[j], y0, side, nl);
+        sleaf[j] = ly * nl + lx;
+        scount[sleaf[j] + 1]++;
+    }
+    for (int k = 0; k < nleaf; ++k) scount[k + 1] += scount[k];
+    int *sorder = (int *)malloc(sizeof(int) * (size_t)(ns > 0 ? ns : 1));
+    int *fill = (int *)calloc((size_t)nleaf, sizeof(int));
+    for (int j = 0; j < ns; ++j) sorder[scount[sleaf[j]] + fill[sleaf[j]]++] = j;
+    free(fill);
+
+    cplx **M = (cplx **)calloc((size_t)L + 1, sizeof(cplx *));
+    cplx **Lx = (cplx **)calloc((size_t)L + 1, sizeof(cplx *));
+    for (int l = 0; l <= L; ++l) {
+        size_t nc = (size_t)1 << (2 * l);
+        M[l] = (cplx *)calloc(nc * (size_t)p, sizeof(cplx));
+        Lx[l] = (cplx *)calloc(nc * (size_t)p, sizeof(cplx));
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nleaf; ++k) {
+        cplx ctr = cell_centre(L, k % nl, k / nl, x0, y0, side);
+        p2m_c(p, ctr, scount[k + 1] - scount[k], sx, sy, sq, sorder + scount[k],
+              M[L] + (size_t)k * p);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        int nc = 1 << l;
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nc * nc; ++k) {
+            int ix = k % nc, iy = k / nc;
+            cplx pc = cell_centre(l, ix, iy, x0, y0, side);
+            for (int d = 0; d < 2; ++d)
+                for (int e = 0; e < 2; ++e) {
+                    int cx = 2 * ix + e, cy = 2 * iy + d;
+                    cplx cc = cell_centre(l + 1, cx, cy, x0, y0, side);
+                    m2m_c(p, M[l + 1] + ((size_t)cy * (2 * nc) + cx) * p, cc - pc,
+                          M[l] + (size_t)k * p);
+                }
+        }
+    }
+    for (int l = 0; l <= L; ++l) {
+        int nc = 1 << l, *st, *sr;
+        group_by_target(&c.m2l, l, nc * nc, &st, &sr);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < nc * nc; ++k) {
+            cplx tc = cell_centre(l, k % nc, k / nc, x0, y0, side);
+            for (int a = st[k]; a < st[k + 1]; ++a) {
+                int s = sr[a];
+                cplx scc = cell_centre(l, s % nc, s / nc, x0, y0, side);
+                m2l_c(p, M[l] + (size_t)s * p, tc - scc, Lx[l] + (size_t)k * p);
+            }
+        }
+        free(st); free(sr);
+        if (l < L) {
+            int nch = 2 * nc;
+#pragma omp parallel for schedule(static)
+            for (int k = 0; k < nch * nch; ++k) {
+                int cx = k % nch, cy = k / nch;
+                cplx cc = cell_centre(l + 1, cx, cy, x0, y0, side);
+                cplx pc = cell_centre(l, cx / 2, cy / 2, x0, y0, side);
+                l2l_c(p, Lx[l] + ((size_t)(cy / 2) * nc + cx / 2) * p, cc - pc,
+                      Lx[l + 1] + (size_t)k * p);
+            }
+        }
+    }
+    int *nst, *nsr;
+    group_by_target(&c.p2p, L, nleaf, &nst, &nsr);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int t = 0; t < nt; ++t) {
+        int lx = leaf_coord(tx[t], x0, side, nl), ly = leaf_coord(ty[t], y0, side, nl);
+        int tl = ly * nl + lx;
+        cplx tz = tx[t] + I * ty[t];
+        double far = l2p_c(p, Lx[L] + (size_t)tl * p, tz - cell_centre(L, lx, ly, x0, y0, side));
+        double near = 0.0;
+        for (int a = nst[tl]; a < nst[tl + 1]; ++a) {
+            int sl = nsr[a];
+            for (int s = scount[sl]; s < scount[sl + 1]; ++s) {
+                int j = sorder[s];
+                double dx = tx[t] - sx[j], dy = ty[t] - sy[j];
+                double r = sqrt(dx * dx + dy * dy);
+                near += sq[j] * (r == 0.0 ? self_log : log(r));
+            }
+        }
+        u[t] = -(far + near) / (2.0 * ORC_PI);
+    }
+    for (int l = 0; l <= L; ++l) { free(M[l]); free(Lx[l]); }
+    free(M); free(Lx); free(scount); free(sleaf); free(sorder); free(nst); free(nsr);
+    free(c.m2l.v); free(c.p2p.v);
+    return 0;
+}
+
+/* ======================================================================== */
 /* Grid problem: 5-point FD Poisson on the unit square, zero Dirichlet data */
 /* interior node (i, j), i, j = 0..n-1 sits at ((i+1)h, (j+1)h), h = 1/(n+1), */
 /* stored row-major at j*n + i.                                              */
@@ -512,6 +715,7 @@ void orc_lu_solve(int m, const double *LU, const int *piv, double *b)
 typedef struct {
     int n, p, bem, exact, L;
     double h, self_log;
+    double theta;      /* 0: interaction lists; else the traversal's MAC */
     double *gx, *gy;   /* interior nodes   */
     double *rx, *ry;   /* ring nodes (4n)  */
     double *LU;        /* factored S       */
@@ -519,10 +723,12 @@ typedef struct {
     double *tx, *ty;   /* pass-1 targets: interior then ring */
 } orc_pc;
 
-void *orc_pc_create(int n, int p, double eps_s, int bem, int exact)
+void *orc_pc_create(int n, int p, double eps_s, int bem, int exact, double theta)
 {
     if (n < 8 || (n & (n - 1)) != 0) return NULL;
+    if (theta < 0.0 || theta > 1.0) return NULL;
     orc_pc *pc = (orc_pc *)calloc(1, sizeof(orc_pc));
+    pc->theta = theta;
     size_t N = (size_t)n * n;
     int m = 4 * n;
     pc->n = n; pc->p = p; pc->bem = bem; pc->exact = exact;
@@ -567,6 +773,9 @@ static void pc_potential(const orc_pc *pc, int ns, const double *sx, const doubl
 {
     if (pc->exact)
         orc_direct(ns, sx, sy, q, nt, tx, ty, pc->self_log, u);
+    else if (pc->theta > 0.0)
+        orc_fmm_theta(pc->L, 0.5 * pc->h, 0.5 * pc->h, pc->n * pc->h, pc->p, pc->theta, ns, sx,
+                      sy, q, nt, tx, ty, pc->self_log, u);
     else
         orc_fmm(pc->L, 0.5 * pc->h, 0.5 * pc->h, pc->n * pc->h, pc->p, ns, sx, sy, q,
                 nt, tx, ty, pc->self_log, u);

@@ -78,6 +78,13 @@ def lib():
                               ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp, _dp,
                               ctypes.c_double, _dp]
         L.orc_fmm.restype = ctypes.c_int
+        L.orc_fmm_theta.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    _dp, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_fmm_theta.restype = ctypes.c_int
+        L.orc_dtt_lists.argtypes = [ctypes.c_int, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_int64), _ip, _ip]
+        L.orc_dtt_lists.restype = ctypes.c_int
         L.orc_stencil.argtypes = [ctypes.c_int, _dp, _dp]
         L.orc_grid_points.argtypes = [ctypes.c_int, _dp, _dp]
         L.orc_ring_points.argtypes = [ctypes.c_int, _dp, _dp]
@@ -86,7 +93,7 @@ def lib():
         L.orc_lu_factor.restype = ctypes.c_int
         L.orc_lu_solve.argtypes = [ctypes.c_int, _dp, _ip, _dp]
         L.orc_pc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                    ctypes.c_int]
+                                    ctypes.c_int, ctypes.c_double]
         L.orc_pc_create.restype = ctypes.c_void_p
         L.orc_pc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_pc_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -180,14 +187,33 @@ def direct(sx, sy, q, tx, ty, self_log=0.0):
     return u
 
 
-def fmm(L, x0, y0, side, p, sx, sy, q, tx, ty, self_log=0.0):
+def fmm(L, x0, y0, side, p, sx, sy, q, tx, ty, self_log=0.0, theta=None):
+    """FMM on a uniform tree; theta None: interaction lists (Sec. 5.2, GR
+    rule), else the dual tree traversal with that MAC."""
     sx, sy, q, tx, ty = map(_f64, (sx, sy, q, tx, ty))
     u = np.zeros(len(tx))
-    rc = lib().orc_fmm(L, x0, y0, side, p, len(q), _ptr(sx), _ptr(sy), _ptr(q), len(tx),
-                       _ptr(tx), _ptr(ty), float(self_log), _ptr(u))
+    if theta is None:
+        rc = lib().orc_fmm(L, x0, y0, side, p, len(q), _ptr(sx), _ptr(sy), _ptr(q), len(tx),
+                           _ptr(tx), _ptr(ty), float(self_log), _ptr(u))
+    else:
+        rc = lib().orc_fmm_theta(L, x0, y0, side, p, float(theta), len(q), _ptr(sx), _ptr(sy),
+                                 _ptr(q), len(tx), _ptr(tx), _ptr(ty), float(self_log), _ptr(u))
     if rc != 0:
         raise ValueError("orc_fmm rejected its arguments")
     return u
+
+
+def dtt_lists(L, theta):
+    """Interaction pairs of the dual tree traversal (Sec. 5.2) on a uniform
+    tree with L levels: (M2L triples (level, target cell, source cell),
+    P2P pairs (target leaf, source leaf)), cells row-major."""
+    cnt = (ctypes.c_int64 * 2)()
+    if lib().orc_dtt_lists(L, float(theta), cnt, None, None) != 0:
+        raise ValueError("orc_dtt_lists rejected its arguments")
+    m2l = np.zeros(3 * cnt[0], dtype=np.int32)
+    p2p = np.zeros(2 * cnt[1], dtype=np.int32)
+    lib().orc_dtt_lists(L, float(theta), cnt, m2l.ctypes.data_as(_ip), p2p.ctypes.data_as(_ip))
+    return m2l.reshape(-1, 3), p2p.reshape(-1, 2)
 
 
 # --------------------------------------------------------------------------
@@ -229,9 +255,10 @@ def stencil(n, v):
     return w
 
 
-def grid_fmm(n, p, q, eps_s=EPS_SELF, with_ring=False):
+def grid_fmm(n, p, q, eps_s=EPS_SELF, with_ring=False, theta=None):
     """FMM volume potential of grid charges q at the interior nodes
-    (and, with_ring, also at the 4n ring nodes appended at the end)."""
+    (and, with_ring, also at the 4n ring nodes appended at the end); theta
+    selects the dual-tree-traversal interactions."""
     h, L = grid_h(n), grid_levels(n)
     gx, gy = grid_points(n)
     tx, ty = gx, gy
@@ -239,7 +266,7 @@ def grid_fmm(n, p, q, eps_s=EPS_SELF, with_ring=False):
         rx, ry = ring_points(n)
         tx, ty = np.concatenate([gx, rx]), np.concatenate([gy, ry])
     return fmm(L, 0.5 * h, 0.5 * h, n * h, p, gx, gy, _f64(q).reshape(-1), tx, ty,
-               self_log(n, eps_s))
+               self_log(n, eps_s), theta=theta)
 
 
 def grid_direct(n, q, eps_s=EPS_SELF):
@@ -277,10 +304,11 @@ def bem_matrix(n):
 class Preconditioner:
     """z = P^{-1} r: FMM (or exact sums) + boundary correction on an n x n grid."""
 
-    def __init__(self, n, p=10, eps_s=EPS_SELF, bem=True, exact=False):
+    def __init__(self, n, p=10, eps_s=EPS_SELF, bem=True, exact=False, theta=None):
         self.n = n
         self.h = grid_h(n)
-        self._pc = lib().orc_pc_create(n, p, eps_s, int(bem), int(exact))
+        self._pc = lib().orc_pc_create(n, p, eps_s, int(bem), int(exact),
+                                       0.0 if theta is None else float(theta))
         if not self._pc:
             raise ValueError("oracle preconditioner: bad arguments")
 
