@@ -98,13 +98,29 @@ typedef struct {
  *   self_eps GRID: the singular self term is G_self = -(1/2pi) log(self_eps h)
  *            (Sec. 4.2 smoothing read as a self-cell value); 0 selects the
  *            default exp(-gamma)/(2 sqrt 2) = 0.1985..., which matches the
- *            5-point lattice Green's function at short range. */
+ *            5-point lattice Green's function at short range.
+ *   theta    well-separatedness.  0: the interaction lists of Sec. 5.2 (the
+ *            children of the parent's 3x3 neighbourhood that are not
+ *            adjacent; near field = 3x3 leaves).  In [0.3, 1]: the multipole
+ *            acceptance criterion of the dual tree traversal (Sec. 5.2): two
+ *            cells of one level interact by M2L when the sum of their radii
+ *            (half diagonals) is below theta times their centre distance,
+ *            failing pairs are split together, failing leaf pairs are P2P.
+ *            On the uniform tree the near field is then the disk of leaves
+ *            |d|^2 <= 2/theta^2 and the lists the parent disk's children
+ *            outside it; theta > 1/sqrt(2) gives the list rule again.
+ *            Smaller theta trades more near-field and M2L work for accuracy
+ *            at a given p (p = 6, theta = 0.4 gives about six digits).
+ *            theta < 1/sqrt(2) requires GRID, FMM_FP64, p <= 12 and
+ *            p (16 + 4K)^2 * 16 <= 160 KiB, K = floor(sqrt(2)/theta) (so
+ *            p <= 10 for theta < 0.354); otherwise FMM_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t p;
     int32_t leaf;
     int32_t prec;
     int32_t bem;
     double self_eps;
+    double theta;
 } fmm_params;
 
 /* Krylov parameters: tol > 0 (relative true residual ||b - Ax||/||b||),

@@ -41,7 +41,8 @@ class fmm_problem(ctypes.Structure):
 
 class fmm_params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("leaf", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("bem", ctypes.c_int32), ("self_eps", ctypes.c_double)]
+                ("bem", ctypes.c_int32), ("self_eps", ctypes.c_double),
+                ("theta", ctypes.c_double)]
 
 
 class gmres_params(ctypes.Structure):
@@ -162,13 +163,13 @@ def fmm_last_error(plan=None):
 
 
 def fmm_setup(kind=FMM_GRID, n=64, p=10, bem=1, self_eps=0.0, x=None, y=None,
-              x0=0.0, y0=0.0, side=1.0, leaf=64, prec=FMM_FP64, stream=None):
+              x0=0.0, y0=0.0, side=1.0, leaf=64, prec=FMM_FP64, theta=0.0, stream=None):
     L = load_library()
     prob = fmm_problem(kind, n, None, None, x0, y0, side)
     if kind == FMM_POINTS:
         prob.x = _dptr(x, "x", n).value
         prob.y = _dptr(y, "y", n).value
-    prm = fmm_params(p, leaf, prec, bem, self_eps)
+    prm = fmm_params(p, leaf, prec, bem, self_eps, theta)
     out = ctypes.c_void_p()
     code = L.fmm_setup(ctypes.byref(prob), ctypes.byref(prm), _stream(stream), ctypes.byref(out))
     _check(code, None)

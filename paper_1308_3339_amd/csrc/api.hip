@@ -92,35 +92,45 @@ static int build_tables(fmm_plan *pl)
                 l2l[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
             }
     }
-    // M2L Hankel generators for source offsets (dx, dy) in [-3, 3]^2 (source
-    // cell = target cell + (dx, dy)); the expansion variable of Sec. 5.3 is
-    // z_{Lambda M} = target centre - source centre = -(dx + i dy) cell widths
-    const int nh = 2 * p - 1;
-    std::vector<double2> hank((size_t)49 * nh, double2{0.0, 0.0});
-    for (int dy = -3; dy <= 3; ++dy)
-        for (int dx = -3; dx <= 3; ++dx) {
-            if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+    // M2L Hankel generators for source offsets (dx, dy) in [-R, R]^2, R =
+    // 2K + 1 (source cell = target cell + (dx, dy)); the expansion variable
+    // of Sec. 5.3 is z_{Lambda M} = target centre - source centre = -(dx + i dy)
+    // cell widths.  Offsets of the near disk are never used.
+    const int nh = 2 * p - 1, K = pl->K, R = 2 * K + 1, RD = 2 * R + 1;
+    std::vector<double2> hank((size_t)RD * RD * nh, double2{0.0, 0.0});
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            if (pl->in_near(dx, dy)) continue;
             const cd d(-(double)dx, -(double)dy);
-            const size_t o = (size_t)((dy + 3) * 7 + dx + 3) * nh;
+            const size_t o = (size_t)((dy + R) * RD + dx + R) * nh;
             hank[o] = double2{-std::log(std::abs(d)), 0.0};
             for (int m = 1; m < nh; ++m) {
                 const cd v = factorial(m - 1) / ipow(d, m);
                 hank[o + m] = double2{v.real(), v.imag()};
             }
         }
-    // interaction-list offsets per parity class (children of the parent's
-    // 3x3 neighbourhood that are not adjacent to the target)
-    std::vector<int4> offs((size_t)4 * 27);
+    // interaction-list offsets per parity class: children of the parent's
+    // near set that are not in the target's own near set (Sec. 5.2; with the
+    // 3x3 near set of the list rule these are the 27 of the paper's Fig. 3,
+    // with a MAC theta the traversal's equivalent lists on the uniform tree)
+    std::vector<std::vector<int4>> cls(4);
     for (int w = 0; w < 4; ++w) {
         const int px = w & 1, py = w >> 1;
-        int c = 0;
-        for (int dy = -2 - py; dy <= 3 - py; ++dy)
-            for (int dx = -2 - px; dx <= 3 - px; ++dx) {
-                if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
-                offs[(size_t)w * 27 + c++] = int4{dx, dy, (dy + 3) * 7 + dx + 3, 0};
+        for (int dy = -2 * K - py; dy <= 2 * K + 1 - py; ++dy)
+            for (int dx = -2 * K - px; dx <= 2 * K + 1 - px; ++dx) {
+                if (pl->in_near(dx, dy)) continue;
+                // parent offset of the source
+                const int Dx = (dx + px) >> 1, Dy = (dy + py) >> 1;
+                if (!pl->in_near(Dx, Dy)) continue;
+                cls[w].push_back(int4{dx, dy, (dy + R) * RD + dx + R, 0});
             }
-        if (c != 27) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
     }
+    for (int w = 1; w < 4; ++w)
+        if (cls[w].size() != cls[0].size()) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
+    pl->nlist = (int)cls[0].size();
+    if (K == 1 && pl->nlist != 27) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
+    std::vector<int4> offs;
+    for (int w = 0; w < 4; ++w) offs.insert(offs.end(), cls[w].begin(), cls[w].end());
     std::vector<double> an(p), bk(p);
     for (int k = 0; k < p; ++k) {
         an[k] = ((k & 1) ? -1.0 : 1.0) / factorial(k);
@@ -138,20 +148,25 @@ static int build_tables(fmm_plan *pl)
             l2p[(size_t)j * p + k] = double2{pk.real(), pk.imag()};
         }
     }
-    // near-field kernel table
-    std::vector<double> kt(31 * 31);
+    // near-field kernel table: lattice offsets within the (2K+1)^2 leaves
+    // around a leaf, |dx|, |dy| <= 8K + 7 (side 31 for K = 1)
+    const int KC = 8 * K + 7, KS = 2 * KC + 1;
+    std::vector<double> kt((size_t)KS * KS);
     const double h = pl->h;
-    for (int dy = -15; dy <= 15; ++dy)
-        for (int dx = -15; dx <= 15; ++dx) {
+    for (int dy = -KC; dy <= KC; ++dy)
+        for (int dx = -KC; dx <= KC; ++dx) {
             const double v = (dx == 0 && dy == 0)
                                  ? std::log(pl->self_eps * h)
                                  : std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
-            kt[(dy + 15) * 31 + dx + 15] = v;
+            kt[(size_t)(dy + KC) * KS + dx + KC] = v;
         }
-    std::vector<double> rt(17 * 17, 0.0);
-    for (int dy = 0; dy <= 16; ++dy)
-        for (int dx = 0; dx <= 16; ++dx)
-            if (dx || dy) rt[dy * 17 + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
+    // ring node to grid node: |dx|, |dy| <= 8(K + 1) (side 17 for K = 1)
+    const int RS = 8 * K + 9;
+    std::vector<double> rt((size_t)RS * RS, 0.0);
+    for (int dy = 0; dy < RS; ++dy)
+        for (int dx = 0; dx < RS; ++dx)
+            if (dx || dy) rt[(size_t)dy * RS + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
+    // the reduced-precision leaf kernels exist for the 3x3 near set only
     std::vector<float> kt32(kt.begin(), kt.end());
     const int prow = 16 * ((2 * p + 15) / 16);
     std::vector<float> p2m32((size_t)prow * 64, 0.0f);
@@ -220,16 +235,17 @@ static int build_levels_and_work(fmm_plan *pl)
                 all.push_back(it);
             }
         // strips of cells whose lists can hold a boundary cell of level l (those
-        // within 3 cells of the boundary): (level, side | depth << 2, start, end),
-        // 64 lanes per item stepping by 2 from start
-        if (nc <= 8) {
+        // within 2K + 1 cells of the boundary): (level, side | depth << 2,
+        // start, end), 64 lanes per item stepping by 2 from start
+        const int band = 2 * pl->K + 2;
+        if (nc <= 2 * band) {
             for (int d = 0; d < nc; ++d)
                 for (int par = 0; par < 2; ++par) ring.push_back(int4{l, 0 | (d << 2), par, nc});
         } else {
             for (int side = 0; side < 4; ++side)
-                for (int d = 0; d < 4; ++d)
+                for (int d = 0; d < band; ++d)
                     for (int par = 0; par < 2; ++par) {
-                        const int lo = (side & 1) ? 4 : 0, hi = (side & 1) ? nc - 4 : nc;
+                        const int lo = (side & 1) ? band : 0, hi = (side & 1) ? nc - band : nc;
                         for (int a0 = lo + par; a0 < hi; a0 += 128)
                             ring.push_back(int4{l, side | (d << 2), a0, hi});
                     }
@@ -304,6 +320,13 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
         return fail(nullptr, FMM_ERR_UNSUPPORTED, "reduced precision is built for GRID plans");
     if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
         return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
+    if (!(prm->theta == 0.0 || (prm->theta >= kThetaMin && prm->theta <= 1.0)))
+        return fail(nullptr, FMM_ERR_ARG, "theta must be 0 (interaction lists) or in [0.3, 1]");
+    const int Kt = near_radius(prm->theta);
+    if (Kt > 1 && (prob->kind != FMM_GRID || prm->prec != FMM_FP64 || prm->p > kThetaPMax))
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "theta < 1/sqrt(2) is built for FP64 GRID plans with p <= 12");
+    if (Kt > 1 && (int64_t)prm->p * (16 + 4 * Kt) * (16 + 4 * Kt) * 16 > kM2LMaxLds)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "p too large for this theta (M2L source tile exceeds LDS)");
     hipStream_t s = (hipStream_t)stream;
     fmm_plan *pl = new (std::nothrow) fmm_plan();
     if (!pl) return fail(nullptr, FMM_ERR_ALLOC, "host allocation failed");
@@ -312,6 +335,7 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     pl->p = prm->p;
     pl->prec = prm->prec;
     pl->bem = prm->bem ? 1 : 0;
+    pl->set_theta(prm->theta);
     {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) == hipSuccess &&

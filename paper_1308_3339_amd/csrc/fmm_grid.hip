@@ -202,8 +202,9 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 // A block is a 16x16 tile of target cells (the whole level if it is
 // smaller) with 12 waves: wave w serves parity class w&3 (cells that share
 // one list shape, so the offset and its Hankel generators are wave-uniform)
-// and third w>>2 of the 27-entry list.  Sources (20x20 cells around the
-// tile) are staged once in LDS, split by parity so that the per-offset LDS
+// and third w>>2 of the class's nlist-entry list (27 with the list rule, more
+// with a MAC theta).  Sources (the tile plus a halo of 2K cells, 20x20 for
+// K = 1) are staged once in LDS, split by parity so that the per-offset LDS
 // reads of a wave are consecutive; the three thirds are summed in LDS in a
 // fixed order.  R is the arithmetic type of the translation (double, or
 // float for the FP32 variant; the level-scaled expansions and generators
@@ -216,7 +217,8 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                                              const typename Cplx<R>::T *__restrict__ hank,
                                              const int4 *__restrict__ offs,
                                              const double *__restrict__ a_n,
-                                             const double *__restrict__ b_k)
+                                             const double *__restrict__ b_k, int nlist,
+                                             int halo)
 {
     using C = typename Cplx<R>::T;
     extern __shared__ __align__(16) unsigned char sm_raw[];
@@ -224,7 +226,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     const M2LItem it = items[blockIdx.x];
     const int l = it.level, nc = 1 << l;
     const int tw = nc < 16 ? nc : 16;
-    const int RW = tw + 4, RH = RW >> 1, SUB = RH * RH, RR = RW * RW;
+    const int RW = tw + 2 * halo, RH = RW >> 1, SUB = RH * RH, RR = RW * RW;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l];
     for (int e0 = threadIdx.x; e0 < P * RR; e0 += 768 * 6) {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
             if (e < P * RR) {
                 const int k = e / RR, r = e - k * RR;
                 const int sy = r / RW, sx = r - sy * RW;
-                const int gx = it.tx0 - 2 + sx, gy = it.ty0 - 2 + sy;
+                const int gx = it.tx0 - halo + sx, gy = it.ty0 - halo + sy;
                 if (gx >= 0 && gx < nc && gy >= 0 && gy < nc) v[i] = Ml[k * ncell + (int64_t)gy * nc + gx];
             }
         }
@@ -265,12 +267,14 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k].x = acc[k].y = (R)0;
     const R logw = (R)lv.logw[l];
-    const int4 *ol = offs + cls * 27 + grp * 9;
+    const int chunk = (nlist + 2) / 3;
+    const int4 *ol = offs + cls * nlist + grp * chunk;
+    const int nown = min(chunk, nlist - grp * chunk);
     if (active) {
-        for (int o = 0; o < 9; ++o) {
+        for (int o = 0; o < nown; ++o) {
             const int4 od = ol[o];
             const C *H = hank + od.z * (2 * P - 1);
-            const int sx = ltx + od.x + 2, sy = lty + od.y + 2;
+            const int sx = ltx + od.x + halo, sy = lty + od.y + halo;
             const int sidx = ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1);
             C m[P];
 #pragma unroll
@@ -445,7 +449,16 @@ struct LeafArgs {
     const double2 *p2m;   // [P][64]
     LevelInfo lv;
     int n, nl, L, far;
+    // near set (Sec. 5.2): radius K leaves; leaves (a, b) with |a| <= kx(|b|)
+    // are near, kx(b) + 1 packed in 4 bits each (near_kx); ktab side ks = 16K
+    // + 15, rtab side rs = 8K + 9
+    int K, kxp, ks, rs;
 };
+
+__device__ __forceinline__ int near_kx(int kxp, int b)
+{
+    return ((kxp >> (4 * b)) & 15) - 1;
+}
 
 template <int P>
 __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
@@ -511,6 +524,107 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
 #pragma unroll 8
             for (int j = 0; j < 64; ++j) {
                 const double v = sq[leaf_tile_idx(j, 0, 0) + cleaf];
+                const double2 w = Wk[j];
+                mx = fma(w.x, v, mx);
+                my = fma(w.y, v, my);
+            }
+            if (active) Ml[k * ncell + cell] = make_double2(mx * a.qscale, my * a.qscale);
+        }
+    }
+    if (!active) return;
+    const double qs = -a.qscale * kInv2Pi;
+    double *ur = a.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
+}
+
+// Leaf stage with the near set of a MAC theta (Sec. 5.2): on the uniform tree
+// the dual tree traversal's P2P pairs of a leaf are the leaves of the
+// lattice disk |d|^2 <= 2/theta^2, radius K <= 4 leaves, instead of the 3x3
+// block.  Same organisation as k_leaf_grid (block = 8x8 leaves, lane = leaf,
+// wave = target row, T rows by scalar loads) with the (8+2K)^2-leaf q tile in
+// LDS and, per row of leaf offsets, the column range from the packed kx.
+// Tile layout as leaf_tile_idx, with a column slot CW >= 8 + 2K chosen so that
+// the row stride 4 CW is 8 or 24 mod 32 doubles (distinct banks for the 8x8
+// window a wave reads).
+template <int K>
+struct WideTile {
+    static constexpr int TW = 8 + 2 * K;
+    static constexpr int CW = K <= 3 ? 14 : 18;
+    static constexpr int RS = 4 * CW;
+    static constexpr int PS = TW * RS;
+    static constexpr int SIZE = 16 * PS;
+    __device__ static constexpr int idx(int pos, int r, int c)
+    {
+        return (pos >> 2) * PS + r * RS + (pos & 3) * CW + c;
+    }
+};
+
+template <int P, int K>
+__global__ __launch_bounds__(512) void k_leaf_wide(LeafArgs a)
+{
+    using W = WideTile<K>;
+    __shared__ double sq[W::SIZE];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, nl = a.nl;
+    const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
+    const int X0 = (TX0 - K) * 8, Y0 = (TY0 - K) * 8;
+    constexpr int PW = 8 * W::TW, NE = PW * PW, NB = 13;
+    for (int base = 0; base < NE; base += 512 * NB) {
+        double v[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = base + tid + 512 * i;
+            const int yy = e / PW, xx = e - yy * PW;
+            const int gx = X0 + xx, gy = Y0 + yy;
+            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = base + tid + 512 * i;
+            const int yy = e / PW, xx = e - yy * PW;
+            if (e < NE) sq[W::idx((yy & 7) * 8 + (xx & 7), yy >> 3, xx >> 3)] = v[i];
+        }
+    }
+    __syncthreads();
+    const int lx = lane & 7, ly = lane >> 3;
+    const int gLx = TX0 + lx, gLy = TY0 + ly;
+    const bool active = gLx < nl && gLy < nl;
+    const int ty = wave;
+    const int cleaf = W::idx(0, ly + K, lx + K);
+    constexpr int KC = 8 * K + 7, KS = 2 * KC + 1;
+    double acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+    const double *__restrict__ kt = a.ktab;
+    for (int oy = -K; oy <= K; ++oy) {
+        const int kxo = near_kx(a.kxp, oy < 0 ? -oy : oy);
+        for (int sy = 0; sy < 8; ++sy) {
+            const double *T0 = kt + (8 * oy + sy - ty + KC) * KS + KC - 7;
+            for (int ox = -kxo; ox <= kxo; ++ox) {
+                double w0[15];
+#pragma unroll
+                for (int c = 0; c < 15; ++c) w0[c] = T0[8 * ox + c];
+                const int sl = cleaf + oy * W::RS + ox;
+#pragma unroll
+                for (int sx = 0; sx < 8; ++sx) {
+                    const double v = sq[W::idx(sy * 8 + sx, 0, 0) + sl];
+#pragma unroll
+                    for (int tx = 0; tx < 8; ++tx) acc[tx] = fma(w0[sx - tx + 7], v, acc[tx]);
+                }
+            }
+        }
+    }
+    if (a.M) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        double2 *Ml = a.M + a.lv.off[a.L];
+        for (int k = wave; k < P; k += 8) {
+            const double2 *__restrict__ Wk = a.p2m + k * 64;
+            double mx = 0.0, my = 0.0;
+#pragma unroll 8
+            for (int j = 0; j < 64; ++j) {
+                const double v = sq[W::idx(j, 0, 0) + cleaf];
                 const double2 w = Wk[j];
                 mx = fma(w.x, v, mx);
                 my = fma(w.y, v, my);
@@ -842,9 +956,9 @@ __device__ __forceinline__ double l2p_eval(const double2 *__restrict__ Lc, doubl
 
 // ---------------------------------------------------------------------------
 // Pass-1 potential at the 4n ring nodes, one wave per node: near field from
-// the (at most 6) in-domain leaves of the 3x3 block around the attached
-// boundary leaf, split over the lanes and summed with shuffles; far field by
-// L2P from that leaf's local expansion.
+// the in-domain leaves of the near set around the attached boundary leaf (at
+// most 6 of the 3x3 block with the list rule), split over the lanes and
+// summed with shuffles; far field by L2P from that leaf's local expansion.
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__restrict__ phi)
@@ -857,14 +971,16 @@ __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__rest
     const int lx = leaf_of(Ix, nl), ly = leaf_of(Iy, nl);
     double near = 0.0;
     const int ia = lane & 7, jb = lane >> 3;
-    for (int b = -1; b <= 1; ++b)
-        for (int c = -1; c <= 1; ++c) {
+    for (int b = -a.K; b <= a.K; ++b) {
+        const int kb = near_kx(a.kxp, b < 0 ? -b : b);
+        for (int c = -kb; c <= kb; ++c) {
             const int qx = lx + c, qy = ly + b;
             if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
             const int gx = qx * 8 + ia, gy = qy * 8 + jb;
             const int dx = abs(Ix - (gx + 1)), dy = abs(Iy - (gy + 1));
-            near = fma(a.q[(size_t)gy * n + gx], a.rtab[dy * 17 + dx], near);
+            near = fma(a.q[(size_t)gy * n + gx], a.rtab[dy * a.rs + dx], near);
         }
+    }
     near = wave_sum(near);
     double far = 0.0;
     if (a.far && lane == 0) {
@@ -965,8 +1081,8 @@ __global__ __launch_bounds__(256) void k_m2m_up_ring(const double *__restrict__ 
 }
 
 // Pass 2 M2L: the multipoles are non-zero only in the boundary cells of each
-// level, and those are in the interaction lists of cells at most three cells
-// from the boundary.  A wave takes one row of that band along one side
+// level, and those are in the interaction lists of cells at most 2K + 1 cells
+// from the boundary (three with the list rule).  A wave takes one row of that band along one side
 // (item = level, side, depth d, first coordinate along the side; lanes step
 // by two, so all lanes share a parity class and hence one list).  For each
 // list entry the source's boundary test is uniform except at the ends of
@@ -982,7 +1098,7 @@ __global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items
                                                   const double2 *__restrict__ hank,
                                                   const int4 *__restrict__ offs,
                                                   const double *__restrict__ a_n,
-                                                  const double *__restrict__ b_k)
+                                                  const double *__restrict__ b_k, int nlist)
 {
     // one item per block; wave w takes list entries w, w+4, ... and the four
     // partial sums are added in LDS in a fixed order
@@ -1000,12 +1116,12 @@ __global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l];
     const int cls = __builtin_amdgcn_readfirstlane(((iy & 1) * 2 + (ix & 1)));
-    const int4 *ol = offs + cls * 27;
+    const int4 *ol = offs + cls * nlist;
     const double logw = lv.logw[l];
     double2 acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
-    for (int o = w; o < 27; o += 4) {
+    for (int o = w; o < nlist; o += 4) {
         const int4 od = ol[o];
         const int sx = ix + od.x, sy = iy + od.y;
         const bool use = valid && sx >= 0 && sy >= 0 && sx < nc && sy < nc &&
@@ -1122,12 +1238,12 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
 }
 
 // Pass 2 near field: u += -(1/2pi) sum over the ring nodes attached to the
-// 3x3 leaves around the target's leaf.  Ring node k of a side attaches to
-// the boundary leaf it borders, so for each side the sum is a window of at
-// most 24 consecutive nodes (the three leaves along that side) with a kernel
-// value from the lattice table, and only targets within two leaves of a
-// side see it.  One thread per point of the 16-deep band (every point when
-// n <= 32).
+// leaves of the near set around the target's leaf.  Ring node k of a side
+// attaches to the boundary leaf it borders, so for each side the sum is a
+// window of consecutive nodes (the near leaves along that side: three, 24
+// nodes, with the list rule) with a kernel value from the lattice table, and
+// only targets within K + 1 leaves of a side see it.  One thread per point
+// of the 8(K+1)-deep band (every point when the band covers the grid).
 __device__ __forceinline__ double side_window(const double *__restrict__ rqs,
                                               const double *__restrict__ trow, int k0, int k1,
                                               int c, int sgn)
@@ -1141,16 +1257,17 @@ __device__ __forceinline__ double side_window(const double *__restrict__ rqs,
 
 __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
                                                     const double *__restrict__ rq,
-                                                    const double *__restrict__ rtab, int n, int nl)
+                                                    const double *__restrict__ rtab, int n, int nl,
+                                                    int K, int kxp, int rs)
 {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int B = 8 * (K + 1);
     int gx, gy;
-    if (n <= 32) {
+    if (n <= 2 * B) {
         if (idx >= (int64_t)n * n) return;
         gx = (int)(idx % n);
         gy = (int)(idx / n);
     } else {
-        const int B = 16;
         const int64_t strip = (int64_t)B * n, side = (int64_t)B * (n - 2 * B);
         if (idx < strip) {
             gy = (int)(idx / n); gx = (int)(idx % n);
@@ -1168,18 +1285,32 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
         }
     }
     const int lx = gx >> 3, ly = gy >> 3;
-    // lattice range [a, b) along a side covered by the leaves l-1..l+1
-    const int ax = 8 * max(lx - 1, 0), bx = 8 * min(lx + 1, nl - 1) + 8;
-    const int ay = 8 * max(ly - 1, 0), by = 8 * min(ly + 1, nl - 1) + 8;
+    // lattice range [a, b) along a side covered by the near leaves l-k..l+k,
+    // k = kx(distance of the target's leaf from that side)
+    auto lo = [&](int l, int k) { return 8 * max(l - k, 0); };
+    auto hi = [&](int l, int k) { return 8 * min(l + k, nl - 1) + 8; };
     double near = 0.0;
-    if (ly <= 1)        // bottom: node k at (k+1, 0)
-        near += side_window(rq, rtab + (gy + 1) * 17, ax, bx, gx, 1);
-    if (lx >= nl - 2)   // right: node k at (n+1, k+1)
-        near += side_window(rq + n, rtab + (n - gx) * 17, ay, by, gy, 1);
-    if (ly >= nl - 2)   // top: node k at (n-k, n+1); Ix-1 = n-1-k in [ax, bx)
-        near += side_window(rq + 2 * n, rtab + (n - gy) * 17, n - bx, n - ax, gx - n + 1, -1);
-    if (lx <= 1)        // left: node k at (0, n-k); Iy-1 = n-1-k in [ay, by)
-        near += side_window(rq + 3 * n, rtab + (gx + 1) * 17, n - by, n - ay, gy - n + 1, -1);
+    const int db = ly, dr = nl - 1 - lx, dt = nl - 1 - ly, dl = lx;
+    if (db <= K) {      // bottom: node k at (k+1, 0)
+        const int k = near_kx(kxp, db);
+        if (k >= 0) near += side_window(rq, rtab + (gy + 1) * rs, lo(lx, k), hi(lx, k), gx, 1);
+    }
+    if (dr <= K) {      // right: node k at (n+1, k+1)
+        const int k = near_kx(kxp, dr);
+        if (k >= 0) near += side_window(rq + n, rtab + (n - gx) * rs, lo(ly, k), hi(ly, k), gy, 1);
+    }
+    if (dt <= K) {      // top: node k at (n-k, n+1); Ix-1 = n-1-k in [ax, bx)
+        const int k = near_kx(kxp, dt);
+        if (k >= 0)
+            near += side_window(rq + 2 * n, rtab + (n - gy) * rs, n - hi(lx, k), n - lo(lx, k),
+                                gx - n + 1, -1);
+    }
+    if (dl <= K) {      // left: node k at (0, n-k); Iy-1 = n-1-k in [ay, by)
+        const int k = near_kx(kxp, dl);
+        if (k >= 0)
+            near += side_window(rq + 3 * n, rtab + (gx + 1) * rs, n - hi(ly, k), n - lo(ly, k),
+                                gy - n + 1, -1);
+    }
     u[(size_t)gy * n + gx] += -near * kInv2Pi;
 }
 
@@ -1215,17 +1346,18 @@ template <int P>
 static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
                        const M2LItem *items, int nitems, hipStream_t s, bool timed)
 {
-    const size_t shm = (size_t)P * 400 * sizeof(double2);
+    const int rw = 16 + 4 * pl->K;
+    const size_t shm = (size_t)P * rw * rw * sizeof(double2);
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
         if (pl->prec != FMM_FP64)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems), dim3(768), shm / 2, s, items, M, Lm,
                                pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
-                               pl->tab.m2l_b);
+                               pl->tab.m2l_b, pl->nlist, 2 * pl->K);
         else
             hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems), dim3(768), shm, s, items, M, Lm,
                                pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
-                               pl->tab.m2l_b);
+                               pl->tab.m2l_b, pl->nlist, 2 * pl->K);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (const auto &c : down_chunks(pl->L))
@@ -1252,7 +1384,22 @@ static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *
     a.nl = pl->nl;
     a.L = pl->L;
     a.far = far ? 1 : 0;
+    a.K = pl->K;
+    a.kxp = near_kx_packed(pl);
+    a.ks = 16 * pl->K + 15;
+    a.rs = 8 * pl->K + 9;
     return a;
+}
+
+// launches the leaf kernel of the plan's near radius (K >= 2: MAC theta)
+template <int P>
+static void launch_leaf_wide(fmm_plan *pl, dim3 gl, const LeafArgs &a, hipStream_t s)
+{
+    if constexpr (P <= kThetaPMax) {
+        if (pl->K == 2) hipLaunchKernelGGL((k_leaf_wide<P, 2>), gl, dim3(512), 0, s, a);
+        else if (pl->K == 3) hipLaunchKernelGGL((k_leaf_wide<P, 3>), gl, dim3(512), 0, s, a);
+        else if (pl->K == 4) hipLaunchKernelGGL((k_leaf_wide<P, 4>), gl, dim3(512), 0, s, a);
+    }
 }
 
 template <int P>
@@ -1273,6 +1420,8 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
         else if (fp32)
             hipLaunchKernelGGL(k_leaf_mfma32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32,
                                pl->tab.p2m32);
+        else if (pl->K > 1)
+            launch_leaf_wide<P>(pl, gl, a, s);
         else
             hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(512), 0, s, a);
     }
@@ -1311,10 +1460,11 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hip
         hipLaunchKernelGGL(k_m2m_up_ring<P>, dim3(nt > 1 ? 4 * (nt - 1) : 1), dim3(256), 0, s,
                            pl->ring_q, pl->ws.M2, pl->tab.m2m, pl->lv, (int)pl->n, L);
         run_m2m_from<P>(pl, pl->ws.M2, L - 3, 1, s);
-        // M2L from boundary cells into the three-cell band of every level
+        // M2L from boundary cells into the (2K+2)-cell band of every level
         hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells), dim3(256), 0, s,
                            pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
-                           pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b);
+                           pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+                           pl->nlist);
         // downward: levels 2..L-3 by k_down, the last three inside the far-field kernel
         const bool chain = L >= 5;
         const int last = chain ? L - 3 : L;
@@ -1325,10 +1475,11 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hip
         hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
                            pl->tab.l2l, chain ? 1 : 0, with_volume ? pl->ws.Lt : nullptr);
     }
-    const int n = (int)pl->n;
-    const int64_t nband = n <= 32 ? (int64_t)n * n : (int64_t)4 * 16 * n - 4 * 16 * 16;
+    const int n = (int)pl->n, B = 8 * (pl->K + 1);
+    const int64_t nband = n <= 2 * B ? (int64_t)n * n : (int64_t)4 * B * n - 4 * B * B;
     hipLaunchKernelGGL(k_pass2_near, dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s, u,
-                       pl->ring_q, pl->tab.rtab, n, nl);
+                       pl->ring_q, pl->tab.rtab, n, nl, pl->K, near_kx_packed(pl),
+                       8 * pl->K + 9);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }
@@ -1374,11 +1525,18 @@ int points_m2l_down(fmm_plan *pl, hipStream_t s)
 template <int P>
 static int m2l_attr_p(fmm_plan *pl)
 {
-    const int shm = P * 400 * (int)sizeof(double2);
+    // the limit is a property of the kernel, shared by every plan of this p:
+    // raise it to the largest tile any plan has needed so far
+    static int high[kPMax + 1] = {0};
+    const int rw = 16 + 4 * pl->K;
+    const int shm = P * rw * rw * (int)sizeof(double2);
+    if ((int64_t)shm > kM2LMaxLds) return fail(pl, FMM_ERR_UNSUPPORTED, "M2L source tile exceeds LDS");
+    if (shm <= high[P]) return FMM_OK;
     FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P, double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm));
     FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P, float>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm / 2));
+    high[P] = shm;
     return FMM_OK;
 }
 

@@ -28,6 +28,25 @@ constexpr int kPMax = 20;
 constexpr int kMaxLevels = 24;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+// MAC theta (Sec. 5.2): smallest accepted value (near radius K <= 4) and the
+// LDS the M2L kernel may use for its source tile
+constexpr double kThetaMin = 0.3;
+constexpr int kMaxK = 4;
+constexpr int kThetaPMax = 12;   // largest p built for theta < 1/sqrt(2)
+constexpr int64_t kM2LMaxLds = 160 * 1024;
+
+// Near radius in leaves of a MAC theta on the uniform tree: two cells of one
+// level, radius r = w/sqrt2 each, are well separated when 2r < theta |d| w,
+// i.e. |d|^2 > 2/theta^2; K is the largest k with (k, 0) not separated.
+// theta = 0 selects the interaction lists of the list rule (K = 1).
+inline int near_radius(double theta)
+{
+    if (theta <= 0.0) return 1;
+    const double lim = 2.0 / (theta * theta);
+    int k = 1;
+    while ((double)((k + 1) * (k + 1)) <= lim) ++k;
+    return k;
+}
 
 // Work item of the all-levels M2L launch: a tile of target cells at a level.
 struct M2LItem {
@@ -82,6 +101,29 @@ struct fmm_plan {
     int prec = FMM_FP64;  // FMM_FP32: P2P and M2L in FP32
     int ncu = 256;        // compute units of the plan's device
     int bem = 1;
+    // well-separatedness: theta = 0 is the list rule (3x3 near leaves);
+    // otherwise the MAC of the dual tree traversal, whose near set on the
+    // uniform tree is the lattice disk |d|^2 <= 2/theta^2 (radius K leaves,
+    // kx[b] = largest |a| with (a, b) near), and nlist M2L offsets per cell
+    double theta = 0.0;
+    int K = 1;
+    int kx[fmmprec::kMaxK + 1] = {1, 1, 1, 1, 1};
+    int nlist = 27;
+    bool in_near(int dx, int dy) const
+    {
+        if (theta <= 0.0) return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
+        return (double)(dx * dx + dy * dy) <= 2.0 / (theta * theta);
+    }
+    void set_theta(double t)
+    {
+        theta = t;
+        K = fmmprec::near_radius(t);
+        for (int b = 0; b <= fmmprec::kMaxK; ++b) {
+            int a = -1;
+            while (a + 1 <= K && in_near(a + 1, b)) ++a;
+            kx[b] = a;   // -1: no near leaf at distance b
+        }
+    }
     double h = 0.0;       // GRID mesh width
     double self_eps = 0.0;
     double x0 = 0.0, y0 = 0.0, side = 1.0;  // tree root square
@@ -213,6 +255,15 @@ int tune_vector_blocks(fmm_plan *plan, hipStream_t s, int *chosen);
 void drop_step_graphs(fmm_plan *plan);
 int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
                       double *sigma, hipStream_t s);
+
+// kx(b) + 1 of the plan's near set in 4 bits per b = 0..kMaxK (the form the
+// kernels take it in: a runtime shift instead of an indexed array)
+inline int near_kx_packed(const fmm_plan *pl)
+{
+    int v = 0;
+    for (int b = 0; b <= kMaxK; ++b) v |= (pl->kx[b] + 1) << (4 * b);
+    return v;
+}
 
 }  // namespace fmmprec
 

@@ -32,11 +32,11 @@ def test_version_string():
     assert "gfx950" in fp.fmm_version()
 
 
-def _setup_raw(kind=0, n=64, p=10, leaf=64, prec=0, bem=1, eps=0.0):
+def _setup_raw(kind=0, n=64, p=10, leaf=64, prec=0, bem=1, eps=0.0, theta=0.0):
     from paper_1308_3339_amd._binding import fmm_params, fmm_problem
     lib = fp.load_library()
     prob = fmm_problem(kind, n, None, None, 0.0, 0.0, 1.0)
-    prm = fmm_params(p, leaf, prec, bem, eps)
+    prm = fmm_params(p, leaf, prec, bem, eps, theta)
     out = ctypes.c_void_p(123)
     code = lib.fmm_setup(ctypes.byref(prob), ctypes.byref(prm), None, ctypes.byref(out))
     return code, out.value, lib.fmm_last_error(None).decode()
@@ -50,6 +50,9 @@ def _setup_raw(kind=0, n=64, p=10, leaf=64, prec=0, bem=1, eps=0.0):
     (dict(n=4), "8 * 2^L"),
     (dict(kind=7), "kind"),
     (dict(eps=-1.0), "self_eps"),
+    (dict(theta=0.2), "theta"),
+    (dict(theta=1.5), "theta"),
+    (dict(theta=-0.5), "theta"),
 ])
 def test_setup_rejects_bad_arguments(kw, frag):
     code, ptr, msg = _setup_raw(**kw)
@@ -61,6 +64,16 @@ def test_setup_rejects_bad_arguments(kw, frag):
 def test_setup_rejects_unbuilt_precision():
     code, ptr, msg = _setup_raw(prec=3)
     assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
+
+
+@pytest.mark.parametrize("kw", [dict(theta=0.4, prec=1), dict(theta=0.4, prec=2),
+                                dict(theta=0.4, kind=1), dict(theta=0.3, p=11),
+                                dict(theta=0.4, p=14)])
+def test_setup_rejects_unbuilt_theta_combinations(kw):
+    # small theta: FP64 GRID plans only, and the M2L source tile must fit in LDS
+    code, ptr, msg = _setup_raw(**kw)
+    assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
+    assert "theta" in msg
 
 
 def test_null_arguments():
