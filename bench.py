@@ -400,6 +400,64 @@ def main():
                                   "mfma_flops_per_algorithmic_flop": mfma_per_flop,
                                   "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)}}
 
+    def mac_block(p_t, theta):
+        """MAC theta (Sec. 5.2): the 2048^2 solve with the dual tree
+        traversal's near disk and lists, next to the list-rule plan."""
+        pl = fp.fmm_setup(n=n, p=p_t, bem=1, theta=theta)
+        pl.tune()
+        for _ in range(args.warmup):
+            u.zero_()
+            pl.solve(f, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            u.zero_()
+            inf = pl.solve(f, u)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t0
+        pl.stencil_apply(u, w)
+        relv = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
+        pl.profile(fp.STAGES)
+        u.zero_()
+        pl.solve(f, u)
+        prof = pl.profile_read()
+        pl.close()
+        # volume potential against the p = 14 list-rule potential (about 1e-9)
+        uv, ur = torch.empty_like(q), torch.empty_like(q)
+        with fp.fmm_setup(n=n, p=p_t, bem=0, theta=theta) as pv:
+            pv.apply(q, uv)
+        with fp.fmm_setup(n=n, p=14, bem=0) as pr:
+            pr.apply(q, ur)
+        dv = float(torch.linalg.vector_norm(uv - ur) / torch.linalg.vector_norm(ur))
+        # near disk of the theta and the algorithmic flops of the leaf kernel
+        lim = 2.0 / (theta * theta)
+        kk = int(math.floor(math.sqrt(lim)))
+        nl = n // 8
+        pairs = 0
+        for b in range(-kk, kk + 1):
+            for a in range(-kk, kk + 1):
+                if a * a + b * b <= lim:
+                    pairs += (nl - abs(a)) * (nl - abs(b)) * 4096
+        flops_t = 2.0 * pairs + 4.0 * p_t * n * n
+        leaf_ms_t, leaf_n_t = prof.get("LEAF", (0.0, 0))
+        avg = leaf_ms_t / max(leaf_n_t, 1)
+        ach = flops_t / (avg * 1e-3) / 1e12
+        return {"p": p_t, "theta": theta, "near_leaves": sum(
+                    1 for b in range(-kk, kk + 1) for a in range(-kk, kk + 1) if a * a + b * b <= lim),
+                "solves_per_s": round(args.steps / tv, 4),
+                "ms_per_step": round(1000.0 * tv / args.steps, 4),
+                "speedup_vs_list_rule_p10": round((args.steps / tv) / solves_per_s, 3),
+                "iters": inf["iters"], "true_rel_res": relv,
+                "volume_rel_l2_diff_vs_p14": dv,
+                "stages_ms_per_solve": {k: round(v[0], 4) for k, v in prof.items()},
+                "leaf_roofline": {"bound": "alu", "kernel": "k_leaf_wide", "pairs": pairs,
+                                  "avg_launch_ms": round(avg, 5), "achieved": round(ach, 3),
+                                  "unit": "TFLOP/s", "peak": 78.6, "frac": round(ach / 78.6, 4)}}
+
+    log("mac theta")
+    mac = mac_block(6, 0.4)
+    log("mac theta p=6 theta=0.4: %.2f solves/s, %d iterations" % (mac["solves_per_s"],
+                                                                   mac["iters"]))
     log("precision variants")
     variant = variant_block(fp.FMM_FP32, "P2P and P2M as FP32 MFMA contractions, M2L in FP32; "
                             "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1)
@@ -465,6 +523,7 @@ def main():
         "adjoint": adjoint,
         "variable_coefficient": varcoef,
         "batched": batched,
+        "mac_theta": mac,
     }
     plan.close()
     print(json.dumps(res), flush=True)
