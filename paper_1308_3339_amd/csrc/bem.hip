@@ -12,9 +12,21 @@
 //   S^_0 = C0 + C1 + C2 + C3 (real),  S^_2 = C0 - C1 + C2 - C3 (real),
 //   S^_1 = (C0 - C2) + i (C1 - C3) (Hermitian),  S^_3 = conj(S^_1).
 // All three are Hermitian positive definite (S is SPD), so they are inverted
-// once at setup by Gauss-Jordan without pivoting, and every application is
-// a DFT over the four sides, three n x n matrix-vector products and the
-// inverse DFT: 4n^2 doubles read instead of the 16n^2 of a dense inverse.
+// once at setup by Gauss-Jordan without pivoting.
+//
+// The ring is also invariant under the reflections of the square, which
+// reverse the node order along a side (J: k -> n-1-k) and map side s to -s.
+// Hence J S^_0 J = S^_0, J S^_2 J = S^_2 and J S^_1 J = conj(S^_1), and the
+// same holds for the inverses X_m.  In the even/odd basis of each side,
+// Q = [[I, J], [I, -J]] on the two halves of the side, the real blocks split
+// into two (n/2)^2 blocks and the complex one into four real (n/2)^2 blocks
+// (its real part maps even to even and odd to odd, its imaginary part even to
+// odd and odd to even).  Setup folds the inverses into these eight halves
+// (each averaged over the four symmetric copies of its entries, with the 1/2
+// of Q^T Q = 2 I), and an application is a DFT over the sides with the
+// even/odd split, eight (n/2) x (n/2) products and the inverse: 2n^2 doubles
+// read, against 4n^2 for the rotation blocks alone and 16n^2 for a dense
+// inverse.
 #include "fmm_internal.h"
 
 namespace fmmprec {
@@ -117,59 +129,121 @@ __global__ __launch_bounds__(256) void k_gj_upd_cplx(const double2 *__restrict__
     B[e] = v;
 }
 
-// b = -phi: b^_0 = sum_s b_s, b^_2 = sum_s (-1)^s b_s, b^_1 = sum_s i^(-s) b_s
-__global__ void k_bem_rhs(const double *__restrict__ phi, double2 *__restrict__ bh, int n)
-{
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= n) return;
-    const double b0 = -phi[k], b1 = -phi[n + k], b2 = -phi[2 * n + k], b3 = -phi[3 * n + k];
-    bh[k] = make_double2((b0 + b1) + (b2 + b3), 0.0);
-    bh[n + k] = make_double2((b0 - b1) + (b2 - b3), 0.0);
-    bh[2 * n + k] = make_double2(b0 - b2, b3 - b1);
-}
+// Halves of the folded inverses, each (n/2) x (n/2) row-major, in one
+// buffer: X0 even, X0 odd, X2 even, X2 odd, Re X1 even, Re X1 odd,
+// Im X1 (odd -> even), Im X1 (even -> odd).
+enum { kH0E = 0, kH0O, kH2E, kH2O, kH1RE, kH1RO, kH1IEO, kH1IOE, kHalves };
 
-// sigma^ = X b^ for the three blocks: blockIdx.y = 0 (X0), 1 (X2), 2 (X1, complex).
-// One wave per row.
-__global__ __launch_bounds__(256) void k_bem_gemv(const double *__restrict__ X0,
+// Folds the full inverses X0, X2 (real) and X1 (complex) into the halves:
+// for r, c < n/2 with c' = n-1-c, r' = n-1-r,
+//   even = (X[r][c] + X[r][c'] + X[r'][c'] + X[r'][c]) / 4,
+//   odd  = (X[r][c] - X[r][c'] + X[r'][c'] - X[r'][c]) / 4,
+// and for Im X1 (J Im X1 J = -Im X1)
+//   odd -> even = (I[r][c] - I[r][c'] - I[r'][c'] + I[r'][c]) / 4,
+//   even -> odd = (I[r][c] + I[r][c'] - I[r'][c'] - I[r'][c]) / 4.
+__global__ __launch_bounds__(256) void k_bem_fold(const double *__restrict__ X0,
                                                   const double *__restrict__ X2,
                                                   const double2 *__restrict__ X1,
+                                                  double *__restrict__ Xh, int n)
+{
+    const int m = n >> 1;
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (r >= m || c >= m) return;
+    const size_t a = (size_t)r * n + c, b = (size_t)r * n + (n - 1 - c);
+    const size_t d = (size_t)(n - 1 - r) * n + (n - 1 - c), e = (size_t)(n - 1 - r) * n + c;
+    const size_t o = (size_t)r * m + c, hs = (size_t)m * m;
+    Xh[kH0E * hs + o] = 0.25 * ((X0[a] + X0[b]) + (X0[d] + X0[e]));
+    Xh[kH0O * hs + o] = 0.25 * ((X0[a] - X0[b]) + (X0[d] - X0[e]));
+    Xh[kH2E * hs + o] = 0.25 * ((X2[a] + X2[b]) + (X2[d] + X2[e]));
+    Xh[kH2O * hs + o] = 0.25 * ((X2[a] - X2[b]) + (X2[d] - X2[e]));
+    const double2 xa = X1[a], xb = X1[b], xd = X1[d], xe = X1[e];
+    Xh[kH1RE * hs + o] = 0.25 * ((xa.x + xb.x) + (xd.x + xe.x));
+    Xh[kH1RO * hs + o] = 0.25 * ((xa.x - xb.x) + (xd.x - xe.x));
+    Xh[kH1IEO * hs + o] = 0.25 * ((xa.y - xb.y) - (xd.y - xe.y));
+    Xh[kH1IOE * hs + o] = 0.25 * ((xa.y + xb.y) - (xd.y + xe.y));
+}
+
+// b = -phi: b^_0 = sum_s b_s, b^_2 = sum_s (-1)^s b_s, b^_1 = sum_s i^(-s) b_s,
+// then the even/odd split of each mode, b^[k] +- b^[n-1-k] for k < n/2:
+// bh = [mode 0: even | odd][mode 2: even | odd][mode 1: even | odd] (n/2 each)
+__global__ void k_bem_rhs(const double *__restrict__ phi, double2 *__restrict__ bh, int n)
+{
+    const int m = n >> 1;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= m) return;
+    const int kr = n - 1 - k;
+    const double b0 = -phi[k], b1 = -phi[n + k], b2 = -phi[2 * n + k], b3 = -phi[3 * n + k];
+    const double c0 = -phi[kr], c1 = -phi[n + kr], c2 = -phi[2 * n + kr], c3 = -phi[3 * n + kr];
+    const double m0 = (b0 + b1) + (b2 + b3), n0 = (c0 + c1) + (c2 + c3);
+    const double m2 = (b0 - b1) + (b2 - b3), n2 = (c0 - c1) + (c2 - c3);
+    const double2 m1 = make_double2(b0 - b2, b3 - b1), n1 = make_double2(c0 - c2, c3 - c1);
+    bh[k] = make_double2(m0 + n0, 0.0);
+    bh[m + k] = make_double2(m0 - n0, 0.0);
+    bh[n + k] = make_double2(m2 + n2, 0.0);
+    bh[n + m + k] = make_double2(m2 - n2, 0.0);
+    bh[2 * n + k] = make_double2(m1.x + n1.x, m1.y + n1.y);
+    bh[2 * n + m + k] = make_double2(m1.x - n1.x, m1.y - n1.y);
+}
+
+// The products of the folded inverses with the split right-hand side, one
+// wave per row of a half (n/2 rows per group), in the layout of bh:
+//   y = 0: X0 even . e0,  1: X0 odd . o0,  2: X2 even . e2,  3: X2 odd . o2,
+//   4: even part of mode 1 = Re X1 even . e1 + i Im X1 (odd -> even) . o1,
+//   5: odd part of mode 1  = i Im X1 (even -> odd) . e1 + Re X1 odd . o1.
+__global__ __launch_bounds__(256) void k_bem_gemv(const double *__restrict__ Xh,
                                                   const double2 *__restrict__ bh,
                                                   double2 *__restrict__ sh, int n)
 {
+    const int m = n >> 1;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int which = blockIdx.y;
-    if (row >= n) return;
+    if (row >= m) return;
+    const size_t hs = (size_t)m * m;
     double ax = 0.0, ay = 0.0;
-    if (which < 2) {
-        const double *X = (which == 0 ? X0 : X2) + (size_t)row * n;
-        const double2 *bv = bh + which * n;
-        for (int j = lane; j < n; j += 64) ax = fma(X[j], bv[j].x, ax);
+    if (which < 4) {
+        const double *X = Xh + which * hs + (size_t)row * m;
+        const double2 *bv = bh + which * m;
+        for (int j = lane; j < m; j += 64) ax = fma(X[j], bv[j].x, ax);
     } else {
-        const double2 *X = X1 + (size_t)row * n;
-        const double2 *bv = bh + 2 * n;
-        for (int j = lane; j < n; j += 64) {
-            const double2 x = X[j], b = bv[j];
-            ax = fma(x.x, b.x, fma(-x.y, b.y, ax));
-            ay = fma(x.x, b.y, fma(x.y, b.x, ay));
+        // which 4: Re part acts on e1, Im part (odd -> even) on o1; which 5:
+        // Im part (even -> odd) on e1, Re part on o1
+        const double *R = Xh + (which == 4 ? kH1RE : kH1RO) * hs + (size_t)row * m;
+        const double *I = Xh + (which == 4 ? kH1IEO : kH1IOE) * hs + (size_t)row * m;
+        const double2 *br = bh + 2 * n + (which == 4 ? 0 : m);   // input of the Re part
+        const double2 *bi = bh + 2 * n + (which == 4 ? m : 0);   // input of the Im part
+        for (int j = lane; j < m; j += 64) {
+            const double xr = R[j], xi = I[j];
+            const double2 u = br[j], v = bi[j];
+            // xr u + i xi v
+            ax = fma(xr, u.x, fma(-xi, v.y, ax));
+            ay = fma(xr, u.y, fma(xi, v.x, ay));
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         ax += __shfl_xor(ax, o);
         ay += __shfl_xor(ay, o);
     }
-    if (lane == 0) sh[which * n + row] = make_double2(ax, ay);
+    if (lane == 0) sh[which * m + row] = make_double2(ax, ay);
 }
 
+// back from even/odd: mode value at node k of a side is even + odd (k < n/2)
+// or even - odd at n-1-k; then
 // sigma_s = (1/4)[ s^_0 + (-1)^s s^_2 + 2 Re(i^s s^_1) ]; ring charges h sigma
 __global__ void k_bem_sigma(const double2 *__restrict__ sh, double *__restrict__ rq,
                             double *__restrict__ sig_out, int n, double h)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= 4 * n) return;
-    const int s = t / n, k = t - s * n;
-    const double a0 = sh[k].x, a2 = sh[n + k].x;
-    const double2 a1 = sh[2 * n + k];
+    const int s = t / n, k = t - s * n, m = n >> 1;
+    const bool lo = k < m;
+    const int kk = lo ? k : n - 1 - k;
+    const double sg_ = lo ? 1.0 : -1.0;
+    const double a0 = sh[kk].x + sg_ * sh[m + kk].x;
+    const double a2 = sh[n + kk].x + sg_ * sh[n + m + kk].x;
+    const double2 e1 = sh[2 * n + kk], o1 = sh[2 * n + m + kk];
+    const double2 a1 = make_double2(e1.x + sg_ * o1.x, e1.y + sg_ * o1.y);
     double re1;
     if (s == 0) re1 = a1.x;
     else if (s == 1) re1 = -a1.y;
@@ -219,10 +293,19 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
         if (A != pl->X1)
             FMM_HIP(pl, hipMemcpyAsync(pl->X1, A, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
+    // fold into the even/odd halves and keep only those
+    FMM_HIP(pl, hipMalloc(&pl->Xh, (size_t)kHalves * (nn / 4) * sizeof(double)));
+    hipLaunchKernelGGL(k_bem_fold, dim3((n / 2 + 63) / 64, (n / 2 + 3) / 4), dim3(256), 0, s,
+                       pl->X0, pl->X2, pl->X1, pl->Xh, n);
     FMM_HIP(pl, hipGetLastError());
     FMM_HIP(pl, hipStreamSynchronize(s));
     FMM_HIP(pl, hipFree(tmp));
     FMM_HIP(pl, hipFree(rk));
+    FMM_HIP(pl, hipFree(pl->X0));
+    FMM_HIP(pl, hipFree(pl->X2));
+    FMM_HIP(pl, hipFree(pl->X1));
+    pl->X0 = pl->X2 = nullptr;
+    pl->X1 = nullptr;
     return FMM_OK;
 }
 
@@ -231,9 +314,10 @@ int bem_apply(fmm_plan *pl, double *sigma_out, hipStream_t s)
 {
     const int n = (int)pl->n;
     StageTimer t(pl, FMM_STAGE_BEM, s);
-    hipLaunchKernelGGL(k_bem_rhs, dim3((n + 255) / 256), dim3(256), 0, s, pl->phi_ring, pl->bhat, n);
-    hipLaunchKernelGGL(k_bem_gemv, dim3((n + 3) / 4, 3), dim3(256), 0, s, pl->X0, pl->X2, pl->X1,
-                       pl->bhat, pl->shat, n);
+    const int m = n / 2;
+    hipLaunchKernelGGL(k_bem_rhs, dim3((m + 255) / 256), dim3(256), 0, s, pl->phi_ring, pl->bhat, n);
+    hipLaunchKernelGGL(k_bem_gemv, dim3((m + 3) / 4, 6), dim3(256), 0, s, pl->Xh, pl->bhat,
+                       pl->shat, n);
     hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256), dim3(256), 0, s, pl->shat,
                        pl->ring_q, sigma_out, n, pl->h);
     FMM_HIP(pl, hipGetLastError());

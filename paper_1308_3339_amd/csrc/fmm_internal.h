@@ -142,6 +142,7 @@ struct fmm_plan {
     double *X0 = nullptr;     // n x n real
     double *X2 = nullptr;     // n x n real
     double2 *X1 = nullptr;    // n x n complex
+    double *Xh = nullptr;     // the three folded into 8 even/odd halves of (n/2)^2 (setup frees X0, X2, X1)
     double *phi_ring = nullptr;   // 4n
     double *ring_q = nullptr;     // 4n  (h * sigma)
     double2 *bhat = nullptr;      // 3n  (b^_0, b^_2 real parts in .x; b^_1 complex)
