@@ -257,6 +257,16 @@ static int build_levels_and_work(fmm_plan *pl)
     if (pl->kind == FMM_GRID && pl->bem && !ring.empty()) {
         pl->n_ring_cells = (int)ring.size();
         if ((st = upload(pl, &pl->ring_cells, ring))) return st;
+        // boundary cells of every level: targets of the ring charges' P2M
+        std::vector<int4> bc;
+        for (int l = 2; l <= L; ++l) {
+            const int nc = 1 << l;
+            for (int iy = 0; iy < nc; ++iy)
+                for (int ix = 0; ix < nc; ++ix)
+                    if (ix == 0 || iy == 0 || ix == nc - 1 || iy == nc - 1) bc.push_back(int4{l, ix, iy, 0});
+        }
+        pl->n_ring_p2m = (int)bc.size();
+        if ((st = upload(pl, &pl->ring_p2m_cells, bc))) return st;
     }
     if (off > 0) {
         const size_t bytes = (size_t)off * sizeof(double2);
@@ -281,7 +291,7 @@ static void release(fmm_plan *pl)
     void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
-                    pl->ring_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,
+                    pl->ring_cells, pl->ring_p2m_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,
                     pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
                     pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal, pl->bump_part};
     for (void *p : ptrs)

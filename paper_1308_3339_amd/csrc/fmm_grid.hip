@@ -126,21 +126,6 @@ __device__ __forceinline__ void store_tile(const double2 *__restrict__ src, doub
     }
 }
 
-// tile coordinates of block b: all tiles row-major, or only the border tiles
-__device__ __forceinline__ void tile_of_block(int b, int nt, int edge_only, int &tx, int &ty)
-{
-    if (!edge_only || nt == 1) {
-        tx = b % nt;
-        ty = b / nt;
-        return;
-    }
-    const int side = b / (nt - 1), k = b - side * (nt - 1);
-    if (side == 0) { tx = k; ty = 0; }
-    else if (side == 1) { tx = nt - 1; ty = k; }
-    else if (side == 2) { tx = nt - 1 - k; ty = nt - 1; }
-    else { tx = 0; ty = nt - 1 - k; }
-}
-
 // multipoles of a tile three more levels up, each level stored to global
 template <int P>
 __device__ __forceinline__ void m2m_chain(const double2 *sA, double2 *s0, double2 *s1, double2 *s2,
@@ -163,18 +148,16 @@ __device__ __forceinline__ void m2m_chain(const double2 *sA, double2 *s0, double
 
 
 // M2M from level l_in three levels up, one 8x8 tile of level-l_in cells per
-// block (only the border tiles when edge_only: the boundary-source pass has
-// non-zero multipoles in boundary cells only).
+// block.
 template <int P>
 __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
                                                 const double2 *__restrict__ A, LevelInfo lv,
-                                                int l_in, int edge_only)
+                                                int l_in)
 {
     __shared__ double2 sA[4 * P * P];
     __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
     const int nc = 1 << l_in, tw = nc < 8 ? nc : 8, nt = nc / tw;
-    int tx, ty;
-    tile_of_block(blockIdx.x, nt, edge_only, tx, ty);
+    const int tx = blockIdx.x % nt, ty = blockIdx.x / nt;
     const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l_in];
@@ -994,22 +977,6 @@ __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__rest
     if (lane == 0) phi[t] = -(fma(a.qscale, near, far)) * kInv2Pi;
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2 (boundary sources): P2M of the ring charges into the boundary
-// leaves they attach to.  Interior leaves are never written (stay zero).
-// ---------------------------------------------------------------------------
-// ring nodes attached to leaf (lx, ly) with nl >= 2: one or two runs of 8
-// consecutive nodes of one side, given as (side, first k); returns the count.
-__device__ __forceinline__ int attached_runs(int lx, int ly, int n, int nl, int side[2], int k0[2])
-{
-    int r = 0;
-    if (ly == 0) { side[r] = 0; k0[r] = 8 * lx; ++r; }                          // bottom
-    if (lx == nl - 1 && r < 2) { side[r] = 1; k0[r] = 8 * ly; ++r; }            // right
-    if (ly == nl - 1 && r < 2) { side[r] = 2; k0[r] = n - 8 * lx - 8; ++r; }    // top
-    if (lx == 0 && r < 2) { side[r] = 3; k0[r] = n - 8 * ly - 8; ++r; }         // left
-    return r;
-}
-
 // lattice coordinates of node k of side s
 __device__ __forceinline__ void side_node(int s, int k, int n, int &Ix, int &Iy)
 {
@@ -1019,65 +986,62 @@ __device__ __forceinline__ void side_node(int s, int k, int n, int &Ix, int &Iy)
     else { Ix = 0; Iy = n - k; }
 }
 
-// Pass 2 upward start: multipoles of the boundary leaves from the ring
-// charges they carry (M~_0 = sum c, M~_k = -sum c tau^k / k), for one border
-// tile of 8x8 leaves, then M2M three levels up.  Only boundary cells are
-// non-zero, and only border tiles are launched.
+// Pass 2 upward, all levels at once: the multipoles of the ring charges in
+// every boundary cell of levels 2..L by direct P2M from the ring nodes the
+// cell borders (M~_0 = sum c, M~_k = -sum c tau^k / k, tau = node offset
+// from the cell centre in cell widths; Sec. 5.3 item 1).  On p-term
+// expansions this equals P2M at the leaves followed by M2M up the tree (a
+// parent's first p coefficients depend only on its children's first p),
+// without a chain of dependent levels.  One wave per boundary cell, items
+// (level, ix, iy); the lanes split the cell's s = n / 2^l nodes per side and
+// the wave sums them with shuffles.
 template <int P>
-__global__ __launch_bounds__(256) void k_m2m_up_ring(const double *__restrict__ rq,
-                                                     double2 *__restrict__ M,
-                                                     const double2 *__restrict__ A, LevelInfo lv,
-                                                     int n, int L)
+__global__ __launch_bounds__(256) void k_p2m_ring(const int4 *__restrict__ cells, int ncells,
+                                                  const double *__restrict__ rq,
+                                                  double2 *__restrict__ M, LevelInfo lv, int n)
 {
-    __shared__ double2 sA[4 * P * P];
-    __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
-    const int nl = 1 << L, tw = nl < 8 ? nl : 8, nt = nl / tw;
-    int tx, ty;
-    tile_of_block(blockIdx.x, nt, 1, tx, ty);
-    const int x0 = tx * tw, y0 = ty * tw, cnt = tw * tw;
-    const int64_t ncell = (int64_t)nl * nl;
-    {
-        double2 va[rounds256(4 * P * P)];
-        fetch(va, 4 * P * P, [&](int t) { return A[t]; });
-        put(va, 4 * P * P, [&](int t, double2 x) { sA[t] = x; });
-    }
-    for (int c = threadIdx.x; c < cnt; c += 256) {
-        const int lx = x0 + c % tw, ly = y0 + c / tw;
-        double2 m[P];
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (w >= ncells) return;
+    const int4 it = cells[w];
+    const int l = it.x, ix = it.y, iy = it.z, nc = 1 << l, s = n >> l;
+    int sd[2], k0[2], r = 0;
+    if (iy == 0) { sd[r] = 0; k0[r] = s * ix; ++r; }
+    if (ix == nc - 1 && r < 2) { sd[r] = 1; k0[r] = s * iy; ++r; }
+    if (iy == nc - 1 && r < 2) { sd[r] = 2; k0[r] = n - s * ix - s; ++r; }
+    if (ix == 0 && r < 2) { sd[r] = 3; k0[r] = n - s * iy - s; ++r; }
+    const double inv = 1.0 / (double)s;
+    const double cx = s * ix + 0.5 * s + 0.5, cy = s * iy + 0.5 * s + 0.5;
+    double2 m[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) m[k] = make_double2(0.0, 0.0);
-        const bool bnd = lx == 0 || ly == 0 || lx == nl - 1 || ly == nl - 1;
-        if (bnd) {
-            int sd[2], k0[2];
-            const int runs = attached_runs(lx, ly, n, nl, sd, k0);
-            for (int r = 0; r < runs; ++r)
-                for (int j = 0; j < 8; ++j) {
-                    int Ix, Iy;
-                    side_node(sd[r], k0[r] + j, n, Ix, Iy);
-                    const double cq = rq[sd[r] * n + k0[r] + j];
-                    const double2 tau = make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125);
-                    double2 pw = make_double2(1.0, 0.0);
-                    m[0].x += cq;
-#pragma unroll
-                    for (int k = 1; k < P; ++k) {
-                        pw = cmul(pw, tau);
-                        m[k].x += cq * pw.x;
-                        m[k].y += cq * pw.y;
-                    }
-                }
+    for (int k = 0; k < P; ++k) m[k] = make_double2(0.0, 0.0);
+    for (int q = 0; q < r; ++q)
+        for (int j = lane; j < s; j += 64) {
+            int Ix, Iy;
+            side_node(sd[q], k0[q] + j, n, Ix, Iy);
+            const double cq = rq[sd[q] * n + k0[q] + j];
+            const double2 tau = make_double2((Ix - cx) * inv, (Iy - cy) * inv);
+            double2 pw = make_double2(1.0, 0.0);
+            m[0].x += cq;
 #pragma unroll
             for (int k = 1; k < P; ++k) {
-                const double f = -1.0 / (double)k;
-                m[k] = make_double2(f * m[k].x, f * m[k].y);
+                pw = cmul(pw, tau);
+                m[k].x = fma(cq, pw.x, m[k].x);
+                m[k].y = fma(cq, pw.y, m[k].y);
             }
-#pragma unroll
-            for (int k = 0; k < P; ++k) M[lv.off[L] + k * ncell + (int64_t)ly * nl + lx] = m[k];
         }
 #pragma unroll
-        for (int k = 0; k < P; ++k) s0[k * cnt + c] = m[k];
+    for (int k = 0; k < P; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+            m[k].x += __shfl_xor(m[k].x, o);
+            m[k].y += __shfl_xor(m[k].y, o);
+        }
+    if (lane != 0) return;
+    const int64_t ncell = (int64_t)nc * nc, cell = (int64_t)iy * nc + ix;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const double f = k == 0 ? 1.0 : -1.0 / (double)k;
+        M[lv.off[l] + k * ncell + cell] = make_double2(f * m[k].x, f * m[k].y);
     }
-    __syncthreads();
-    m2m_chain<P>(sA, s0, s1, s2, s3, M, lv, L, tw, x0, y0);
 }
 
 // Pass 2 M2L: the multipoles are non-zero only in the boundary cells of each
@@ -1318,14 +1282,12 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
 // host drivers
 // ---------------------------------------------------------------------------
 template <int P>
-static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, int edge_only, hipStream_t s)
+static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, hipStream_t s)
 {
     // each launch lifts the multipoles three levels, from l_in down to 2
     for (int l = l_in; l > 2; l -= 3) {
         const int nc = 1 << l, tw = std::min(nc, 8), nt = nc / tw;
-        const int nblk = (edge_only && nt > 1) ? 4 * (nt - 1) : nt * nt;
-        hipLaunchKernelGGL(k_m2m_up<P>, dim3(nblk), dim3(256), 0, s, M, pl->tab.m2m, pl->lv, l,
-                           edge_only);
+        hipLaunchKernelGGL(k_m2m_up<P>, dim3(nt * nt), dim3(256), 0, s, M, pl->tab.m2m, pl->lv, l);
     }
 }
 
@@ -1428,7 +1390,7 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     if (far) {
         {
             StageTimer t(pl, FMM_STAGE_M2M, s);
-            run_m2m_from<P>(pl, pl->ws.M, pl->L, 0, s);
+            run_m2m_from<P>(pl, pl->ws.M, pl->L, s);
         }
         run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
     }
@@ -1455,11 +1417,11 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hip
     const bool far = L >= 2;
     StageTimer t(pl, FMM_STAGE_PASS2, s);
     if (far) {
-        // upward: ring charges -> boundary leaves -> three levels up, border tiles only
-        const int tw = std::min(nl, 8), nt = nl / tw;
-        hipLaunchKernelGGL(k_m2m_up_ring<P>, dim3(nt > 1 ? 4 * (nt - 1) : 1), dim3(256), 0, s,
-                           pl->ring_q, pl->ws.M2, pl->tab.m2m, pl->lv, (int)pl->n, L);
-        run_m2m_from<P>(pl, pl->ws.M2, L - 3, 1, s);
+        // upward: ring charges -> every boundary cell of levels 2..L
+        const int tw = std::min(nl, 8);
+        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((pl->n_ring_p2m + 3) / 4), dim3(256), 0, s,
+                           pl->ring_p2m_cells, pl->n_ring_p2m, pl->ring_q, pl->ws.M2, pl->lv,
+                           (int)pl->n);
         // M2L from boundary cells into the (2K+2)-cell band of every level
         hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells), dim3(256), 0, s,
                            pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
@@ -1500,7 +1462,7 @@ template <int P>
 static int points_up_p(fmm_plan *pl, hipStream_t s)
 {
     StageTimer t(pl, FMM_STAGE_M2M, s);
-    run_m2m_from<P>(pl, pl->ws.M, pl->L, 0, s);
+    run_m2m_from<P>(pl, pl->ws.M, pl->L, s);
     return FMM_OK;
 }
 

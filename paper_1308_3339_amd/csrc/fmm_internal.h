@@ -134,8 +134,10 @@ struct fmm_plan {
     fmmprec::Workspace ws{};
     fmmprec::M2LItem *m2l_items = nullptr;  // all tiles of levels 2..L
     int n_m2l_items = 0;
-    int4 *ring_cells = nullptr;   // strips within 3 cells of the boundary (see k_m2l_ring)
+    int4 *ring_cells = nullptr;   // strips within 2K+1 cells of the boundary (see k_m2l_ring)
     int n_ring_cells = 0;
+    int4 *ring_p2m_cells = nullptr;  // boundary cells of levels 2..L: (level, ix, iy, 0)
+    int n_ring_p2m = 0;
 
     // boundary correction (GRID, bem = 1): inverses of the three distinct
     // diagonal blocks of the rotation-diagonalised collocation matrix
