@@ -24,9 +24,10 @@
 // odd and odd to even).  Setup folds the inverses into these eight halves
 // (each averaged over the four symmetric copies of its entries, with the 1/2
 // of Q^T Q = 2 I), and an application is a DFT over the sides with the
-// even/odd split, eight (n/2) x (n/2) products and the inverse: 2n^2 doubles
-// read, against 4n^2 for the rotation blocks alone and 16n^2 for a dense
-// inverse.
+// even/odd split (formed by the ring-target kernel of the volume pass), eight
+// (n/2) x (n/2) products (here) and the inverse (formed where the
+// boundary-source pass reads the density): 2n^2 doubles read, against 4n^2
+// for the rotation blocks alone and 16n^2 for a dense inverse.
 #include "fmm_internal.h"
 
 namespace fmmprec {
@@ -164,28 +165,6 @@ __global__ __launch_bounds__(256) void k_bem_fold(const double *__restrict__ X0,
     Xh[kH1IOE * hs + o] = 0.25 * ((xa.y + xb.y) - (xd.y + xe.y));
 }
 
-// b = -phi: b^_0 = sum_s b_s, b^_2 = sum_s (-1)^s b_s, b^_1 = sum_s i^(-s) b_s,
-// then the even/odd split of each mode, b^[k] +- b^[n-1-k] for k < n/2:
-// bh = [mode 0: even | odd][mode 2: even | odd][mode 1: even | odd] (n/2 each)
-__global__ void k_bem_rhs(const double *__restrict__ phi, double2 *__restrict__ bh, int n)
-{
-    const int m = n >> 1;
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= m) return;
-    const int kr = n - 1 - k;
-    const double b0 = -phi[k], b1 = -phi[n + k], b2 = -phi[2 * n + k], b3 = -phi[3 * n + k];
-    const double c0 = -phi[kr], c1 = -phi[n + kr], c2 = -phi[2 * n + kr], c3 = -phi[3 * n + kr];
-    const double m0 = (b0 + b1) + (b2 + b3), n0 = (c0 + c1) + (c2 + c3);
-    const double m2 = (b0 - b1) + (b2 - b3), n2 = (c0 - c1) + (c2 - c3);
-    const double2 m1 = make_double2(b0 - b2, b3 - b1), n1 = make_double2(c0 - c2, c3 - c1);
-    bh[k] = make_double2(m0 + n0, 0.0);
-    bh[m + k] = make_double2(m0 - n0, 0.0);
-    bh[n + k] = make_double2(m2 + n2, 0.0);
-    bh[n + m + k] = make_double2(m2 - n2, 0.0);
-    bh[2 * n + k] = make_double2(m1.x + n1.x, m1.y + n1.y);
-    bh[2 * n + m + k] = make_double2(m1.x - n1.x, m1.y - n1.y);
-}
-
 // The products of the folded inverses with the split right-hand side, one
 // wave per row of a half (n/2 rows per group), in the layout of bh:
 //   y = 0: X0 even . e0,  1: X0 odd . o0,  2: X2 even . e2,  3: X2 odd . o2,
@@ -228,28 +207,15 @@ __global__ __launch_bounds__(256) void k_bem_gemv(const double *__restrict__ Xh,
     if (lane == 0) sh[which * m + row] = make_double2(ax, ay);
 }
 
-// back from even/odd: mode value at node k of a side is even + odd (k < n/2)
-// or even - odd at n-1-k; then
-// sigma_s = (1/4)[ s^_0 + (-1)^s s^_2 + 2 Re(i^s s^_1) ]; ring charges h sigma
+// sigma (ring_sigma) and the ring charges h sigma at every node; the
+// boundary-source pass computes them itself when the tree has levels >= 2
 __global__ void k_bem_sigma(const double2 *__restrict__ sh, double *__restrict__ rq,
                             double *__restrict__ sig_out, int n, double h)
 {
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= 4 * n) return;
-    const int s = t / n, k = t - s * n, m = n >> 1;
-    const bool lo = k < m;
-    const int kk = lo ? k : n - 1 - k;
-    const double sg_ = lo ? 1.0 : -1.0;
-    const double a0 = sh[kk].x + sg_ * sh[m + kk].x;
-    const double a2 = sh[n + kk].x + sg_ * sh[n + m + kk].x;
-    const double2 e1 = sh[2 * n + kk], o1 = sh[2 * n + m + kk];
-    const double2 a1 = make_double2(e1.x + sg_ * o1.x, e1.y + sg_ * o1.y);
-    double re1;
-    if (s == 0) re1 = a1.x;
-    else if (s == 1) re1 = -a1.y;
-    else if (s == 2) re1 = -a1.x;
-    else re1 = a1.y;
-    const double sg = 0.25 * (a0 + ((s & 1) ? -a2 : a2) + 2.0 * re1);
+    const int s = t / n, k = t - s * n;
+    const double sg = ring_sigma(sh, s, k, n);
     rq[t] = h * sg;
     if (sig_out) sig_out[t] = sg;
 }
@@ -309,17 +275,21 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
     return FMM_OK;
 }
 
-// sigma = -S^{-1} phi_ring (pl->phi_ring), ring charges h sigma -> pl->ring_q
+// sigma = -S^{-1} phi_ring: the products of the folded inverses with the
+// split right-hand side pl->bhat (written by the ring-target kernel of the
+// volume pass) into pl->shat.  With levels >= 2 the boundary-source pass
+// forms sigma and the charges from pl->shat inside its P2M; otherwise they
+// are formed here (pl->ring_q, and sigma_out when given).
 int bem_apply(fmm_plan *pl, double *sigma_out, hipStream_t s)
 {
     const int n = (int)pl->n;
     StageTimer t(pl, FMM_STAGE_BEM, s);
     const int m = n / 2;
-    hipLaunchKernelGGL(k_bem_rhs, dim3((m + 255) / 256), dim3(256), 0, s, pl->phi_ring, pl->bhat, n);
     hipLaunchKernelGGL(k_bem_gemv, dim3((m + 3) / 4, 6), dim3(256), 0, s, pl->Xh, pl->bhat,
                        pl->shat, n);
-    hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256), dim3(256), 0, s, pl->shat,
-                       pl->ring_q, sigma_out, n, pl->h);
+    if (pl->L < 2)
+        hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256), dim3(256), 0, s, pl->shat,
+                           pl->ring_q, sigma_out, n, pl->h);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }

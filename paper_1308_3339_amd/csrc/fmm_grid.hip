@@ -938,17 +938,26 @@ __device__ __forceinline__ double l2p_eval(const double2 *__restrict__ Lc, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Pass-1 potential at the 4n ring nodes, one wave per node: near field from
-// the in-domain leaves of the near set around the attached boundary leaf (at
-// most 6 of the 3x3 block with the list rule), split over the lanes and
-// summed with shuffles; far field by L2P from that leaf's local expansion.
+// Pass-1 potential at the ring nodes and the right-hand side of the boundary
+// solve.  A block of 8 waves takes the eight nodes (side s, k) and
+// (s, n-1-k), s = 0..3, of one k < n/2, one node per wave.  Each node's near
+// field comes from the in-domain leaves of the near set around its boundary
+// leaf (at most 6 of the 3x3 block with the list rule), split over the lanes
+// and summed with shuffles; its far field is the L2P of that leaf's local
+// expansion.  Then phi and, with bh, b = -phi as the DFT over the sides
+// (b^_0 = sum_s b_s, b^_2 = sum_s (-1)^s b_s, b^_1 = sum_s i^(-s) b_s) split
+// into even and odd parts b^[k] +- b^[n-1-k], the layout the boundary
+// solve's products read: bh = [mode 0: even | odd][mode 2: even | odd]
+// [mode 1: even | odd].
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__restrict__ phi)
+__global__ __launch_bounds__(512) void k_ring_targets(LeafArgs a, double *__restrict__ phi,
+                                                      double2 *__restrict__ bh)
 {
-    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int n = a.n, nl = a.nl;
-    if (t >= 4 * n) return;
+    __shared__ double val[8];
+    const int kq = blockIdx.x, v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = a.n, nl = a.nl, m = n >> 1;
+    const int t = (v & 3) * n + (v < 4 ? kq : n - 1 - kq);
     int Ix, Iy;
     ring_node(t, n, Ix, Iy);
     const int lx = leaf_of(Ix, nl), ly = leaf_of(Iy, nl);
@@ -965,16 +974,33 @@ __global__ __launch_bounds__(256) void k_ring_targets(LeafArgs a, double *__rest
         }
     }
     near = wave_sum(near);
-    double far = 0.0;
-    if (a.far && lane == 0) {
-        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
-        const double2 *Ll = a.Lt + a.lv.off[a.L];
-        double2 Lc[P];
+    if (lane == 0) {
+        double far = 0.0;
+        if (a.far) {
+            const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
+            const double2 *Ll = a.Lt + a.lv.off[a.L];
+            double2 Lc[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
-        far = l2p_eval<P>(Lc, make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125));
+            for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
+            far = l2p_eval<P>(Lc, make_double2((Ix - 8 * lx - 4.5) * 0.125, (Iy - 8 * ly - 4.5) * 0.125));
+        }
+        const double ph = -(fma(a.qscale, near, far)) * kInv2Pi;
+        phi[t] = ph;
+        val[v] = ph;
     }
-    if (lane == 0) phi[t] = -(fma(a.qscale, near, far)) * kInv2Pi;
+    __syncthreads();
+    if (!bh || threadIdx.x != 0) return;
+    const double b0 = -val[0], b1 = -val[1], b2 = -val[2], b3 = -val[3];
+    const double c0 = -val[4], c1 = -val[5], c2 = -val[6], c3 = -val[7];
+    const double m0 = (b0 + b1) + (b2 + b3), n0 = (c0 + c1) + (c2 + c3);
+    const double m2 = (b0 - b1) + (b2 - b3), n2 = (c0 - c1) + (c2 - c3);
+    const double2 m1 = make_double2(b0 - b2, b3 - b1), n1 = make_double2(c0 - c2, c3 - c1);
+    bh[kq] = make_double2(m0 + n0, 0.0);
+    bh[m + kq] = make_double2(m0 - n0, 0.0);
+    bh[n + kq] = make_double2(m2 + n2, 0.0);
+    bh[n + m + kq] = make_double2(m2 - n2, 0.0);
+    bh[2 * n + kq] = make_double2(m1.x + n1.x, m1.y + n1.y);
+    bh[2 * n + m + kq] = make_double2(m1.x - n1.x, m1.y - n1.y);
 }
 
 // lattice coordinates of node k of side s
@@ -994,11 +1020,16 @@ __device__ __forceinline__ void side_node(int s, int k, int n, int &Ix, int &Iy)
 // parent's first p coefficients depend only on its children's first p),
 // without a chain of dependent levels.  One wave per boundary cell, items
 // (level, ix, iy); the lanes split the cell's s = n / 2^l nodes per side and
-// the wave sums them with shuffles.
+// the wave sums them with shuffles.  The charges h sigma are formed here from
+// the boundary solve's products (ring_sigma); the leaf-level waves, which
+// see every node exactly once, also store them (rq, and sigma to sig_out).
 template <int P>
 __global__ __launch_bounds__(256) void k_p2m_ring(const int4 *__restrict__ cells, int ncells,
-                                                  const double *__restrict__ rq,
-                                                  double2 *__restrict__ M, LevelInfo lv, int n)
+                                                  const double2 *__restrict__ sh, double h,
+                                                  double *__restrict__ rq,
+                                                  double *__restrict__ sig_out,
+                                                  double2 *__restrict__ M, LevelInfo lv, int n,
+                                                  int L)
 {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (w >= ncells) return;
@@ -1018,7 +1049,12 @@ __global__ __launch_bounds__(256) void k_p2m_ring(const int4 *__restrict__ cells
         for (int j = lane; j < s; j += 64) {
             int Ix, Iy;
             side_node(sd[q], k0[q] + j, n, Ix, Iy);
-            const double cq = rq[sd[q] * n + k0[q] + j];
+            const double sg = ring_sigma(sh, sd[q], k0[q] + j, n);
+            const double cq = h * sg;
+            if (l == L) {
+                rq[sd[q] * n + k0[q] + j] = cq;
+                if (sig_out) sig_out[sd[q] * n + k0[q] + j] = sg;
+            }
             const double2 tau = make_double2((Ix - cx) * inv, (Iy - cy) * inv);
             double2 pw = make_double2(1.0, 0.0);
             m[0].x += cq;
@@ -1125,6 +1161,58 @@ __global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items
     }
 }
 
+// Pass 2 near field: u += -(1/2pi) sum over the ring nodes attached to the
+// leaves of the near set around the target's leaf.  Ring node k of a side
+// attaches to the boundary leaf it borders, so for each side the sum is a
+// window of consecutive nodes (the near leaves along that side: three, 24
+// nodes, with the list rule) with a kernel value from the lattice table, and
+// only targets within K + 1 leaves of a side see it.
+__device__ __forceinline__ double side_window(const double *__restrict__ rqs,
+                                              const double *__restrict__ trow, int k0, int k1,
+                                              int c, int sgn)
+{
+    // sum_{k0 <= k < k1} rqs[k] * trow[|c - sgn k|]
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) acc = fma(rqs[k], trow[abs(c - sgn * k)], acc);
+    return acc;
+}
+
+// the pass-2 near sum (before the -1/2pi) at grid point (gx, gy)
+__device__ __forceinline__ double pass2_near_at(int gx, int gy, const double *__restrict__ rq,
+                                                const double *__restrict__ rtab, int n, int nl,
+                                                int K, int kxp, int rs)
+{
+    const int lx = gx >> 3, ly = gy >> 3;
+    // lattice range [a, b) along a side covered by the near leaves l-k..l+k,
+    // k = kx(distance of the target's leaf from that side)
+    auto lo = [&](int l, int k) { return 8 * max(l - k, 0); };
+    auto hi = [&](int l, int k) { return 8 * min(l + k, nl - 1) + 8; };
+    double near = 0.0;
+    const int db = ly, dr = nl - 1 - lx, dt = nl - 1 - ly, dl = lx;
+    if (db <= K) {      // bottom: node k at (k+1, 0)
+        const int k = near_kx(kxp, db);
+        if (k >= 0) near += side_window(rq, rtab + (gy + 1) * rs, lo(lx, k), hi(lx, k), gx, 1);
+    }
+    if (dr <= K) {      // right: node k at (n+1, k+1)
+        const int k = near_kx(kxp, dr);
+        if (k >= 0) near += side_window(rq + n, rtab + (n - gx) * rs, lo(ly, k), hi(ly, k), gy, 1);
+    }
+    if (dt <= K) {      // top: node k at (n-k, n+1); Ix-1 = n-1-k in [ax, bx)
+        const int k = near_kx(kxp, dt);
+        if (k >= 0)
+            near += side_window(rq + 2 * n, rtab + (n - gy) * rs, n - hi(lx, k), n - lo(lx, k),
+                                gx - n + 1, -1);
+    }
+    if (dl <= K) {      // left: node k at (0, n-k); Iy-1 = n-1-k in [ay, by)
+        const int k = near_kx(kxp, dl);
+        if (k >= 0)
+            near += side_window(rq + 3 * n, rtab + (gx + 1) * rs, n - hi(ly, k), n - lo(ly, k),
+                                gy - n + 1, -1);
+    }
+    return near;
+}
+
 // Far field at every grid point, the last stage of an application:
 //   u += -(1/2pi) Re sum_k (L~ring_k + L~vol_k) tau^k   (L2P, Sec. 5.3)
 // over the leaves of an 8x8 tile.  The boundary-source expansions L~ring
@@ -1201,24 +1289,8 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
     }
 }
 
-// Pass 2 near field: u += -(1/2pi) sum over the ring nodes attached to the
-// leaves of the near set around the target's leaf.  Ring node k of a side
-// attaches to the boundary leaf it borders, so for each side the sum is a
-// window of consecutive nodes (the near leaves along that side: three, 24
-// nodes, with the list rule) with a kernel value from the lattice table, and
-// only targets within K + 1 leaves of a side see it.  One thread per point
-// of the 8(K+1)-deep band (every point when the band covers the grid).
-__device__ __forceinline__ double side_window(const double *__restrict__ rqs,
-                                              const double *__restrict__ trow, int k0, int k1,
-                                              int c, int sgn)
-{
-    // sum_{k0 <= k < k1} rqs[k] * trow[|c - sgn k|]
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = k0; k < k1; ++k) acc = fma(rqs[k], trow[abs(c - sgn * k)], acc);
-    return acc;
-}
-
+// one thread per point of the 8(K+1)-deep band (every point when the band
+// covers the grid)
 __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
                                                     const double *__restrict__ rq,
                                                     const double *__restrict__ rtab, int n, int nl,
@@ -1248,34 +1320,7 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
             return;
         }
     }
-    const int lx = gx >> 3, ly = gy >> 3;
-    // lattice range [a, b) along a side covered by the near leaves l-k..l+k,
-    // k = kx(distance of the target's leaf from that side)
-    auto lo = [&](int l, int k) { return 8 * max(l - k, 0); };
-    auto hi = [&](int l, int k) { return 8 * min(l + k, nl - 1) + 8; };
-    double near = 0.0;
-    const int db = ly, dr = nl - 1 - lx, dt = nl - 1 - ly, dl = lx;
-    if (db <= K) {      // bottom: node k at (k+1, 0)
-        const int k = near_kx(kxp, db);
-        if (k >= 0) near += side_window(rq, rtab + (gy + 1) * rs, lo(lx, k), hi(lx, k), gx, 1);
-    }
-    if (dr <= K) {      // right: node k at (n+1, k+1)
-        const int k = near_kx(kxp, dr);
-        if (k >= 0) near += side_window(rq + n, rtab + (n - gx) * rs, lo(ly, k), hi(ly, k), gy, 1);
-    }
-    if (dt <= K) {      // top: node k at (n-k, n+1); Ix-1 = n-1-k in [ax, bx)
-        const int k = near_kx(kxp, dt);
-        if (k >= 0)
-            near += side_window(rq + 2 * n, rtab + (n - gy) * rs, n - hi(lx, k), n - lo(lx, k),
-                                gx - n + 1, -1);
-    }
-    if (dl <= K) {      // left: node k at (0, n-k); Iy-1 = n-1-k in [ay, by)
-        const int k = near_kx(kxp, dl);
-        if (k >= 0)
-            near += side_window(rq + 3 * n, rtab + (gx + 1) * rs, n - hi(ly, k), n - lo(ly, k),
-                                gy - n + 1, -1);
-    }
-    u[(size_t)gy * n + gx] += -near * kInv2Pi;
+    u[(size_t)gy * n + gx] += -pass2_near_at(gx, gy, rq, rtab, n, nl, K, kxp, rs) * kInv2Pi;
 }
 
 // ---------------------------------------------------------------------------
@@ -1396,8 +1441,8 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
-        hipLaunchKernelGGL(k_ring_targets<P>, dim3((4 * pl->n + 3) / 4), dim3(256), 0, s, a,
-                           ring_out);
+        hipLaunchKernelGGL(k_ring_targets<P>, dim3(pl->n / 2), dim3(512), 0, s, a, ring_out,
+                           pl->bem ? pl->bhat : nullptr);
     }
     if (far && !defer_l2p) {
         StageTimer t(pl, FMM_STAGE_L2L, s);
@@ -1411,7 +1456,8 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
 }
 
 template <int P>
-static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hipStream_t s)
+static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, double *sigma_out,
+                                  hipStream_t s)
 {
     const int L = pl->L, nl = pl->nl;
     const bool far = L >= 2;
@@ -1420,8 +1466,8 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hip
         // upward: ring charges -> every boundary cell of levels 2..L
         const int tw = std::min(nl, 8);
         hipLaunchKernelGGL(k_p2m_ring<P>, dim3((pl->n_ring_p2m + 3) / 4), dim3(256), 0, s,
-                           pl->ring_p2m_cells, pl->n_ring_p2m, pl->ring_q, pl->ws.M2, pl->lv,
-                           (int)pl->n);
+                           pl->ring_p2m_cells, pl->n_ring_p2m, pl->shat, pl->h, pl->ring_q,
+                           sigma_out, pl->ws.M2, pl->lv, (int)pl->n, L);
         // M2L from boundary cells into the (2K+2)-cell band of every level
         hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells), dim3(256), 0, s,
                            pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
@@ -1440,8 +1486,7 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, hip
     const int n = (int)pl->n, B = 8 * (pl->K + 1);
     const int64_t nband = n <= 2 * B ? (int64_t)n * n : (int64_t)4 * B * n - 4 * B * B;
     hipLaunchKernelGGL(k_pass2_near, dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s, u,
-                       pl->ring_q, pl->tab.rtab, n, nl, pl->K, near_kx_packed(pl),
-                       8 * pl->K + 9);
+                       pl->ring_q, pl->tab.rtab, n, nl, pl->K, near_kx_packed(pl), 8 * pl->K + 9);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }
@@ -1452,9 +1497,10 @@ int grid_volume_fmm(fmm_plan *pl, const double *q, double qscale, double *u, dou
     FMM_DISPATCH_P(pl->p, grid_volume_fmm_p, pl, q, qscale, u, ring_out, defer_l2p, s);
 }
 
-int grid_ring_source_fmm(fmm_plan *pl, double *u, bool with_volume, hipStream_t s)
+int grid_ring_source_fmm(fmm_plan *pl, double *u, bool with_volume, double *sigma_out,
+                         hipStream_t s)
 {
-    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, s);
+    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, sigma_out, s);
 }
 
 // level-generic stages reused by point-cloud plans

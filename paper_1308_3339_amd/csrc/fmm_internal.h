@@ -227,9 +227,12 @@ struct StageTimer {
 // leaf-level local expansions (plan->ws.Lt) for grid_ring_source_fmm to add.
 int grid_volume_fmm(fmm_plan *plan, const double *q, double qscale, double *u,
                     double *ring_out, bool defer_l2p, hipStream_t s);
-// second pass: ring charges plan->ring_q, add their potential to u (and the
-// deferred far field of the volume pass when with_volume)
-int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, hipStream_t s);
+// second pass: the boundary density from the boundary solve's products
+// (plan->shat; also written to plan->ring_q as charges h sigma and to
+// sigma_out when given), add its potential to u (and the deferred far field
+// of the volume pass when with_volume)
+int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, double *sigma_out,
+                         hipStream_t s);
 int m2l_kernel_setup(fmm_plan *plan);
 int points_fmm(fmm_plan *plan, const double *q, double *u, hipStream_t s);
 // Gaussian-bump source model and its parameter gradients (adjoint.hip)
@@ -258,6 +261,24 @@ int tune_vector_blocks(fmm_plan *plan, hipStream_t s, int *chosen);
 void drop_step_graphs(fmm_plan *plan);
 int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
                       double *sigma, hipStream_t s);
+
+// Boundary density at node k of side s from the products of the boundary
+// solve: sh = [mode 0: even | odd][mode 2: even | odd][mode 1: even | odd]
+// (n/2 each).  The mode value at node k is even + odd (k < n/2) or even - odd
+// at n-1-k, and sigma_s = (1/4)[ s^_0 + (-1)^s s^_2 + 2 Re(i^s s^_1) ].
+__device__ __forceinline__ double ring_sigma(const double2 *__restrict__ sh, int s, int k, int n)
+{
+    const int m = n >> 1;
+    const bool lo = k < m;
+    const int kk = lo ? k : n - 1 - k;
+    const double sg = lo ? 1.0 : -1.0;
+    const double a0 = sh[kk].x + sg * sh[m + kk].x;
+    const double a2 = sh[n + kk].x + sg * sh[n + m + kk].x;
+    const double2 e1 = sh[2 * n + kk], o1 = sh[2 * n + m + kk];
+    const double a1x = e1.x + sg * o1.x, a1y = e1.y + sg * o1.y;
+    const double re1 = s == 0 ? a1x : (s == 1 ? -a1y : (s == 2 ? -a1x : a1y));
+    return 0.25 * (a0 + ((s & 1) ? -a2 : a2) + 2.0 * re1);
+}
 
 // kx(b) + 1 of the plan's near set in 4 bits per b = 0..kMaxK (the form the
 // kernels take it in: a runtime shift instead of an indexed array)

@@ -131,9 +131,22 @@ __global__ __launch_bounds__(256) void k_arnoldi_dots(const double *__restrict__
     block_reduce_store<NA>(acc, part);
 }
 
-// rho, h_j, rt and the sweep-B coefficients from the reduced sums of step nj
-__global__ void k_arnoldi_coef(double *__restrict__ d, int nj)
+// The block partials of sweep A reduced to a_i, b_i, c, d, e (one wave per
+// row, lanes in a fixed order, then a shuffle tree), and from them rho, h_j,
+// rt and the sweep-B coefficients: one launch between the two sweeps.
+__global__ __launch_bounds__(1024) void k_arnoldi_coef(const double *__restrict__ part, int nblk,
+                                                       double *__restrict__ d, int nj)
 {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wv; i < 2 * nj + 3; i += 16) {
+        const double *pi = part + (size_t)i * kRedBlocks;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int b = lane; b < nblk; b += 64) acc += pi[b];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (lane == 0) d[kRaw + i] = acc;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     const double *a = d + kRaw, *b = d + kRaw + nj;
     const double c = d[kRaw + 2 * nj], ud = d[kRaw + 2 * nj + 1], e = d[kRaw + 2 * nj + 2];
@@ -379,7 +392,7 @@ int precond_apply_one(fmm_plan *pl, const double *r, double *z, double *phi_ring
     if (pl->bem) {
         st = bem_apply(pl, sigma, s);
         if (st != FMM_OK) return st;
-        st = grid_ring_source_fmm(pl, z, true, s);
+        st = grid_ring_source_fmm(pl, z, true, sigma, s);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;
@@ -549,9 +562,8 @@ class Fgmres {
             launch_arnoldi_dots<true>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
         else
             launch_arnoldi_dots<false>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
-        hipLaunchKernelGGL(k_finish, dim3(2 * j + 3), dim3(256), 0, s_, pl_->partial, nblk_,
-                           pl_->dscal + kRaw, nullptr, nullptr, 0);
-        hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(64), 0, s_, pl_->dscal, j);
+        hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(1024), 0, s_, pl_->partial, nblk_,
+                           pl_->dscal, j);
         if (var_)
             launch_arnoldi_update<true>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
         else
