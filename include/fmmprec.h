@@ -111,7 +111,7 @@ typedef struct {
  *            outside it; theta > 1/sqrt(2) gives the list rule again.
  *            Smaller theta trades more near-field and M2L work for accuracy
  *            at a given p (p = 6, theta = 0.4 gives about six digits).
- *            theta < 1/sqrt(2) requires GRID, FMM_FP64, p <= 12 and
+ *            theta < 1/sqrt(2) requires FMM_FP64, p <= 12 and
  *            p (16 + 4K)^2 * 16 <= 160 KiB, K = floor(sqrt(2)/theta) (so
  *            p <= 10 for theta < 0.354); otherwise FMM_ERR_UNSUPPORTED. */
 typedef struct {

@@ -333,8 +333,8 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (!(prm->theta == 0.0 || (prm->theta >= kThetaMin && prm->theta <= 1.0)))
         return fail(nullptr, FMM_ERR_ARG, "theta must be 0 (interaction lists) or in [0.3, 1]");
     const int Kt = near_radius(prm->theta);
-    if (Kt > 1 && (prob->kind != FMM_GRID || prm->prec != FMM_FP64 || prm->p > kThetaPMax))
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "theta < 1/sqrt(2) is built for FP64 GRID plans with p <= 12");
+    if (Kt > 1 && (prm->prec != FMM_FP64 || prm->p > kThetaPMax))
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "theta < 1/sqrt(2) is built for FP64 plans with p <= 12");
     if (Kt > 1 && (int64_t)prm->p * (16 + 4 * Kt) * (16 + 4 * Kt) * 16 > kM2LMaxLds)
         return fail(nullptr, FMM_ERR_UNSUPPORTED, "p too large for this theta (M2L source tile exceeds LDS)");
     hipStream_t s = (hipStream_t)stream;

@@ -6,9 +6,10 @@
 // row-major order) and keeps the sorted coordinates on the device.  An
 // application gathers the charges into leaf order, builds leaf multipoles,
 // reuses the level-generic M2M, M2L and L2L kernels of the grid path, and
-// finishes with one block per target leaf: the sources of the 3x3 leaves
-// around it are staged through LDS in chunks, four waves split the sources,
-// and the local expansion is evaluated at each target.
+// finishes with one block per target leaf: the sources of the near leaves
+// around it (3x3 with the list rule, the disk of a MAC theta) are staged
+// through LDS in chunks, four waves split the sources, and the local
+// expansion is evaluated at each target.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -95,7 +96,8 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
                                                      const int *__restrict__ start,
                                                      const double2 *__restrict__ Lt, LevelInfo lv,
                                                      int L, int far, double *__restrict__ us,
-                                                     double x0, double y0, double w)
+                                                     double x0, double y0, double w, int K,
+                                                     int kxp)
 {
     __shared__ double sx[kChunk], sy[kChunk], sqv[kChunk];
     __shared__ double red[3][64];
@@ -112,17 +114,18 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
         for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + leaf];
     }
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
-    // targets in slices of 64; sources of the 3x3 leaves in chunks through LDS
+    // targets in slices of 64; sources of the near leaves (the 3x3 block with
+    // the list rule, the disk of radius K with a MAC theta) in chunks through LDS
     for (int tb = t0; tb < t1; tb += 64) {
         const int t = tb + lane;
         const bool tv = t < t1;
         const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
         double acc = 0.0;
-        for (int b = -1; b <= 1; ++b) {
-            const int qy = ly + b;
-            if (qy < 0 || qy >= nl) continue;
-            const int qx0 = lx > 0 ? lx - 1 : 0, qx1 = lx < nl - 1 ? lx + 1 : nl - 1;
-            // the leaves of one row of the 3x3 block are contiguous in the sorted order
+        for (int b = -K; b <= K; ++b) {
+            const int qy = ly + b, kb = ((kxp >> (4 * (b < 0 ? -b : b))) & 15) - 1;
+            if (qy < 0 || qy >= nl || kb < 0) continue;
+            const int qx0 = max(lx - kb, 0), qx1 = min(lx + kb, nl - 1);
+            // the leaves of one row of the near set are contiguous in the sorted order
             const int s0 = start[qy * nl + qx0], s1 = start[qy * nl + qx1 + 1];
             for (int cb = s0; cb < s1; cb += kChunk) {
                 const int cnt = min(kChunk, s1 - cb);
@@ -228,7 +231,7 @@ static int points_fmm_p(fmm_plan *pl, const double *q, double *u, hipStream_t s)
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         hipLaunchKernelGGL(k_leaf_points<P>, dim3(nl * nl), dim3(256), 0, s, pl->px, pl->py, pl->qs,
                            pl->leaf_start, pl->ws.Lt, pl->lv, L, far ? 1 : 0, pl->us, pl->x0,
-                           pl->y0, w);
+                           pl->y0, w, pl->K, near_kx_packed(pl));
     }
     hipLaunchKernelGGL(k_scatter, dim3((N + 255) / 256), dim3(256), 0, s, pl->us, pl->perm, u, N);
     FMM_HIP(pl, hipGetLastError());

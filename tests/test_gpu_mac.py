@@ -12,6 +12,8 @@ uniform tree) against the oracle's traversal, through the C ABI.
   * accuracy against the exact sum (about six digits at p = 6, theta = 0.4)
     and a solve against the oracle's (solution within 1e-6, true residual
     <= 1e-8 recomputed on the CPU, iterations within one);
+  * point clouds with a MAC theta against the oracle's traversal FMM (1e-12),
+    and more accurate than the list rule at the same p;
   * full size (2048^2, p = 6, theta = 0.4, the configuration bench.py times):
     charges in one leaf give the exact lattice sum at every node of the near
     disk around it; 512 sampled nodes against the direct sum within the
@@ -144,6 +146,42 @@ def test_theta_solve_matches_oracle(n):
     say("  iterations gpu %d oracle %d" % (info["iters"], io["iters"]))
     assert abs(info["iters"] - io["iters"]) <= 1
     assert np.linalg.norm(ug - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def _levels(N):
+    L = 0
+    while (64 << (2 * L)) < N:
+        L += 1
+    return L
+
+
+@pytest.mark.parametrize("N,p,theta", [(300, 8, 0.4), (5000, 10, 0.55), (8192, 6, 0.4),
+                                       (20000, 8, 0.3)])
+def test_points_theta_match_oracle(N, p, theta):
+    """Point clouds (u_i = sum_{j != i} q_j G) with the traversal's near disk
+    and lists: against the oracle's traversal FMM (1e-12) and, more accurate
+    than the list rule at the same p, against the direct sum."""
+    import torch
+
+    import paper_1308_3339_amd as fp
+    say("case theta points N=%d p=%d theta=%g" % (N, p, theta))
+    x, y, q = inputs.random_points(N, seed_xy=800 + N, seed_q=900 + N)
+    out = {}
+    for th in (theta, 0.0):
+        with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=dev(x), y=dev(y), theta=th) as plan:
+            u = torch.empty(N, dtype=torch.float64, device="cuda")
+            plan.apply(dev(q), u)
+            out[th] = host(u)
+    uo = o.fmm(_levels(N), 0.0, 0.0, 1.0, p, x, y, q, x, y, 0.0, theta=theta)
+    err = relmax(out[theta], uo)
+    say("  max rel err vs oracle traversal FMM %.3e" % err)
+    assert err <= 1e-12
+    if _levels(N) >= 2:
+        ud = o.direct(x, y, q, x, y, 0.0)
+        e_t = np.linalg.norm(out[theta] - ud) / np.linalg.norm(ud)
+        e_l = np.linalg.norm(out[0.0] - ud) / np.linalg.norm(ud)
+        say("  rel L2 vs direct: theta %.2e, list rule %.2e" % (e_t, e_l))
+        assert e_t < e_l
 
 
 @pytest.fixture(scope="module")
