@@ -77,15 +77,27 @@ def cpu_baseline(n, p, f, iters):
     import oracle as o
     h = 1.0 / (n + 1)
     q = f * h * h
-    t0 = time.perf_counter()
-    o.grid_fmm(n, p, q)
-    t = time.perf_counter() - t0
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        o.grid_fmm(n, p, q)
+        times.append(time.perf_counter() - t0)
+    t = sorted(times)[1]
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / (t * max(iters, 1)), "unit": "solves/s", "cores": o.max_threads(),
-            "kind": "oracle",
-            "sample": "one oracle volume-FMM apply at %dx%d, p=%d (%.2f s wall), scaled by the "
-                      "GPU solve's %d iterations; excludes the oracle's boundary solve, second "
-                      "pass and Arnoldi" % (n, n, p, t, iters),
-            "sample_seconds": t}
+            "kind": "oracle", "cpu": model, "nproc": os.cpu_count(),
+            "sample": "oracle volume-FMM apply at %dx%d, p=%d, same f (median of 3: %.2f s "
+                      "wall), scaled by the GPU solve's %d iterations; excludes the oracle's "
+                      "boundary solve, second pass and Arnoldi" % (n, n, p, t, iters),
+            "sample_seconds": 3 * t}
 
 
 def adjoint_block(fp, inputs, torch, steps, warmup):
