@@ -433,9 +433,9 @@ struct LeafArgs {
     LevelInfo lv;
     int n, nl, L, far;
     // near set (Sec. 5.2): radius K leaves; leaves (a, b) with |a| <= kx(|b|)
-    // are near, kx(b) + 1 packed in 4 bits each (near_kx); ktab side ks = 16K
-    // + 15, rtab side rs = 8K + 9
-    int K, kxp, ks, rs;
+    // are near, kx(b) + 1 packed in 4 bits each (near_kx); rtab side rs = 8K + 9
+    // (ktab side 16K + 15)
+    int K, kxp, rs;
 };
 
 __device__ __forceinline__ int near_kx(int kxp, int b)
@@ -1393,7 +1393,6 @@ static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *
     a.far = far ? 1 : 0;
     a.K = pl->K;
     a.kxp = near_kx_packed(pl);
-    a.ks = 16 * pl->K + 15;
     a.rs = 8 * pl->K + 9;
     return a;
 }

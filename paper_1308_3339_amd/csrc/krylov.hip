@@ -272,13 +272,10 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ v,
     block_reduce_store<1>(acc, part);
 }
 
-// out[i] = sum_b part[i][b] (+ add[i]); mode 1: out[i] = sqrt(sum); out2, if
-// given, also receives the plain sum.  One block per coefficient i; the
-// summation order is fixed.
+// out[i] = sqrt(sum_b part[i][b]) (a norm from its block partials).  One
+// block per row i; the summation order is fixed.
 __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part, int nblk,
-                                                double *__restrict__ out,
-                                                const double *__restrict__ add,
-                                                double *__restrict__ out2, int mode)
+                                                double *__restrict__ out)
 {
     __shared__ double red[4];
     const int i = blockIdx.x;
@@ -289,15 +286,7 @@ __global__ __launch_bounds__(256) void k_finish(const double *__restrict__ part,
     for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double sum = (red[0] + red[1]) + (red[2] + red[3]);
-        if (mode == 1) {
-            out[i] = sqrt(sum);
-        } else {
-            if (out2) out2[i] = sum;
-            out[i] = add ? sum + add[i] : sum;
-        }
-    }
+    if (threadIdx.x == 0) out[i] = sqrt((red[0] + red[1]) + (red[2] + red[3]));
 }
 
 // y = x * (1 / *scal) or y = x * c
@@ -528,8 +517,7 @@ class Fgmres {
 
     int fetch_scalar()
     {
-        hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s_, pl_->partial, nblk_, pl_->dscal + kScal,
-                           nullptr, nullptr, 1);
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s_, pl_->partial, nblk_, pl_->dscal + kScal);
         FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin + kScal, pl_->dscal + kScal, sizeof(double),
                                     hipMemcpyDeviceToHost, s_));
         return FMM_OK;
