@@ -316,7 +316,13 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 // deepest level, laid out [k][tw*tw] with tw = 2^m.
 // The block's own expansion is read from top[k * top_stride] (k < P) in the
 // same round trip as the tables and M2L sums, and also stored to top_out when
-// that is not null.
+// that is not null.  With top == nullptr it is built instead from the M2L
+// sums of its ancestors at levels 2..r (r <= 5), fetched in the same round
+// trip: L~_2 = M2L sum of the level-2 ancestor, then L~_l = B L~_(l-1) + M2L
+// sum, the same chain the launches above it would compute, so that the
+// levels above r need no launch of their own.
+constexpr int kMaxAncestorLevel = 5;
+
 template <int P>
 __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
                                                       double2 *__restrict__ Lt,
@@ -326,9 +332,19 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
                                                       double2 *buf0, double2 *buf1,
                                                       const double2 *__restrict__ top,
                                                       int64_t top_stride,
-                                                      double2 *__restrict__ top_out)
+                                                      double2 *__restrict__ top_out,
+                                                      double2 *sanc)
 {
+    const bool anc = top == nullptr;
     {
+        // M2L sum k of the level-(2 + j) ancestor, t = j P + k
+        auto anc_sum = [&](int t) {
+            const int j = t / P, k = t - j * P, l = 2 + j, nc = 1 << l;
+            const int ax = rx >> (r - l), ay = ry >> (r - l);
+            return Lm[lv.off[l] + k * (int64_t)nc * nc + (int64_t)ay * nc + ax];
+        };
+        double2 va[rounds256((kMaxAncestorLevel - 1) * P)];
+        fetch(va, anc ? (r - 1) * P : 0, anc_sum);
         auto m2l_sum = [&](int st, int t) {
             const int l = r + st, tw = 1 << st, nc = 1 << l;
             const int nn = t >> (2 * st), c = t & (tw * tw - 1);
@@ -338,12 +354,13 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
         double2 vb[rounds256(4 * P * P)], vt[1], v1[rounds256(4 * P)], v2[rounds256(16 * P)],
             v3[rounds256(64 * P)];
         fetch(vb, 4 * P * P, [&](int t) { return B[t]; });
-        fetch(vt, P, [&](int t) { return top[t * top_stride]; });
+        fetch(vt, anc ? 0 : P, [&](int t) { return top[t * top_stride]; });
         fetch(v1, m >= 1 ? 4 * P : 0, [&](int t) { return m2l_sum(1, t); });
         fetch(v2, m >= 2 ? 16 * P : 0, [&](int t) { return m2l_sum(2, t); });
         fetch(v3, m >= 3 ? 64 * P : 0, [&](int t) { return m2l_sum(3, t); });
         put(vb, 4 * P * P, [&](int t, double2 x) { sB[t] = x; });
-        put(vt, P, [&](int t, double2 x) {
+        put(va, anc ? (r - 1) * P : 0, [&](int t, double2 x) { sanc[t] = x; });
+        put(vt, anc ? 0 : P, [&](int t, double2 x) {
             buf0[t] = x;
             if (top_out) top_out[t * top_stride] = x;
         });
@@ -352,6 +369,27 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
         put(v3, m >= 3 ? 64 * P : 0, [&](int t, double2 x) { sm2l[(t >> 6) * 84 + 20 + (t & 63)] = x; });
     }
     __syncthreads();
+    if (anc) {
+        // down the ancestors, one coefficient per thread, into buf0
+        const double2 *cur = sanc;
+        for (int l = 3; l <= r; ++l) {
+            const int ax = rx >> (r - l), ay = ry >> (r - l), qd = (ay & 1) * 2 + (ax & 1);
+            double2 *out = l == r ? buf0 : buf1 + (l & 1) * P;
+            if (threadIdx.x < P) {
+                const int nn = threadIdx.x;
+                double2 acc = sanc[(l - 2) * P + nn];
+                const double2 *Br = sB + (qd * P + nn) * P;
+#pragma unroll
+                for (int k = 0; k < P; ++k)
+                    if (k >= nn) cmac(acc, Br[k], cur[k]);
+                out[nn] = acc;
+            }
+            __syncthreads();
+            cur = out;
+        }
+        if (r == 2 && threadIdx.x < P) buf0[threadIdx.x] = sanc[threadIdx.x];
+        __syncthreads();
+    }
     double2 *prev = buf0;
     int pw = 1;
     for (int st = 1; st <= m; ++st) {
@@ -379,20 +417,25 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
     return prev;
 }
 
+// root: 1 = the root is a level-2 cell (its expansion is its M2L sum, also
+// stored), 0 = read the root's expansion from Lt, 2 = build it from the
+// ancestors (r <= 5)
 template <int P>
 __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
                                               double2 *__restrict__ Lt,
                                               const double2 *__restrict__ B, LevelInfo lv, int r,
-                                              int m, int top)
+                                              int m, int root)
 {
     __shared__ double2 sB[4 * P * P];
     __shared__ double2 sm2l[P * 84];          // M2L sums of the 4 + 16 + 64 descendants
     __shared__ double2 buf0[P * 64], buf1[P * 64];
+    __shared__ double2 sanc[(kMaxAncestorLevel - 1) * P];
     const int nr = 1 << r;
     const int rx = blockIdx.x & (nr - 1), ry = blockIdx.x >> r;
     const int64_t gi = lv.off[r] + (int64_t)ry * nr + rx;
-    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1, (top ? Lm : Lt) + gi,
-                   (int64_t)nr * nr, top ? Lt + gi : nullptr);
+    const double2 *top = root == 2 ? nullptr : (root == 1 ? Lm : Lt) + gi;
+    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1, top, (int64_t)nr * nr,
+                   root == 1 ? Lt + gi : nullptr, sanc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1217,7 +1260,9 @@ __device__ __forceinline__ double pass2_near_at(int gx, int gy, const double *__
 //   u += -(1/2pi) Re sum_k (L~ring_k + L~vol_k) tau^k   (L2P, Sec. 5.3)
 // over the leaves of an 8x8 tile.  The boundary-source expansions L~ring
 // come from one of: none (a.Lt null), the leaf level of a.Lt, or (chain)
-// the three levels below a.Lt's level L-3 built in LDS from the M2L sums Lm.
+// the three levels below level L-3 built in LDS from the M2L sums Lm, with
+// the level-(L-3) root read from a.Lt (chain 1) or built from its ancestors'
+// M2L sums (chain 2, L - 3 <= 5).
 // The volume expansions Lvol (leaf level), when given, are added in LDS, so
 // the preconditioner's two passes share one sweep over u.
 template <int P>
@@ -1228,6 +1273,7 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
     __shared__ double2 sB[4 * P * P];
     __shared__ double2 sm2l[P * 84];
     __shared__ double2 buf0[P * 64], buf1[P * 64];
+    __shared__ double2 sanc[(kMaxAncestorLevel - 1) * P];
     const int n = a.n, nl = a.nl, tw = nl < 8 ? nl : 8, pw = tw * 8;
     const int lx0 = blockIdx.x * tw, ly0 = blockIdx.y * tw, cnt = tw * tw;
     const int ltw = __builtin_ctz(tw);
@@ -1243,9 +1289,10 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
     double2 *sL;
     if (chain) {
         const int r = a.L - 3, nr = 1 << r;
+        const double2 *top =
+            chain == 2 ? nullptr : a.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x;
         sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1,
-                            a.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x,
-                            (int64_t)nr * nr, nullptr);
+                            top, (int64_t)nr * nr, nullptr, sanc);
         if (Lvol) {
             put(vv, P * cnt, [&](int t, double2 x) {
                 sL[t].x += x.x;
@@ -1337,15 +1384,21 @@ static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, hipStream_t s)
 }
 
 
-// downward launches: (root level, levels below it, root is a level-2 cell)
+// downward launches: (root level r, levels below it, root mode of k_down).
+// Levels 2..L in chunks of three: trees with L <= 5 take one launch from the
+// level-2 cells; deeper trees start at level 5, whose blocks build their own
+// root from the ancestors (so levels 2..5 need no launch), then 8, 11, ...
 struct DownChunk {
-    int r, m, top;
+    int r, m, root;
 };
 static std::vector<DownChunk> down_chunks(int L)
 {
     std::vector<DownChunk> ch;
-    ch.push_back({2, std::min(3, L - 2), 1});
-    for (int r = 5; r < L; r += 3) ch.push_back({r, std::min(3, L - r), 0});
+    if (L <= 5) {
+        ch.push_back({2, L - 2, 1});
+        return ch;
+    }
+    for (int r = 5; r < L; r += 3) ch.push_back({r, std::min(3, L - r), r == 5 ? 2 : 0});
     return ch;
 }
 
@@ -1369,7 +1422,7 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (const auto &c : down_chunks(pl->L))
         hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, Lm, Lt, pl->tab.l2l,
-                           pl->lv, c.r, c.m, c.top);
+                           pl->lv, c.r, c.m, c.root);
     return FMM_OK;
 }
 
@@ -1472,15 +1525,19 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, dou
                            pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
                            pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                            pl->nlist);
-        // downward: levels 2..L-3 by k_down, the last three inside the far-field kernel
+        // downward: levels 2..L-3 by k_down, the last three inside the far-field
+        // kernel, whose blocks build their level-(L-3) root from the ancestors
+        // when L - 3 <= 5 (then no k_down launch at all)
         const bool chain = L >= 5;
         const int last = chain ? L - 3 : L;
-        for (const auto &c : down_chunks(last))
-            hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, pl->ws.Lm2,
-                               pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.top);
+        const int chain_mode = !chain ? 0 : (last <= kMaxAncestorLevel ? 2 : 1);
+        if (chain_mode != 2)
+            for (const auto &c : down_chunks(last))
+                hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, pl->ws.Lm2,
+                                   pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.root);
         const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far);
         hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
-                           pl->tab.l2l, chain ? 1 : 0, with_volume ? pl->ws.Lt : nullptr);
+                           pl->tab.l2l, chain_mode, with_volume ? pl->ws.Lt : nullptr);
     }
     const int n = (int)pl->n, B = 8 * (pl->K + 1);
     const int64_t nband = n <= 2 * B ? (int64_t)n * n : (int64_t)4 * B * n - 4 * B * B;

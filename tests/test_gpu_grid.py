@@ -117,7 +117,7 @@ def test_stencil_matches_oracle(n):
     assert np.abs(wg - wo).max() <= 1e-15 * np.abs(wo).max()
 
 
-@pytest.mark.parametrize("n,p", [(8, 6), (16, 10), (32, 10), (64, 10), (128, 12)])
+@pytest.mark.parametrize("n,p", [(8, 6), (16, 10), (32, 10), (64, 10), (128, 12), (512, 10)])
 def test_preconditioner_stages_match_oracle(n, p):
     say("case precond stages n=%d p=%d" % (n, p))
     fp = _fp()

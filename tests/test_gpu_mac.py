@@ -75,7 +75,7 @@ def test_fmm_apply_theta_matches_oracle(n, p, theta):
 
 
 @pytest.mark.parametrize("n,p,theta", [(16, 6, 0.4), (32, 6, 0.4), (64, 6, 0.4), (128, 8, 0.3),
-                                       (128, 6, 0.6), (256, 6, 0.4)])
+                                       (128, 6, 0.6), (256, 6, 0.4), (512, 6, 0.4)])
 def test_precond_stages_theta_match_oracle(n, p, theta):
     import paper_1308_3339_amd as fp
     say("case theta precond stages n=%d p=%d theta=%g" % (n, p, theta))
