@@ -299,6 +299,8 @@ static void release(fmm_plan *pl)
     if (pl->hpin) (void)hipHostFree(pl->hpin);
     drop_step_graphs(pl);
     if (pl->bevent) (void)hipEventDestroy(pl->bevent);
+    for (hipEvent_t e : pl->sevent)
+        if (e) (void)hipEventDestroy(e);
     if (pl->bstream) (void)hipStreamDestroy(pl->bstream);
 }
 

@@ -163,7 +163,8 @@ struct fmm_plan {
     double *w = nullptr, *b = nullptr;
     double *partial = nullptr;    // reduction partials
     double *dscal = nullptr;      // small device scalars / coefficient vectors
-    double *hpin = nullptr;       // pinned host mirror of dscal
+    double *hpin = nullptr;       // pinned host mirror of dscal (two slots)
+    hipEvent_t sevent[2] = {nullptr, nullptr};   // end of step j's copy, slot j & 1
 
     // bump-gradient reduction partials (allocated on first use)
     double *bump_part = nullptr;

@@ -42,6 +42,12 @@ constexpr int kRaw = 0;     // a_0..a_{j-1}, b_0..b_{j-1}, c, d, e
 constexpr int kOut = 72;    // rho, h_j, rt
 constexpr int kCoef = 80;   // sweep-B coefficients: 1/rho, 1/rt, -h_j/(rho rt), -a_i/rho, -(b_i - h_j a_i/rho)/rt
 constexpr int kScal = 160;  // norms
+// pinned host mirror: two slots of kHostSlot doubles; step j's scalars land in
+// slot j & 1, so that step j + 1 may run (and copy) while the host reads j's
+constexpr int kHostSlot = 256;
+// a step is issued ahead of the host's decision when the residual estimate is
+// above this multiple of the tolerance (one more step cannot reach it)
+constexpr double kSpecMargin = 1e3;
 
 __global__ __launch_bounds__(256) void k_stencil(const double *__restrict__ v,
                                                  double *__restrict__ w, int n, double ih2)
@@ -405,7 +411,10 @@ static int ensure_krylov(fmm_plan *pl, int m)
     if (!pl->b) FMM_HIP(pl, hipMalloc(&pl->b, N * sizeof(double)));
     if (!pl->partial) FMM_HIP(pl, hipMalloc(&pl->partial, (size_t)kRedBlocks * kPartRows * sizeof(double)));
     if (!pl->dscal) FMM_HIP(pl, hipMalloc(&pl->dscal, 256 * sizeof(double)));
-    if (!pl->hpin) FMM_HIP(pl, hipHostMalloc((void **)&pl->hpin, 256 * sizeof(double), hipHostMallocDefault));
+    if (!pl->hpin)
+        FMM_HIP(pl, hipHostMalloc((void **)&pl->hpin, 2 * kHostSlot * sizeof(double), hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i)
+        if (!pl->sevent[i]) FMM_HIP(pl, hipEventCreateWithFlags(&pl->sevent[i], hipEventDisableTiming));
     hipError_t e1 = hipMalloc(&pl->V, (size_t)(m + 1) * N * sizeof(double));
     if (e1 != hipSuccess) return fail(pl, FMM_ERR_ALLOC, "Krylov basis allocation failed");
     hipError_t e2 = hipMalloc(&pl->Z, (size_t)m * N * sizeof(double));
@@ -425,13 +434,30 @@ static int ensure_krylov(fmm_plan *pl, int m)
 // A single solve drives it with a stream synchronisation per chunk; the
 // batch driver interleaves many solves on their own streams.  With graphs,
 // step j of a plan is captured once into a HIP graph and replayed.
+//
+// With spec (single solves), step j + 1 is issued before the host has read
+// step j's scalars whenever step j - 1 left the residual estimate far above
+// the tolerance; the host then waits for step j's event only, and the GPU
+// runs on while it does the Givens update.  A step issued this way that turns
+// out not to be needed only writes basis vectors beyond the cycle's last one.
 class Fgmres {
   public:
     Fgmres(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params &prm,
-           hipStream_t s, Faces fc, bool graphs)
+           hipStream_t s, Faces fc, bool graphs, bool spec = false)
         : pl_(pl), f_(f), g_(g), u_(u), tol_(prm.tol), m_(prm.restart), maxit_(prm.maxit), s_(s),
-          fc_(fc), var_(fc.ax != nullptr), graphs_(graphs)
+          fc_(fc), var_(fc.ax != nullptr), graphs_(graphs), spec_(spec && !graphs)
     {
+    }
+
+    // waits for the work advance() consumes next
+    int wait()
+    {
+        if (phase_ == STEP && spec_) {
+            FMM_HIP(pl_, hipEventSynchronize(pl_->sevent[j_ & 1]));
+        } else {
+            FMM_HIP(pl_, hipStreamSynchronize(s_));
+        }
+        return FMM_OK;
     }
 
     int begin()
@@ -484,7 +510,10 @@ class Fgmres {
             beta_ = beta;
             rt_prev_ = 0.0;
             j_ = 0;
-            return issue_step();
+            ahead_ = -1;
+            const int st = issue_step();
+            if (st != FMM_OK) return st;
+            return issue_ahead(beta / bnorm_);
         }
         case STEP: {
             int st = consume_step();
@@ -494,7 +523,11 @@ class Fgmres {
                 return issue_residual();
             }
             ++j_;
-            return issue_step();
+            if (ahead_ != j_) {
+                st = issue_step();
+                if (st != FMM_OK) return st;
+            }
+            return issue_ahead(est_);
         }
         case DONE:
             break;
@@ -539,6 +572,14 @@ class Fgmres {
     }
 
     // the launches of Arnoldi step j (identical on every call, so capturable)
+    // with spec: step j_ + 1 now, if an estimate of est leaves it certainly needed
+    int issue_ahead(double est)
+    {
+        if (!spec_ || j_ + 1 >= m_ || iters_ + 2 > maxit_ || !(est > tol_ * kSpecMargin)) return FMM_OK;
+        ahead_ = j_ + 1;
+        return launch_step(j_ + 1);
+    }
+
     int launch_step(int j)
     {
         double *uj = pl_->V + (size_t)j * N_, *zj = pl_->Z + (size_t)j * N_;
@@ -557,8 +598,9 @@ class Fgmres {
         else
             launch_arnoldi_update<false>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
         ta.stop();
-        FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin, pl_->dscal, kCoef * sizeof(double),
-                                    hipMemcpyDeviceToHost, s_));
+        FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin + kHostSlot * (j & 1), pl_->dscal,
+                                    kCoef * sizeof(double), hipMemcpyDeviceToHost, s_));
+        if (spec_) FMM_HIP(pl_, hipEventRecord(pl_->sevent[j & 1], s_));
         return FMM_OK;
     }
 
@@ -589,8 +631,9 @@ class Fgmres {
     int consume_step()
     {
         const int j = j_, m = m_;
-        const double *a = pl_->hpin + kRaw, *bb = pl_->hpin + kRaw + j;
-        const double rho = pl_->hpin[kOut], hj = pl_->hpin[kOut + 1], rt = pl_->hpin[kOut + 2];
+        const double *hs = pl_->hpin + kHostSlot * (j & 1);
+        const double *a = hs + kRaw, *bb = hs + kRaw + j;
+        const double rho = hs[kOut], hj = hs[kOut + 1], rt = hs[kOut + 2];
         if (!(rho > 0.0) || !std::isfinite(rho) || !std::isfinite(hj) || !std::isfinite(rt))
             return fail(pl_, FMM_ERR_NUMERIC, "Arnoldi produced a non-finite or zero norm");
         if (j == 0) {
@@ -650,7 +693,8 @@ class Fgmres {
     int m_, maxit_;
     hipStream_t s_;
     Faces fc_;
-    bool var_, graphs_;
+    bool var_, graphs_, spec_;
+    int ahead_ = -1;   // step issued ahead of the host's decision, or -1
     int n_ = 0, ln_ = 0, nblk_ = 1;
     int64_t N_ = 0;
     double ih2_ = 0.0;
@@ -664,11 +708,11 @@ class Fgmres {
 int gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u, const gmres_params *prm,
                 gmres_result *res, hipStream_t s, const double *ax, const double *ay)
 {
-    Fgmres sol(pl, f, g, u, *prm, s, Faces{ax, ay}, false);
+    Fgmres sol(pl, f, g, u, *prm, s, Faces{ax, ay}, false, true);
     int st = sol.begin();
     while (st == FMM_OK && !sol.done()) {
-        FMM_HIP(pl, hipStreamSynchronize(s));
-        st = sol.advance();
+        st = sol.wait();
+        if (st == FMM_OK) st = sol.advance();
     }
     if (st != FMM_OK) return st;
     FMM_HIP(pl, hipStreamSynchronize(s));
