@@ -1319,6 +1319,36 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
         __syncthreads();
         sL = buf0;
     }
+    if (pw == 64) {
+        // element e = threadIdx.x + 256 r: column xx = threadIdx.x % 64 is fixed and row yy =
+        // threadIdx.x / 64 + 4 r takes two in-leaf offsets (r even, r odd), so each class
+        // of eight points shares the powers of tau (same per-point order of operations)
+        const int xx = threadIdx.x & 63, y0 = threadIdx.x >> 6;
+#pragma unroll
+        for (int cls = 0; cls < 2; ++cls) {
+            const double2 tau = make_double2(((xx & 7) - 3.5) * 0.125, (((y0 + 4 * cls) & 7) - 3.5) * 0.125);
+            double far[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) far[j] = 0.0;
+            double2 pk = make_double2(1.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int yy = y0 + 4 * (2 * j + cls);
+                    const double2 c = sL[k * 64 + (yy >> 3) * 8 + (xx >> 3)];
+                    far[j] = fma(c.x, pk.x, fma(-c.y, pk.y, far[j]));
+                }
+                pk = cmul(pk, tau);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int yy = y0 + 4 * (2 * j + cls);
+                a.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far[j] * kInv2Pi;
+            }
+        }
+        return;
+    }
 #pragma unroll 4
     for (int e = threadIdx.x; e < pw * pw; e += 256) {
         const int yy = e / pw, xx = e - yy * pw;
