@@ -44,6 +44,49 @@ def leaf_kernel_flops(n, p):
     return 2.0 * pairs + 4.0 * p * n * n
 
 
+PEAK_HBM_TBS = 8.0             # MI355X HBM3E
+
+
+def m2l_translations(L):
+    """M2L translations of one application on the uniform tree with the list rule
+    (children of the parent's 3x3 neighbourhood minus the own 3x3 block, cut at
+    the domain edge), levels 2..L."""
+    return sum(16 * (3 * 2 ** (l - 1) - 2) ** 2 - (3 * 2 ** l - 2) ** 2 for l in range(2, L + 1))
+
+
+def stage_rooflines(n, p, prof):
+    """Each timed stage of one solve against its own bound.  prof maps a stage to
+    (ms per solve, timed calls per solve: one per application or Arnoldi step).  Algorithmic work per launch:
+      LEAF    leaf_kernel_flops (near-field pairs + P2M), FP64 VALU;
+      M2L     8 p^2 flops per translation (p^2 complex multiply-adds), FP64 VALU;
+      BEM     the eight folded (n/2)^2 FP64 halves of the boundary inverse, HBM;
+      ARNOLDI step j reads z, v_0..v_j twice and writes two vectors: (2j+6) 8N bytes, HBM.
+    The tree passes (M2M, L2L, RING, PASS2) and the residuals (STENCIL) are bound by
+    the latency of their dependent steps; only their time is given."""
+    L = (n // 8).bit_length() - 1
+    N = n * n
+    out = {}
+    for name, (ms, cnt) in prof.items():
+        if not cnt or ms <= 0:
+            continue
+        sec = ms * 1e-3
+        if name == "LEAF":
+            work, unit, peak, bound = leaf_kernel_flops(n, p) * cnt / 1e12, "TFLOP/s", PEAK_FP64_VALU_TFLOPS, "alu"
+        elif name == "M2L":
+            work, unit, peak, bound = 8.0 * p * p * m2l_translations(L) * cnt / 1e12, "TFLOP/s", PEAK_FP64_VALU_TFLOPS, "alu"
+        elif name == "BEM":
+            work, unit, peak, bound = 8.0 * (n // 2) ** 2 * 8 * cnt / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
+        elif name == "ARNOLDI":
+            work, unit, peak, bound = sum((2 * j + 6) * 8.0 * N for j in range(cnt)) / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
+        else:
+            out[name] = {"ms_per_solve": round(ms, 4), "calls": cnt, "bound": "latency"}
+            continue
+        ach = work / sec
+        out[name] = {"ms_per_solve": round(ms, 4), "calls": cnt, "bound": bound, "achieved": round(ach, 3),
+                     "unit": unit, "peak": peak, "frac": round(ach / peak, 4)}
+    return out
+
+
 def leaf_kernel_hash():
     """sha256 of the source text of k_leaf_grid (from its template line to the
     closing brace), so that only a change of that kernel invalidates the
@@ -336,7 +379,9 @@ def main():
     plan.profile(fp.STAGES)
     u.zero_()
     plan.solve(f, u)
-    stages = {k: round(v[0], 4) for k, v in plan.profile_read().items()}
+    sprof = plan.profile_read()
+    stages = {k: round(v[0], 4) for k, v in sprof.items()}
+    stage_roof = stage_rooflines(n, p, sprof)
     plan.profile(())
 
     # bare FMM and preconditioner throughput (HIP events on the same stream)
@@ -528,6 +573,7 @@ def main():
         "setup_s": round(setup_s, 3),
         "tuned_vector_blocks": vec_blocks,
         "stages_ms_per_solve": stages,
+        "stage_rooflines": stage_roof,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variant_fp32": variant,
