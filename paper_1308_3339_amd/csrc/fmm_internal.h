@@ -158,6 +158,7 @@ struct fmm_plan {
 
     // Krylov workspace (GRID)
     int kry_m = 0;
+    int64_t ldb = 0;      // element stride between Krylov basis vectors (n^2 plus padding)
     double *V = nullptr;          // (m+1) x N
     double *Z = nullptr;          // m x N
     double *w = nullptr, *b = nullptr;

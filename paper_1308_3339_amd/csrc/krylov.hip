@@ -35,6 +35,7 @@ namespace fmmprec {
 
 constexpr int kMaxBasis = 32;   // restart <= 32
 constexpr int kRedBlocks = 4096;  // partial sums per reduction (coefficient-major)
+constexpr int64_t kBasisPad = 256; // elements between consecutive basis vectors beyond n^2
 constexpr int kPartRows = 2 * kMaxBasis + 4;
 
 // layout of plan->dscal (device) / plan->hpin (host mirror)
@@ -415,9 +416,12 @@ static int ensure_krylov(fmm_plan *pl, int m)
         FMM_HIP(pl, hipHostMalloc((void **)&pl->hpin, 2 * kHostSlot * sizeof(double), hipHostMallocDefault));
     for (int i = 0; i < 2; ++i)
         if (!pl->sevent[i]) FMM_HIP(pl, hipEventCreateWithFlags(&pl->sevent[i], hipEventDisableTiming));
-    hipError_t e1 = hipMalloc(&pl->V, (size_t)(m + 1) * N * sizeof(double));
+    // vectors n^2 = 2^(2k) elements apart would start on the same memory
+    // channels, and the sweeps stream up to m + 2 of them side by side
+    pl->ldb = (int64_t)N + kBasisPad;
+    hipError_t e1 = hipMalloc(&pl->V, (size_t)(m + 1) * pl->ldb * sizeof(double));
     if (e1 != hipSuccess) return fail(pl, FMM_ERR_ALLOC, "Krylov basis allocation failed");
-    hipError_t e2 = hipMalloc(&pl->Z, (size_t)m * N * sizeof(double));
+    hipError_t e2 = hipMalloc(&pl->Z, (size_t)m * pl->ldb * sizeof(double));
     if (e2 != hipSuccess) return fail(pl, FMM_ERR_ALLOC, "Krylov basis allocation failed");
     pl->kry_m = m;
     return FMM_OK;
@@ -582,21 +586,22 @@ class Fgmres {
 
     int launch_step(int j)
     {
-        double *uj = pl_->V + (size_t)j * N_, *zj = pl_->Z + (size_t)j * N_;
+        const int64_t ld = pl_->ldb;
+        double *uj = pl_->V + (size_t)j * ld, *zj = pl_->Z + (size_t)j * ld;
         int st = precond_apply_one(pl_, uj, zj, nullptr, nullptr, s_);
         if (st != FMM_OK) return st;
         StageTimer ta(pl_, FMM_STAGE_ARNOLDI, s_);
         const dim3 gv(nblk_);
         if (var_)
-            launch_arnoldi_dots<true>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
+            launch_arnoldi_dots<true>(j, gv, s_, zj, pl_->V, ld, pl_->partial, n_, ln_, ih2_, fc_);
         else
-            launch_arnoldi_dots<false>(j, gv, s_, zj, pl_->V, N_, pl_->partial, n_, ln_, ih2_, fc_);
+            launch_arnoldi_dots<false>(j, gv, s_, zj, pl_->V, ld, pl_->partial, n_, ln_, ih2_, fc_);
         hipLaunchKernelGGL(k_arnoldi_coef, dim3(1), dim3(1024), 0, s_, pl_->partial, nblk_,
                            pl_->dscal, j);
         if (var_)
-            launch_arnoldi_update<true>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
+            launch_arnoldi_update<true>(j, gv, s_, zj, pl_->V, ld, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
         else
-            launch_arnoldi_update<false>(j, gv, s_, zj, pl_->V, N_, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
+            launch_arnoldi_update<false>(j, gv, s_, zj, pl_->V, ld, pl_->dscal + kCoef, n_, ln_, ih2_, fc_);
         ta.stop();
         FMM_HIP(pl_, hipMemcpyAsync(pl_->hpin + kHostSlot * (j & 1), pl_->dscal,
                                     kCoef * sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -682,7 +687,7 @@ class Fgmres {
         }
         Coef cy{};
         for (int i = 0; i < k; ++i) cy.c[i] = y_[i];
-        hipLaunchKernelGGL(k_axpy_multi, dim3(nblk_), dim3(256), 0, s_, pl_->Z, N_, k, cy, u_, N_);
+        hipLaunchKernelGGL(k_axpy_multi, dim3(nblk_), dim3(256), 0, s_, pl_->Z, pl_->ldb, k, cy, u_, N_);
         r_.restarts++;
     }
 
@@ -820,7 +825,7 @@ int tune_vector_blocks(fmm_plan *pl, hipStream_t s, int *chosen)
     FMM_HIP(pl, hipEventCreate(&e0));
     FMM_HIP(pl, hipEventCreate(&e1));
     // a finite basis to sweep over (values do not affect the timing)
-    hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->V, pl->V, nullptr, 0.0, N * 6);
+    hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->V, pl->V, nullptr, 0.0, pl->ldb * 6);
     hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->Z, pl->Z, nullptr, 0.0, N);
     float best_ms = 1e30f;
     int best = red_blocks(nullptr, N);
@@ -830,9 +835,9 @@ int tune_vector_blocks(fmm_plan *pl, hipStream_t s, int *chosen)
         float ms = 0.0f;
         for (int rep = 0; rep < 3; ++rep) {
             FMM_HIP(pl, hipEventRecord(e0, s));
-            launch_arnoldi_dots<false>(4, dim3(nb), s, pl->Z, pl->V, N, pl->partial, n, ln, ih2,
+            launch_arnoldi_dots<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->partial, n, ln, ih2,
                                        Faces{nullptr, nullptr});
-            launch_arnoldi_update<false>(4, dim3(nb), s, pl->Z, pl->V, N, pl->dscal + kCoef, n, ln,
+            launch_arnoldi_update<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->dscal + kCoef, n, ln,
                                          ih2, Faces{nullptr, nullptr});
             FMM_HIP(pl, hipEventRecord(e1, s));
             FMM_HIP(pl, hipEventSynchronize(e1));
