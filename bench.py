@@ -9,9 +9,10 @@ leaves, FGMRES(30) to a 1e-8 true relative residual, all in FP64.  Setup
 separately.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  Also reports the bare FMM throughput (Mpoints/s),
-a per-stage breakdown, the roofline of the dominant kernel (the fused
-L2P + P2P leaf kernel, timed with HIP events on the library's stream over
-the timed region) and the CPU oracle on a bounded sample.
+a per-stage breakdown with each stage against its own bound, the roofline of
+the dominant kernel (the leaf kernel: near field and P2M, timed with HIP
+events on the library's stream over the timed region) and the CPU oracle on
+a bounded sample.
 """
 import argparse
 import hashlib
