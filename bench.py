@@ -298,7 +298,7 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter-collection driver: one 512 MiB elementwise y = x*1 (the "
                          "calibration kernel of known size: 512 MiB read, 512 MiB written), "
-                         "then 3 FMM applies and 3 preconditioner applies")
+                         "then 3 FMM applies, 3 preconditioner applies and one solve")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -345,8 +345,10 @@ def main():
             plan.apply(q, out)
         for _ in range(3):
             plan.precond_apply(q, out)
+        info = plan.solve(f, u)
         torch.cuda.synchronize()
-        print(json.dumps({"probe": "done", "copy_bytes_each_way": x.numel() * 8, "n": n, "p": p}))
+        print(json.dumps({"probe": "done", "copy_bytes_each_way": x.numel() * 8, "n": n, "p": p,
+                          "solve_iters": info["iters"], "vector_blocks": vec_blocks}))
         plan.close()
         return
 
