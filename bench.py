@@ -227,6 +227,59 @@ def varcoef_block(fp, inputs, torch, plan, f, steps, warmup):
             "iters": info["iters"], "true_rel_res": rel}
 
 
+def points_block(fp, inputs, torch, steps, warmup):
+    """Point-cloud FMM (Sec. 5 on a uniform tree, list rule): 1,048,576 uniform
+    random points in the unit square, charges U(-1, 1), p = 10, FP64 next to
+    FMM_FP32 (near field pairwise in FP32 with the polynomial logarithm and
+    Kahan sums, Secs. 5.3 and 7.1; far field FP64).  Near pairs counted from
+    the leaf occupancy (every ordered pair of points in 3x3-adjacent leaves,
+    self pairs excluded)."""
+    import numpy as np
+    N, p = 1 << 20, 10
+    x, y, q = inputs.random_points(N)
+    L = 0
+    while (64 << (2 * L)) < N:
+        L += 1
+    nl = 1 << L
+    ix = np.clip(np.floor(x * nl).astype(np.int64), 0, nl - 1)
+    iy = np.clip(np.floor(y * nl).astype(np.int64), 0, nl - 1)
+    cnt = np.bincount(iy * nl + ix, minlength=nl * nl).reshape(nl, nl).astype(np.float64)
+    pad = np.pad(cnt, 1)
+    near = sum(pad[1 + b:1 + b + nl, 1 + a:1 + a + nl] for b in (-1, 0, 1) for a in (-1, 0, 1))
+    pairs = float((cnt * near).sum() - N)
+    dev = torch.device("cuda:0")
+    xd, yd, qd = (torch.from_numpy(v).to(dev) for v in (x, y, q))
+    out = {}
+    res = {}
+    for name, prec in (("fp64", fp.FMM_FP64), ("fp32", fp.FMM_FP32)):
+        with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=xd, y=yd, prec=prec) as pl:
+            u = torch.empty(N, dtype=torch.float64, device=dev)
+            for _ in range(max(warmup, 1)):
+                pl.apply(qd, u)
+            pl.profile(("LEAF",))
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                pl.apply(qd, u)
+            e1.record(st)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            lms, ln = pl.profile_read().get("LEAF", (0.0, 0))
+            pl.profile(())
+            leaf_ms = lms / max(ln, 1)
+            res[name] = u.clone()
+            out[name] = {"apply_ms": round(ms, 4), "mpoints_per_s": round(N / (ms * 1e-3) / 1e6, 2),
+                         "leaf_ms": round(leaf_ms, 4),
+                         "near_gpairs_per_s": round(pairs / (leaf_ms * 1e-3) / 1e9, 2)}
+    diff = float((res["fp32"] - res["fp64"]).abs().max() / res["fp64"].abs().max())
+    return {"workload": "%d uniform random points in the unit square (seeds %d, %d), q ~ U(-1,1), "
+                        "p=%d, list rule, L=%d" % (N, inputs.SEED_POINTS_XY, inputs.SEED_POINTS_Q, p, L),
+            "near_pairs": pairs, "fp64": out["fp64"], "fp32": out["fp32"],
+            "fp32_max_rel_diff_vs_fp64": diff,
+            "fp32_speedup": round(out["fp64"]["apply_ms"] / out["fp32"]["apply_ms"], 3)}
+
+
 def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     """64 independent solves of uneven sizes (16 each of 128^2, 256^2, 512^2,
     1024^2; instance k has 16 bumps seeded 1000 + k), p = 10, FGMRES(30) to
@@ -514,6 +567,10 @@ def main():
                                   "avg_launch_ms": round(avg, 5), "achieved": round(ach, 3),
                                   "unit": "TFLOP/s", "peak": 78.6, "frac": round(ach / 78.6, 4)}}
 
+    log("point cloud, 1M points")
+    points = points_block(fp, inputs, torch, args.steps, args.warmup)
+    log("points fp64 %.1f Mpoints/s, fp32 %.1f Mpoints/s" % (points["fp64"]["mpoints_per_s"],
+                                                            points["fp32"]["mpoints_per_s"]))
     log("mac theta")
     mac = mac_block(6, 0.4)
     log("mac theta p=6 theta=0.4: %.2f solves/s, %d iterations" % (mac["solves_per_s"],
@@ -585,6 +642,7 @@ def main():
         "variable_coefficient": varcoef,
         "batched": batched,
         "mac_theta": mac,
+        "points": points,
     }
     plan.close()
     print(json.dumps(res), flush=True)

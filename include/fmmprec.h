@@ -63,6 +63,11 @@ typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
  * plans): the near field (P2P) and P2M run as FP32 matrix-core contractions
  * (each 64-term FP32 partial folded into FP64) and the multipole-to-local
  * translations in FP32 (the preconditioner's tunable accuracy, Sec. 6.2).
+ * FMM_FP32 (POINTS plans): the near field runs pairwise in FP32 as in Secs.
+ * 5.3 and 7.1 (FP32 offsets from the target leaf's centre, log2 from a
+ * polynomial fit of log2(x)/(x - 1), Kahan-compensated sums; pairs whose
+ * FP32 r^2 is below the smallest normal float are left out like the self
+ * pair); P2M, M2M, M2L, L2L and L2P stay FP64.
  * FMM_SPLIT_FP16 (GRID plans): as FMM_FP32, but the near field and P2M take
  * each operand as an FP16 pair x = hi + lo (charges scaled per tile by a
  * power of two) and sum hi*hi + hi*lo + lo*hi on the FP16 matrix cores with
@@ -92,7 +97,8 @@ typedef struct {
 /* FMM parameters.
  *   p        number of expansion coefficients, M_0..M_{p-1} (Sec. 5.3), 2..20.
  *   leaf     points per leaf side squared; must be 64 (8 x 8 grid blocks).
- *   prec     fmm_precision (FMM_FP32 for GRID plans only).
+ *   prec     fmm_precision (FMM_FP32 for GRID and POINTS plans, FMM_SPLIT_FP16
+ *            for GRID plans).
  *   bem      GRID: 1 = boundary correction on (Sec. 4), 0 = free-space
  *            volume potential only.  Ignored for POINTS.
  *   self_eps GRID: the singular self term is G_self = -(1/2pi) log(self_eps h)

@@ -328,8 +328,8 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (prm->leaf != 64) return fail(nullptr, FMM_ERR_ARG, "leaf must be 64");
     if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32 && prm->prec != FMM_SPLIT_FP16)
         return fail(nullptr, FMM_ERR_UNSUPPORTED, "prec must be FMM_FP64, FMM_FP32 or FMM_SPLIT_FP16");
-    if (prm->prec != FMM_FP64 && prob->kind != FMM_GRID)
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "reduced precision is built for GRID plans");
+    if (prm->prec == FMM_SPLIT_FP16 && prob->kind != FMM_GRID)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "FMM_SPLIT_FP16 is built for GRID plans");
     if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
         return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
     if (!(prm->theta == 0.0 || (prm->theta >= kThetaMin && prm->theta <= 1.0)))

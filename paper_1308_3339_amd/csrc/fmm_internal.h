@@ -28,6 +28,7 @@ constexpr int kPMax = 20;
 constexpr int kMaxLevels = 24;
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr double kInv2Pi = 1.0 / (2.0 * kPi);
+constexpr double kLn2 = 0.693147180559945309417;
 // MAC theta (Sec. 5.2): smallest accepted value (near radius K <= 4) and the
 // LDS the M2L kernel may use for its source tile
 constexpr double kThetaMin = 0.3;

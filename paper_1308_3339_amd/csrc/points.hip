@@ -9,12 +9,16 @@
 // finishes with one block per target leaf: the sources of the near leaves
 // around it (3x3 with the list rule, the disk of a MAC theta) are staged
 // through LDS in chunks, four waves split the sources, and the local
-// expansion is evaluated at each target.
+// expansion is evaluated at each target.  FMM_FP32 plans run that near
+// field pairwise in FP32 (the paper's P2P of Secs. 5.3 and 7.1: a polynomial
+// logarithm and Kahan-compensated sums); the far field stays FP64.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <vector>
 
 #include "fmm_internal.h"
+#include "log2_poly.h"
 
 namespace fmmprec {
 
@@ -166,6 +170,113 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
     }
 }
 
+// log2(x) for a normal FP32 x > 0: the exponent from the bits, the mantissa
+// folded into [1/sqrt(2), sqrt(2)) and log2(m) = u p(u), u = m - 1 (Sec. 5.3's
+// polynomial fit of log2(x)/(x - 1); coefficients in log2_poly.h).
+__device__ __forceinline__ float log2_poly(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    int e = (int)(b >> 23) - 127;
+    float m = __uint_as_float((b & 0x007fffffu) | 0x3f800000u);
+    if (m > 1.41421356f) {
+        m *= 0.5f;
+        ++e;
+    }
+    const float u = m - 1.0f;
+    float p = kLog2Poly[kLog2PolyDegree];
+#pragma unroll
+    for (int i = kLog2PolyDegree - 1; i >= 0; --i) p = fmaf(p, u, kLog2Poly[i]);
+    return fmaf(u, p, (float)e);
+}
+
+// FMM_FP32 form of k_leaf_points: the same blocks, waves and source chunks,
+// with the pair sums in FP32 (Sec. 7.1).  Coordinates enter as FP32 offsets
+// from the target leaf's centre (at most 1.5 leaf widths for the 3x3 near
+// set), the charges as FP32; each lane sums q_j log2(r^2) over its quarter of
+// the sources with Kahan compensation, and the four quarter sums, the factor
+// ln2 / 2 and the FP64 local expansion are combined in FP64.  A pair with r^2
+// below the smallest normal FP32 number (the target itself, or two points
+// that FP32 offsets cannot tell apart) is left out like the self pair.
+template <int P>
+__global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restrict__ px,
+                                                         const double *__restrict__ py,
+                                                         const double *__restrict__ qs,
+                                                         const int *__restrict__ start,
+                                                         const double2 *__restrict__ Lt, LevelInfo lv,
+                                                         int L, int far, double *__restrict__ us,
+                                                         double x0, double y0, double w, int K,
+                                                         int kxp)
+{
+    __shared__ float sx[kChunk], sy[kChunk], sqv[kChunk];
+    __shared__ double red[3][64];
+    const int nl = 1 << L;
+    const int leaf = blockIdx.x;
+    const int lx = leaf % nl, ly = leaf / nl;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t0 = start[leaf], t1 = start[leaf + 1];
+    double2 Lc[P];
+    if (far) {
+        const int64_t ncell = (int64_t)nl * nl;
+        const double2 *Ll = Lt + lv.off[L];
+#pragma unroll
+        for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + leaf];
+    }
+    const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
+    for (int tb = t0; tb < t1; tb += 64) {
+        const int t = tb + lane;
+        const bool tv = t < t1;
+        const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
+        const float txf = (float)(tx - cx), tyf = (float)(ty - cy);
+        float ks = 0.0f, kc = 0.0f;   // Kahan sum of q log2(r^2) and its compensation
+        for (int b = -K; b <= K; ++b) {
+            const int qy = ly + b, kb = ((kxp >> (4 * (b < 0 ? -b : b))) & 15) - 1;
+            if (qy < 0 || qy >= nl || kb < 0) continue;
+            const int qx0 = max(lx - kb, 0), qx1 = min(lx + kb, nl - 1);
+            const int s0 = start[qy * nl + qx0], s1 = start[qy * nl + qx1 + 1];
+            for (int cb = s0; cb < s1; cb += kChunk) {
+                const int cnt = min(kChunk, s1 - cb);
+                __syncthreads();
+                for (int e = threadIdx.x; e < cnt; e += 256) {
+                    sx[e] = (float)(px[cb + e] - cx);
+                    sy[e] = (float)(py[cb + e] - cy);
+                    sqv[e] = (float)qs[cb + e];
+                }
+                __syncthreads();
+                if (tv) {
+                    for (int e = wv; e < cnt; e += 4) {
+                        const float dx = txf - sx[e], dy = tyf - sy[e];
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        if (r2 >= FLT_MIN) {
+                            const float y = fmaf(sqv[e], log2_poly(r2), -kc);
+                            const float tsum = ks + y;
+                            kc = (tsum - ks) - y;
+                            ks = tsum;
+                        }
+                    }
+                }
+            }
+        }
+        double acc = ((double)ks - (double)kc) * (0.5 * kLn2);
+        __syncthreads();
+        if (wv > 0) red[wv - 1][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && tv) {
+            acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+            double farv = 0.0;
+            if (far) {
+                const double2 tau = make_double2((tx - cx) * iw, (ty - cy) * iw);
+                double2 pk = make_double2(1.0, 0.0);
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    farv = fma(Lc[k].x, pk.x, fma(-Lc[k].y, pk.y, farv));
+                    pk = pcmul(pk, tau);
+                }
+            }
+            us[t] = -(acc + farv) * kInv2Pi;
+        }
+    }
+}
+
 int points_setup(fmm_plan *pl, const double *dx, const double *dy, hipStream_t s)
 {
     const int64_t N = pl->n;
@@ -229,9 +340,14 @@ static int points_fmm_p(fmm_plan *pl, const double *q, double *u, hipStream_t s)
     }
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
-        hipLaunchKernelGGL(k_leaf_points<P>, dim3(nl * nl), dim3(256), 0, s, pl->px, pl->py, pl->qs,
-                           pl->leaf_start, pl->ws.Lt, pl->lv, L, far ? 1 : 0, pl->us, pl->x0,
-                           pl->y0, w, pl->K, near_kx_packed(pl));
+        if (pl->prec == FMM_FP32)
+            hipLaunchKernelGGL(k_leaf_points_f32<P>, dim3(nl * nl), dim3(256), 0, s, pl->px, pl->py,
+                               pl->qs, pl->leaf_start, pl->ws.Lt, pl->lv, L, far ? 1 : 0, pl->us,
+                               pl->x0, pl->y0, w, pl->K, near_kx_packed(pl));
+        else
+            hipLaunchKernelGGL(k_leaf_points<P>, dim3(nl * nl), dim3(256), 0, s, pl->px, pl->py,
+                               pl->qs, pl->leaf_start, pl->ws.Lt, pl->lv, L, far ? 1 : 0, pl->us,
+                               pl->x0, pl->y0, w, pl->K, near_kx_packed(pl));
     }
     hipLaunchKernelGGL(k_scatter, dim3((N + 255) / 256), dim3(256), 0, s, pl->us, pl->perm, u, N);
     FMM_HIP(pl, hipGetLastError());
