@@ -31,12 +31,13 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
 
 
-def run(x, y, q, p, prec):
+def run(x, y, q, p, prec, theta=0.0):
     import torch
 
     import paper_1308_3339_amd as fp
     N = len(x)
-    with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=dev(x), y=dev(y), prec=prec) as plan:
+    with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=dev(x), y=dev(y), prec=prec,
+                      theta=theta) as plan:
         u = torch.empty(N, dtype=torch.float64, device="cuda")
         plan.apply(dev(q), u)
         torch.cuda.synchronize()
@@ -48,6 +49,21 @@ def levels(N):
     while (64 << (2 * L)) < N:
         L += 1
     return L
+
+
+def test_points_fp32_single_point():
+    import paper_1308_3339_amd as fp
+    x, y, q = np.array([0.3]), np.array([0.7]), np.array([1.5])
+    assert np.array_equal(run(x, y, q, 6, fp.FMM_FP32), np.zeros(1))
+
+
+def test_points_fp32_with_list_rule_theta():
+    """theta = 0.8 > 1/sqrt(2) gives the list rule's lists (the only theta FP32
+    plans take): the same result as theta = 0 bit for bit."""
+    import paper_1308_3339_amd as fp
+    N, p = 5000, 8
+    x, y, q = inputs.random_points(N, seed_xy=1401, seed_q=1402)
+    assert np.array_equal(run(x, y, q, p, fp.FMM_FP32, theta=0.8), run(x, y, q, p, fp.FMM_FP32))
 
 
 @pytest.mark.parametrize("N,p", [(2, 6), (300, 8), (5000, 10), (20000, 10), (100000, 10)])
