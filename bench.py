@@ -513,10 +513,12 @@ def main():
                                   "mfma_flops_per_algorithmic_flop": mfma_per_flop,
                                   "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)}}
 
-    def mac_block(p_t, theta):
+    def mac_block(p_t, theta, prec=fp.FMM_FP64):
         """MAC theta (Sec. 5.2): the 2048^2 solve with the dual tree
-        traversal's near disk and lists, next to the list-rule plan."""
-        pl = fp.fmm_setup(n=n, p=p_t, bem=1, theta=theta)
+        traversal's near disk and lists, next to the list-rule plan.  With
+        prec = FMM_FP32 the near field of the disk runs on the FP32 matrix
+        cores and M2L in FP32 (the single-precision P2P of Sec. 7.1)."""
+        pl = fp.fmm_setup(n=n, p=p_t, bem=1, theta=theta, prec=prec)
         pl.tune()
         for _ in range(args.warmup):
             u.zero_()
@@ -537,7 +539,7 @@ def main():
         pl.close()
         # volume potential against the p = 14 list-rule potential (about 1e-9)
         uv, ur = torch.empty_like(q), torch.empty_like(q)
-        with fp.fmm_setup(n=n, p=p_t, bem=0, theta=theta) as pv:
+        with fp.fmm_setup(n=n, p=p_t, bem=0, theta=theta, prec=prec) as pv:
             pv.apply(q, uv)
         with fp.fmm_setup(n=n, p=14, bem=0) as pr:
             pr.apply(q, ur)
@@ -555,7 +557,9 @@ def main():
         leaf_ms_t, leaf_n_t = prof.get("LEAF", (0.0, 0))
         avg = leaf_ms_t / max(leaf_n_t, 1)
         ach = flops_t / (avg * 1e-3) / 1e12
-        return {"p": p_t, "theta": theta, "near_leaves": sum(
+        fp32 = prec == fp.FMM_FP32
+        peak_t = 157.3 if fp32 else PEAK_FP64_VALU_TFLOPS
+        return {"p": p_t, "theta": theta, "prec": "fp32" if fp32 else "fp64", "near_leaves": sum(
                     1 for b in range(-kk, kk + 1) for a in range(-kk, kk + 1) if a * a + b * b <= lim),
                 "solves_per_s": round(args.steps / tv, 4),
                 "ms_per_step": round(1000.0 * tv / args.steps, 4),
@@ -563,9 +567,11 @@ def main():
                 "iters": inf["iters"], "true_rel_res": relv,
                 "volume_rel_l2_diff_vs_p14": dv,
                 "stages_ms_per_solve": {k: round(v[0], 4) for k, v in prof.items()},
-                "leaf_roofline": {"bound": "alu", "kernel": "k_leaf_wide", "pairs": pairs,
-                                  "avg_launch_ms": round(avg, 5), "achieved": round(ach, 3),
-                                  "unit": "TFLOP/s", "peak": 78.6, "frac": round(ach / 78.6, 4)}}
+                "leaf_roofline": {"bound": "mfma" if fp32 else "alu",
+                                  "kernel": "k_leaf_wide_mfma32" if fp32 else "k_leaf_wide",
+                                  "pairs": pairs, "avg_launch_ms": round(avg, 5),
+                                  "achieved": round(ach, 3), "unit": "TFLOP/s", "peak": peak_t,
+                                  "frac": round(ach / peak_t, 4)}}
 
     log("point cloud, 1M points")
     points = points_block(fp, inputs, torch, args.steps, args.warmup)
@@ -575,6 +581,8 @@ def main():
     mac = mac_block(6, 0.4)
     log("mac theta p=6 theta=0.4: %.2f solves/s, %d iterations" % (mac["solves_per_s"],
                                                                    mac["iters"]))
+    mac32 = mac_block(6, 0.4, fp.FMM_FP32)
+    log("mac theta fp32: %.2f solves/s, %d iterations" % (mac32["solves_per_s"], mac32["iters"]))
     log("precision variants")
     variant = variant_block(fp.FMM_FP32, "P2P and P2M as FP32 MFMA contractions, M2L in FP32; "
                             "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1)
@@ -642,6 +650,7 @@ def main():
         "variable_coefficient": varcoef,
         "batched": batched,
         "mac_theta": mac,
+        "mac_theta_fp32": mac32,
         "points": points,
     }
     plan.close()

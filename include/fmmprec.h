@@ -117,9 +117,10 @@ typedef struct {
  *            outside it; theta > 1/sqrt(2) gives the list rule again.
  *            Smaller theta trades more near-field and M2L work for accuracy
  *            at a given p (p = 6, theta = 0.4 gives about six digits).
- *            theta < 1/sqrt(2) requires FMM_FP64, p <= 12 and
- *            p (16 + 4K)^2 * 16 <= 160 KiB, K = floor(sqrt(2)/theta) (so
- *            p <= 10 for theta < 0.354); otherwise FMM_ERR_UNSUPPORTED. */
+ *            theta < 1/sqrt(2) requires FMM_FP64 (any kind) or FMM_FP32 (GRID:
+ *            the disk's near field on the FP32 matrix cores, M2L in FP32),
+ *            p <= 12 and p (16 + 4K)^2 * 16 <= 160 KiB, K = floor(sqrt(2)/theta)
+ *            (so p <= 10 for theta < 0.354); otherwise FMM_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t p;
     int32_t leaf;

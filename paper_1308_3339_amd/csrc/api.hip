@@ -166,7 +166,7 @@ static int build_tables(fmm_plan *pl)
     for (int dy = 0; dy < RS; ++dy)
         for (int dx = 0; dx < RS; ++dx)
             if (dx || dy) rt[(size_t)dy * RS + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
-    // the reduced-precision leaf kernels exist for the 3x3 near set only
+    // FP32 and split-FP16 tables (the split-FP16 leaf kernel exists for the 3x3 near set only)
     std::vector<float> kt32(kt.begin(), kt.end());
     const int prow = 16 * ((2 * p + 15) / 16);
     std::vector<float> p2m32((size_t)prow * 64, 0.0f);
@@ -335,8 +335,10 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (!(prm->theta == 0.0 || (prm->theta >= kThetaMin && prm->theta <= 1.0)))
         return fail(nullptr, FMM_ERR_ARG, "theta must be 0 (interaction lists) or in [0.3, 1]");
     const int Kt = near_radius(prm->theta);
-    if (Kt > 1 && (prm->prec != FMM_FP64 || prm->p > kThetaPMax))
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "theta < 1/sqrt(2) is built for FP64 plans with p <= 12");
+    if (Kt > 1 && (prm->prec == FMM_SPLIT_FP16 || prm->p > kThetaPMax ||
+                   (prm->prec == FMM_FP32 && prob->kind != FMM_GRID)))
+        return fail(nullptr, FMM_ERR_UNSUPPORTED,
+                    "theta < 1/sqrt(2) is built for FP64 plans and FP32 grid plans, with p <= 12");
     if (Kt > 1 && (int64_t)prm->p * (16 + 4 * Kt) * (16 + 4 * Kt) * 16 > kM2LMaxLds)
         return fail(nullptr, FMM_ERR_UNSUPPORTED, "p too large for this theta (M2L source tile exceeds LDS)");
     hipStream_t s = (hipStream_t)stream;

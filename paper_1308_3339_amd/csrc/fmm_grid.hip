@@ -799,6 +799,129 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
     }
 }
 
+// FP32 leaf stage with the near set of a MAC theta (radius K >= 2): the
+// contraction of k_leaf_mfma32 over the leaf offsets of the lattice disk
+// (rows |oy| <= K, columns |ox| <= kx(|oy|)) instead of the 3x3 block.
+// Block = 8x8 target leaves, wave w = leaves 16w..16w+15 (rows 2w, 2w+1), as
+// there.  LDS: the (8+2K)^2-leaf q tile in FP32 at
+//   (pos/4) * TW*72 + row*72 + (pos%4)*16 + col,   col < TW = 8 + 2K <= 16,
+// so one B read (8 columns x 2 rows x 4 positions) covers the 64 banks once;
+// the kernel table T (side 16K + 15) with rows 80 floats apart (a half-wave's
+// 2 rows x 11 columns of A addresses on distinct banks).  Bounds: row and
+// column of a B read are ly + K + oy and lx + K + ox, both in [0, TW); a T
+// index dy + 8K + 7 with |dy| <= 8K + 7 stays in [0, 16K + 15).
+template <int P, int K>
+__global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const float *__restrict__ kt32,
+                                                          const float *__restrict__ w32)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int TW = 8 + 2 * K, PS = TW * 72, KC = 8 * K + 7, KS = 2 * KC + 1, TS = KS;
+    constexpr int MTP = (2 * P + 15) / 16;      // P2M row tiles
+    static_assert(TW <= 16 && KS <= TS, "tile layout");
+    __shared__ float sq[16 * PS];
+    __shared__ float st[KS * TS];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = a.n, nl = a.nl;
+    const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
+    const int X0 = (TX0 - K) * 8, Y0 = (TY0 - K) * 8;
+    constexpr int PW = 8 * TW, NE = PW * PW, NB = 8;
+#pragma unroll 1
+    for (int base = 0; base < NE; base += 256 * NB) {
+        float v[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = base + tid + 256 * i;
+            const int yy = e / PW, xx = e - yy * PW;
+            const int gx = X0 + xx, gy = Y0 + yy;
+            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)a.q[(size_t)gy * n + gx] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = base + tid + 256 * i;
+            const int yy = e / PW, xx = e - yy * PW;
+            const int pos = (yy & 7) * 8 + (xx & 7);
+            if (e < NE) sq[(pos >> 2) * PS + (yy >> 3) * 72 + (pos & 3) * 16 + (xx >> 3)] = v[i];
+        }
+    }
+    for (int e = tid; e < KS * KS; e += 256) st[(e / KS) * TS + e % KS] = kt32[e];
+    __syncthreads();
+    const int g = lane >> 4, m16 = lane & 15;
+    const int lx = m16 & 7, ly = 2 * wave + (m16 >> 3);   // leaf of this lane's B column
+    // A operand of lane: target t = 16 mt + m16 -> tx = lane & 7, ty = 2 mt + ((lane >> 3) & 1);
+    // source s = 4 kk + g -> sx = 4 (kk & 1) + g, sy = kk >> 1
+    const int abase = (KC - ((lane >> 3) & 1)) * TS + KC + g - (lane & 7);
+    const int bbase = (ly + K) * 72 + g * 16 + lx + K;
+    double acc[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
+#pragma unroll 1
+    for (int oy = -K; oy <= K; ++oy) {
+        const int kxo = near_kx(a.kxp, oy < 0 ? -oy : oy);
+#pragma unroll 1
+        for (int ox = -kxo; ox <= kxo; ++ox) {
+            f4 c[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            const float *Ab = st + abase + 8 * oy * TS + 8 * ox;
+            const float *Bb = sq + bbase + oy * 72 + ox;
+#pragma unroll 4
+            for (int kk = 0; kk < 16; ++kk) {
+                const float b = Bb[kk * PS];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    c[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[((kk >> 1) - 2 * mt) * TS + 4 * (kk & 1)], b,
+                                                                 c[mt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+        }
+    }
+    // P2M: rows of w32 against the centre leaves
+    f4 pm[MTP];
+#pragma unroll
+    for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.M) {
+        const float *Bb = sq + bbase;
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const float b = Bb[kk * PS];
+#pragma unroll
+            for (int mt = 0; mt < MTP; ++mt)
+                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(w32[(16 * mt + m16) * 64 + 4 * kk + g], b,
+                                                              pm[mt], 0, 0, 0);
+        }
+    }
+    const int gLx = TX0 + lx, gLy = TY0 + ly;
+    if (gLx >= nl || gLy >= nl) return;
+    const double qs = -a.qscale * kInv2Pi;
+    // D row m = 4 g + i of tile mt is target t = 16 mt + 4 g + i: ty = 2 mt + g / 2, tx = 4 (g & 1) + i
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
+    }
+    if (a.M) {
+        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+        double2 *Ml = a.M + a.lv.off[a.L];
+        // D rows 16 mt + 4 g + {0,1} and {2,3} are (Re, Im) of coefficients 8 mt + 2 g + {0, 1}
+#pragma unroll
+        for (int mt = 0; mt < MTP; ++mt)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int k = 8 * mt + 2 * g + j;
+                if (k < P)
+                    Ml[k * ncell + cell] = make_double2(a.qscale * (double)pm[mt][2 * j],
+                                                        a.qscale * (double)pm[mt][2 * j + 1]);
+            }
+    }
+}
+
 // Split-FP16 variant of the leaf stage: the contraction of k_leaf_mfma32 on
 // the FP16 matrix cores (v_mfma_f32_16x16x32_f16, K = 32 source positions =
 // four source rows per product).  Each operand is an FP16 pair x = hi + lo:
@@ -1491,6 +1614,18 @@ static void launch_leaf_wide(fmm_plan *pl, dim3 gl, const LeafArgs &a, hipStream
     }
 }
 
+// FP32 plans with a MAC theta (K >= 2)
+template <int P>
+static void launch_leaf_wide_mfma32(fmm_plan *pl, dim3 gl, const LeafArgs &a, hipStream_t s)
+{
+    if constexpr (P <= kThetaPMax) {
+        const float *kt = pl->tab.ktab32, *w = pl->tab.p2m32;
+        if (pl->K == 2) hipLaunchKernelGGL((k_leaf_wide_mfma32<P, 2>), gl, dim3(256), 0, s, a, kt, w);
+        else if (pl->K == 3) hipLaunchKernelGGL((k_leaf_wide_mfma32<P, 3>), gl, dim3(256), 0, s, a, kt, w);
+        else if (pl->K == 4) hipLaunchKernelGGL((k_leaf_wide_mfma32<P, 4>), gl, dim3(256), 0, s, a, kt, w);
+    }
+}
+
 template <int P>
 static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, double *u,
                              double *ring_out, bool defer_l2p, hipStream_t s)
@@ -1506,6 +1641,8 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
         if (pl->prec == FMM_SPLIT_FP16)
             hipLaunchKernelGGL(k_leaf_mfma16<P>, gl, dim3(256), 0, s, a, pl->tab.ktab16,
                                pl->tab.p2m16);
+        else if (fp32 && pl->K > 1)
+            launch_leaf_wide_mfma32<P>(pl, gl, a, s);
         else if (fp32)
             hipLaunchKernelGGL(k_leaf_mfma32<P>, gl, dim3(256), 0, s, a, pl->tab.ktab32,
                                pl->tab.p2m32);

@@ -66,10 +66,11 @@ def test_setup_rejects_unbuilt_precision():
     assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
 
 
-@pytest.mark.parametrize("kw", [dict(theta=0.4, prec=1), dict(theta=0.4, prec=2),
+@pytest.mark.parametrize("kw", [dict(theta=0.4, prec=1, kind=1), dict(theta=0.4, prec=2),
                                 dict(theta=0.3, p=11), dict(theta=0.4, p=14)])
 def test_setup_rejects_unbuilt_theta_combinations(kw):
-    # small theta: FP64 plans with p <= 12 only, and the M2L source tile must fit in LDS
+    # small theta: FP64 plans and FP32 grid plans with p <= 12 only, and the M2L
+    # source tile must fit in LDS
     code, ptr, msg = _setup_raw(**kw)
     assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
     assert "theta" in msg
