@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probe", action="store_true",
-                    help="counter-collection driver: one 512 MiB elementwise y = x*1 (the "
+                    help="counter-collection mode: one 512 MiB elementwise y = x*1 (the "
                          "calibration kernel of known size: 512 MiB read, 512 MiB written), "
                          "then 3 FMM applies, 3 preconditioner applies and one solve")
     args = ap.parse_args()

@@ -436,7 +436,7 @@ static int ensure_krylov(fmm_plan *pl, int m)
 //   RES   true residual r = b - A u and |r| (start of a cycle)
 //   STEP  one Arnoldi step j (preconditioner, both sweeps, coefficients)
 // A single solve drives it with a stream synchronisation per chunk; the
-// batch driver interleaves many solves on their own streams.  With graphs,
+// batch loop interleaves many solves on their own streams.  With graphs,
 // step j of a plan is captured once into a HIP graph and replayed.
 //
 // With spec (single solves), step j + 1 is issued before the host has read
