@@ -46,6 +46,7 @@ def leaf_kernel_flops(n, p):
 
 
 PEAK_HBM_TBS = 8.0             # MI355X HBM3E
+PEAK_FP32_VALU_TFLOPS = 157.3  # MI355X FP32 vector (packed FP32 issue)
 
 
 def m2l_translations(L):
@@ -502,6 +503,11 @@ def main():
         leaf_ms_v, leaf_n_v = prof.get("LEAF", (0.0, 0))
         avg = leaf_ms_v / max(leaf_n_v, 1)
         ach = flops / (avg * 1e-3) / 1e12
+        # M2L in FP32 on the vector ALU (k_m2l<P, float>): 8 p^2 flops per translation
+        m2l_ms_v, m2l_n_v = prof.get("M2L", (0.0, 0))
+        m2l_avg = m2l_ms_v / max(m2l_n_v, 1)
+        m2l_flops = 8.0 * p * p * m2l_translations((n // 8).bit_length() - 1)
+        m2l_ach = m2l_flops / (m2l_avg * 1e-3) / 1e12 if m2l_avg > 0 else 0.0
         return {"prec": label, "solves_per_s": round(args.steps / tv, 4),
                 "ms_per_step": round(1000.0 * tv / args.steps, 4),
                 "speedup_vs_fp64": round((args.steps / tv) / solves_per_s, 3),
@@ -511,7 +517,15 @@ def main():
                                   "avg_launch_ms": round(avg, 5),
                                   "achieved": round(ach, 3), "unit": "TFLOP/s",
                                   "mfma_flops_per_algorithmic_flop": mfma_per_flop,
-                                  "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)}}
+                                  "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)},
+                "m2l_roofline": {"bound": "alu", "kernel": "k_m2l<P, float>",
+                                 "avg_call_ms": round(m2l_avg, 5), "achieved": round(m2l_ach, 3),
+                                 "unit": "TFLOP/s", "peak": PEAK_FP32_VALU_TFLOPS,
+                                 "frac": round(m2l_ach / PEAK_FP32_VALU_TFLOPS, 4),
+                                 # the library is built without packed FP32 instructions,
+                                 # which halves the vector FP32 rate it can issue
+                                 "peak_unpacked": PEAK_FP32_VALU_TFLOPS / 2,
+                                 "frac_unpacked": round(2 * m2l_ach / PEAK_FP32_VALU_TFLOPS, 4)}}
 
     def mac_block(p_t, theta, prec=fp.FMM_FP64):
         """MAC theta (Sec. 5.2): the 2048^2 solve with the dual tree
