@@ -1563,7 +1563,9 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
     const size_t shm = (size_t)P * rw * rw * sizeof(double2);
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
-        if (pl->prec != FMM_FP64)
+        // reduced-precision grid plans translate in FP32; point clouds take only
+        // their near field in FP32 (Sec. 7.1) and keep M2L in FP64
+        if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems), dim3(768), shm / 2, s, items, M, Lm,
                                pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K);
