@@ -745,7 +745,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
         for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
         const float *Ab = st + abase + 8 * oy * 48 + 8 * ox;
         const float *Bb = sq + bbase + oy * 136 + ox;
-#pragma unroll 4
+#pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
             const float b = Bb[kk * 453];
 #pragma unroll
@@ -867,7 +867,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
             for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
             const float *Ab = st + abase + 8 * oy * TS + 8 * ox;
             const float *Bb = sq + bbase + oy * 72 + ox;
-#pragma unroll 4
+#pragma unroll
             for (int kk = 0; kk < 16; ++kk) {
                 const float b = Bb[kk * PS];
 #pragma unroll
