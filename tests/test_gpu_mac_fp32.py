@@ -107,3 +107,24 @@ def test_fp32_theta_solve(n):
         say("  CPU-recomputed true rel res %.3e" % res)
         assert res <= 1e-8
     assert its[fp.FMM_FP32] <= its[fp.FMM_FP64] + 1
+
+
+def test_fp32_theta_fullsize_sampled_against_direct():
+    """2048^2, p = 6, theta = 0.4 (the configuration bench.py times) with the
+    FP32 near field and M2L: 512 sampled nodes against the direct sum, within
+    the FP64 theta plan's bar (2e-6: truncation about 1e-6, FP32 adds about
+    2e-7)."""
+    import paper_1308_3339_amd as fp
+    n = 2048
+    say("case fp32 theta fullsize sampled")
+    q = inputs.random_charges(n * n, seed=77)
+    with fp.fmm_setup(n=n, p=6, bem=0, theta=0.4, prec=fp.FMM_FP32) as plan:
+        u = empty(n * n)
+        plan.apply(dev(q), u)
+        ug = host(u)
+    idx = inputs.target_subset(n * n, 512, seed=78)
+    gx, gy = o.grid_points(n)
+    ud = o.direct(gx, gy, q, gx[idx], gy[idx], o.self_log(n))
+    err = np.linalg.norm(ug[idx] - ud) / np.linalg.norm(ud)
+    say("  rel L2 err at 512 sampled nodes %.3e" % err)
+    assert err <= 2e-6

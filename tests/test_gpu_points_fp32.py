@@ -107,3 +107,19 @@ def test_points_split_fp16_rejected():
     x, y, _ = inputs.random_points(100, seed_xy=1, seed_q=2)
     with pytest.raises(fp.FmmError):
         fp.fmm_setup(kind=fp.FMM_POINTS, n=100, p=6, x=dev(x), y=dev(y), prec=fp.FMM_SPLIT_FP16)
+
+
+def test_points_fp32_one_million_against_direct_subset():
+    """The bare-FMM workload at full size: 1M U(0,1)^2 points, U(-1,1)
+    charges, p = 12, FP32 near field, against the direct sum on the seeded
+    4096-target subset (the FP64 plan's bar, 1e-6: FP32 adds about 1e-7)."""
+    import paper_1308_3339_amd as fp
+    say("case points fp32 N=1M p=12")
+    N = 1 << 20
+    x, y, q = inputs.random_points(N)
+    ug = run(x, y, q, 12, fp.FMM_FP32)
+    idx = inputs.target_subset(N, 4096)
+    ud = o.direct(x, y, q, x[idx], y[idx], 0.0)
+    err = np.linalg.norm(ug[idx] - ud) / np.linalg.norm(ud)
+    say("  rel L2 vs direct on 4096 targets %.3e" % err)
+    assert err <= 1e-6
