@@ -819,6 +819,19 @@ int orc_pc_apply(void *v, const double *r, double *z)
     return orc_pc_apply_ex(v, r, z, NULL, NULL);
 }
 
+/* The boundary stage alone: sigma = -S^{-1} phi_ring (Sec. 4.3, the
+ * collocation system with zero Dirichlet data), with the factors of S kept
+ * by the preconditioner.  Returns -1 when it was built without bem. */
+int orc_pc_bem_solve(void *v, const double *phi_ring, double *sigma)
+{
+    orc_pc *pc = (orc_pc *)v;
+    if (!pc->bem) return -1;
+    int m = 4 * pc->n;
+    for (int k = 0; k < m; ++k) sigma[k] = -phi_ring[k];
+    orc_lu_solve(m, pc->LU, pc->piv, sigma);
+    return 0;
+}
+
 /* ======================================================================== */
 /* Right-preconditioned FGMRES(m), modified Gram-Schmidt, Givens rotations.  */
 /* pc == NULL means the identity preconditioner.  x holds x0 on entry.       */

@@ -41,10 +41,10 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = False) -> str:
-    """Compile fmm_oracle.c into libfmm_oracle.so (gcc, -O2, OpenMP)."""
+    """Compile fmm_oracle.c into libfmm_oracle.so (gcc, -O3, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-std=gnu99", "-O3", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -98,6 +98,8 @@ def lib():
         L.orc_pc_destroy.argtypes = [ctypes.c_void_p]
         L.orc_pc_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_pc_apply_ex.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
+        L.orc_pc_bem_solve.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_pc_bem_solve.restype = ctypes.c_int
         L.orc_fgmres.argtypes = [ctypes.c_int, ctypes.c_void_p, _dp, _dp, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, _ip, _dp, _dp]
         L.orc_fgmres.restype = ctypes.c_int
@@ -321,6 +323,14 @@ class Preconditioner:
         phi_r, sig = np.zeros(4 * self.n), np.zeros(4 * self.n)
         lib().orc_pc_apply_ex(self._pc, _ptr(r), _ptr(z), _ptr(phi_r), _ptr(sig))
         return z, phi_r, sig
+
+    def bem_solve(self, phi_ring):
+        """sigma = -S^{-1} phi_ring with the preconditioner's factors of S."""
+        phi = _f64(phi_ring).reshape(-1)
+        sig = np.zeros_like(phi)
+        if lib().orc_pc_bem_solve(self._pc, _ptr(phi), _ptr(sig)) != 0:
+            raise ValueError("preconditioner was built without the boundary correction")
+        return sig
 
     def close(self):
         if self._pc:
