@@ -267,6 +267,20 @@ int fmm_bumps_grad(fmm_plan *plan, int32_t K, const double *cx, const double *cy
                    const double *w, const double *a, const double *g, double *gcx,
                    double *gcy, double *gw, double *ga, void *stream);
 
+/* As fmm_bumps_grad, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * the call allocates nothing.  Its partial sums live in a static workspace
+ * of the library, 1 MiB per device (the partials of K <= 256 bumps), which
+ * each device the library runs on keeps until the process ends; larger K
+ * is rejected with FMM_ERR_ARG.  Every call on one device shares that
+ * workspace and fully overwrites the part it reads, so nothing carries over
+ * between calls, but calls that overlap on one device (two streams, or two
+ * threads) race and must be ordered by the caller.  Arguments, outputs and
+ * results are those of fmm_bumps_grad (bitwise: the same kernels). */
+int fmm_bumps_grad_noalloc(fmm_plan *plan, int32_t K, const double *cx, const double *cy,
+                           const double *w, const double *a, const double *g, double *gcx,
+                           double *gcy, double *gw, double *ga, void *stream);
+
 /* Per-stage device timing (tracing support).  Stages of an apply or solve:
  * P2M (a pass of its own in FMM_FP32 plans), M2M, M2L, L2L (Sec. 5.3 items
  * 1-4; L2L also covers the far-field L2P sweep when no boundary pass

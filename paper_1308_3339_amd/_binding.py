@@ -22,6 +22,7 @@ exported_symbols = (
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
     "fmm_stencil_var_apply", "precond_gmres_solve_var", "precond_gmres_solve_batch", "fmm_tune",
+    "fmm_bumps_grad_noalloc",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -107,6 +108,8 @@ def load_library():
     L.fmm_bumps_eval.restype = i32
     L.fmm_bumps_grad.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.fmm_bumps_grad.restype = i32
+    L.fmm_bumps_grad_noalloc.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
+    L.fmm_bumps_grad_noalloc.restype = i32
     L.fmm_destroy.argtypes = [vp]
     L.fmm_destroy.restype = i32
     L.fmm_last_error.argtypes = [vp]
@@ -317,6 +320,16 @@ def fmm_bumps_grad(plan, cx, cy, w, a, g, gcx=None, gcy=None, gw=None, ga=None, 
     return _check(code, plan._ptr)
 
 
+def fmm_bumps_grad_noalloc(plan, cx, cy, w, a, g, gcx=None, gcy=None, gw=None, ga=None,
+                           stream=None):
+    """fmm_bumps_grad without any device allocation (static workspace)."""
+    K, ptrs = _bump_args(cx, cy, w, a)
+    outs = [_dptr(t, nm, K) for t, nm in ((gcx, "gcx"), (gcy, "gcy"), (gw, "gw"), (ga, "ga"))]
+    code = load_library().fmm_bumps_grad_noalloc(plan._ptr, K, *ptrs, _dptr(g, "g", plan.npts),
+                                                 *outs, _stream(stream))
+    return _check(code, plan._ptr)
+
+
 def fmm_profile(plan, stages=()):
     """Enable hipEvent timing of the named stages (empty: disable)."""
     mask = 0
@@ -359,6 +372,7 @@ class Plan:
     solve_var = precond_gmres_solve_var
     bumps_eval = fmm_bumps_eval
     bumps_grad = fmm_bumps_grad
+    bumps_grad_noalloc = fmm_bumps_grad_noalloc
     profile = fmm_profile
     profile_read = fmm_profile_read
 

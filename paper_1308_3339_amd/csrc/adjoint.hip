@@ -11,6 +11,7 @@
 // Both kernels are HBM bound (one or two sweeps over the grid); the sums are
 // two-stage with a fixed order, so results are bitwise reproducible.
 #include <cmath>
+#include <mutex>
 
 #include "fmm_internal.h"
 
@@ -18,6 +19,18 @@ namespace fmmprec {
 
 constexpr int kBumpMax = 256;        // bumps per call
 constexpr int kBumpBlocks = 128;     // partial sums per (bump, quantity)
+
+// Workspace of the allocation-free gradient entry point: the block partials
+// of up to kBumpMax bumps, resident on every device the library runs on
+// until the process ends (1 MiB each).  Host code never passes the array's
+// name to a kernel: it takes the device address from hipGetSymbolAddress,
+// once per device, and keeps it in g_scratch_addr.
+constexpr int kScratchDoubles = kBumpMax * 4 * kBumpBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_addr[kMaxDevices] = {};
 
 struct BumpParams {
     const double *cx, *cy, *w, *a;
@@ -125,6 +138,20 @@ int bumps_eval(fmm_plan *pl, int K, const double *cx, const double *cy, const do
     return FMM_OK;
 }
 
+// the two launches of a gradient evaluation, partials in part
+// (K * 4 * kBumpBlocks doubles, every one written before it is read)
+static int bumps_grad_launch(fmm_plan *pl, int K, const BumpParams &bp, const double *g,
+                             double *part, double *gcx, double *gcy, double *gw, double *ga,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bumps_grad_part, dim3(kBumpBlocks, K), dim3(256), 0, s, bp, g, part,
+                       (int)pl->n, pl->L + 3, pl->h);
+    hipLaunchKernelGGL(k_bumps_grad_finish, dim3(K), dim3(64), 0, s, bp, part, kBumpBlocks, gcx,
+                       gcy, gw, ga);
+    FMM_HIP(pl, hipGetLastError());
+    return FMM_OK;
+}
+
 int bumps_grad(fmm_plan *pl, int K, const double *cx, const double *cy, const double *w,
                const double *a, const double *g, double *gcx, double *gcy, double *gw,
                double *ga, hipStream_t s)
@@ -132,13 +159,41 @@ int bumps_grad(fmm_plan *pl, int K, const double *cx, const double *cy, const do
     if (K < 1 || K > kBumpMax) return fail(pl, FMM_ERR_ARG, "K must be in [1, 256]");
     if (!pl->bump_part)
         FMM_HIP(pl, hipMalloc(&pl->bump_part, (size_t)kBumpMax * 4 * kBumpBlocks * sizeof(double)));
-    const BumpParams bp{cx, cy, w, a};
-    hipLaunchKernelGGL(k_bumps_grad_part, dim3(kBumpBlocks, K), dim3(256), 0, s, bp, g,
-                       pl->bump_part, (int)pl->n, pl->L + 3, pl->h);
-    hipLaunchKernelGGL(k_bumps_grad_finish, dim3(K), dim3(64), 0, s, bp, pl->bump_part,
-                       kBumpBlocks, gcx, gcy, gw, ga);
-    FMM_HIP(pl, hipGetLastError());
+    return bumps_grad_launch(pl, K, BumpParams{cx, cy, w, a}, g, pl->bump_part, gcx, gcy, gw, ga, s);
+}
+
+// Device address of the static workspace on the current device, looked up
+// once per device (at plan setup, with the plan's device current).
+int bumps_scratch_init(fmm_plan *pl)
+{
+    int dev = 0;
+    FMM_HIP(pl, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(pl, FMM_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *addr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !addr)
+            return fail(pl, FMM_ERR_DEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<double *>(addr);
+    }
+    pl->bump_scratch = g_scratch_addr[dev];
     return FMM_OK;
+}
+
+int bumps_grad_noalloc(fmm_plan *pl, int K, const double *cx, const double *cy, const double *w,
+                       const double *a, const double *g, double *gcx, double *gcy, double *gw,
+                       double *ga, hipStream_t s)
+{
+    if (K < 1 || K > kBumpMax)
+        return fail(pl, FMM_ERR_ARG,
+                    "K must be in [1, 256] (the static workspace holds the partials of 256 bumps)");
+    if (!pl->bump_scratch) return fail(pl, FMM_ERR_DEVICE, "static workspace address unknown");
+    if ((int64_t)K * 4 * kBumpBlocks > kScratchDoubles)
+        return fail(pl, FMM_ERR_ARG, "request exceeds the static workspace");
+    return bumps_grad_launch(pl, K, BumpParams{cx, cy, w, a}, g, pl->bump_scratch, gcx, gcy, gw, ga,
+                             s);
 }
 
 }  // namespace fmmprec

@@ -408,6 +408,12 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
             return st;
         }
     }
+    if (pl->kind == FMM_GRID && (st = bumps_scratch_init(pl)) != FMM_OK) {
+        g_setup_error = pl->err;
+        release(pl);
+        delete pl;
+        return st;
+    }
     if (pl->kind == FMM_GRID && pl->bem) {
         if ((st = bem_setup(pl, s)) != FMM_OK) {
             g_setup_error = pl->err;
@@ -621,6 +627,16 @@ int fmm_bumps_grad(fmm_plan *pl, int32_t K, const double *cx, const double *cy, 
     if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "bumps need a GRID plan");
     if (!cx || !cy || !w || !a || !g) return fail(pl, FMM_ERR_ARG, "NULL bump parameter or g");
     return bumps_grad(pl, K, cx, cy, w, a, g, gcx, gcy, gw, ga, (hipStream_t)stream);
+}
+
+int fmm_bumps_grad_noalloc(fmm_plan *pl, int32_t K, const double *cx, const double *cy,
+                           const double *w, const double *a, const double *g, double *gcx,
+                           double *gcy, double *gw, double *ga, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "bumps need a GRID plan");
+    if (!cx || !cy || !w || !a || !g) return fail(pl, FMM_ERR_ARG, "NULL bump parameter or g");
+    return bumps_grad_noalloc(pl, K, cx, cy, w, a, g, gcx, gcy, gw, ga, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -168,8 +168,11 @@ struct fmm_plan {
     double *hpin = nullptr;       // pinned host mirror of dscal (two slots)
     hipEvent_t sevent[2] = {nullptr, nullptr};   // end of step j's copy, slot j & 1
 
-    // bump-gradient reduction partials (allocated on first use)
+    // bump-gradient reduction partials (allocated on first use), and the
+    // device address of the library's static workspace on the plan's device
+    // (used by the allocation-free entry point; not owned by the plan)
     double *bump_part = nullptr;
+    double *bump_scratch = nullptr;
 
     // Krylov vector kernels: tuned block count (0: one block per 1024 elements)
     int vec_blocks = 0;
@@ -244,6 +247,10 @@ int bumps_eval(fmm_plan *plan, int K, const double *cx, const double *cy, const 
 int bumps_grad(fmm_plan *plan, int K, const double *cx, const double *cy, const double *w,
                const double *a, const double *g, double *gcx, double *gcy, double *gw,
                double *ga, hipStream_t s);
+int bumps_grad_noalloc(fmm_plan *plan, int K, const double *cx, const double *cy,
+                       const double *w, const double *a, const double *g, double *gcx,
+                       double *gcy, double *gw, double *ga, hipStream_t s);
+int bumps_scratch_init(fmm_plan *plan);
 int points_setup(fmm_plan *plan, const double *dx, const double *dy, hipStream_t s);
 
 // ---- boundary correction (bem.hip) ----
