@@ -603,8 +603,11 @@ def main():
     variant16 = variant_block(fp.FMM_SPLIT_FP16, "P2P and P2M as FP16 hi+lo MFMA products "
                               "(hi*hi + hi*lo + lo*hi, FP32 accumulation), M2L in FP32; M2M, L2L, "
                               "L2P, boundary, stencil, Arnoldi FP64", 2500.0, 3)
-    log("fp32 variant %.2f solves/s, split-fp16 %.2f" % (variant["solves_per_s"],
-                                                         variant16["solves_per_s"]))
+    variantb16 = variant_block(fp.FMM_SPLIT_BF16, "P2P and P2M as BF16 hi+lo MFMA products "
+                               "(hi*hi + hi*lo + lo*hi + lo*lo, FP32 accumulation), M2L in FP32; "
+                               "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 2500.0, 4)
+    log("fp32 variant %.2f solves/s, split-fp16 %.2f, split-bf16 %.2f" % (
+        variant["solves_per_s"], variant16["solves_per_s"], variantb16["solves_per_s"]))
     log("variable coefficient")
     varcoef = varcoef_block(fp, inputs, torch, plan, f, args.steps, args.warmup)
     log("variable coefficient %.2f solves/s, %d iterations" % (varcoef["solves_per_s"],
@@ -660,6 +663,7 @@ def main():
         "cpu_baseline": cpu,
         "variant_fp32": variant,
         "variant_split_fp16": variant16,
+        "variant_split_bf16": variantb16,
         "adjoint": adjoint,
         "variable_coefficient": varcoef,
         "batched": batched,

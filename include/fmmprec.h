@@ -71,10 +71,19 @@ typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
  * FMM_SPLIT_FP16 (GRID plans): as FMM_FP32, but the near field and P2M take
  * each operand as an FP16 pair x = hi + lo (charges scaled per tile by a
  * power of two) and sum hi*hi + hi*lo + lo*hi on the FP16 matrix cores with
- * FP32 accumulation.  In every precision M2M, L2L, L2P, the boundary
- * correction, the stencil and Krylov stay FP64, and the flexible outer
- * iteration reaches the same FP64 residual. */
-typedef enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_SPLIT_FP16 = 2 } fmm_precision;
+ * FP32 accumulation (about 2^-22 relative per product).
+ * FMM_SPLIT_BF16 (GRID plans): the same with BF16 pairs on the BF16 matrix
+ * cores, summing all four products hi*hi + hi*lo + lo*hi + lo*lo (about
+ * 2^-16 relative per product, the pairs' representation error).
+ * In every precision M2M, L2L, L2P, the boundary correction, the stencil and
+ * Krylov stay FP64, and the flexible outer iteration reaches the same FP64
+ * residual. */
+typedef enum {
+    FMM_FP64 = 0,
+    FMM_FP32 = 1,
+    FMM_SPLIT_BF16 = 2,
+    FMM_SPLIT_FP16 = 3
+} fmm_precision;
 
 /* The problem the plan is built for.
  *   GRID:   n = interior points per side, n = 8 * 2^L with 0 <= L <= 12 (n <= 32768,
@@ -97,8 +106,8 @@ typedef struct {
 /* FMM parameters.
  *   p        number of expansion coefficients, M_0..M_{p-1} (Sec. 5.3), 2..20.
  *   leaf     points per leaf side squared; must be 64 (8 x 8 grid blocks).
- *   prec     fmm_precision (FMM_FP32 for GRID and POINTS plans, FMM_SPLIT_FP16
- *            for GRID plans).
+ *   prec     fmm_precision (FMM_FP32 for GRID and POINTS plans, FMM_SPLIT_BF16
+ *            and FMM_SPLIT_FP16 for GRID plans).
  *   bem      GRID: 1 = boundary correction on (Sec. 4), 0 = free-space
  *            volume potential only.  Ignored for POINTS.
  *   self_eps GRID: the singular self term is G_self = -(1/2pi) log(self_eps h)

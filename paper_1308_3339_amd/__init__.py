@@ -8,7 +8,7 @@ GPU; every call needs the built library and a GPU, and raises otherwise.
 """
 from ._binding import (  # noqa: F401
     FMM_ERR_ALLOC, FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_NUMERIC, FMM_ERR_UNSUPPORTED,
-    FMM_FP32, FMM_FP64, FMM_SPLIT_FP16, FMM_GRID, STAGES, FMM_NOT_CONVERGED, FMM_OK, FMM_POINTS, FmmError, Plan, exported_symbols,
+    FMM_FP32, FMM_FP64, FMM_SPLIT_BF16, FMM_SPLIT_FP16, FMM_GRID, STAGES, FMM_NOT_CONVERGED, FMM_OK, FMM_POINTS, FmmError, Plan, exported_symbols,
     fmm_apply, fmm_destroy, fmm_last_error, fmm_precond_apply, fmm_precond_stages, fmm_profile, fmm_profile_read, fmm_setup,
     fmm_stencil_apply, fmm_version, library_path, load_library, precond_gmres_solve,
     precond_gmres_solve_adjoint, fmm_bumps_eval, fmm_bumps_grad, fmm_bumps_grad_noalloc, fmm_stencil_var_apply,

@@ -13,7 +13,7 @@ _LIBNAME = "libfmmprec.so"
 FMM_OK, FMM_NOT_CONVERGED = 0, 1
 FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_ALLOC, FMM_ERR_NUMERIC, FMM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 FMM_GRID, FMM_POINTS = 0, 1
-FMM_FP64, FMM_FP32, FMM_SPLIT_FP16 = 0, 1, 2
+FMM_FP64, FMM_FP32, FMM_SPLIT_BF16, FMM_SPLIT_FP16 = 0, 1, 2, 3
 FMM_BATCH_GRAPHS = 1
 
 # every symbol include/fmmprec.h declares

@@ -181,23 +181,54 @@ static int build_tables(fmm_plan *pl)
         hi = (_Float16)x;
         lo = (_Float16)(x - (double)hi);
     };
+    // the same with BF16 halves (round to nearest even on the FP32 bits)
+    auto to_bf16 = [](double x) {
+        const float f = (float)x;
+        uint32_t b;
+        std::memcpy(&b, &f, 4);
+        b += 0x7fffu + ((b >> 16) & 1u);
+        const uint16_t hb = (uint16_t)(b >> 16);
+        __bf16 r;
+        std::memcpy(&r, &hb, 2);
+        return r;
+    };
+    auto bf16_val = [](__bf16 h) {
+        uint16_t hb;
+        std::memcpy(&hb, &h, 2);
+        const uint32_t b = (uint32_t)hb << 16;
+        float f;
+        std::memcpy(&f, &b, 4);
+        return (double)f;
+    };
+    auto splitb16 = [&](double x, __bf16 &hi, __bf16 &lo) {
+        hi = to_bf16(x);
+        lo = to_bf16(x - bf16_val(hi));
+    };
+    std::vector<__bf16> p2mb16((size_t)2 * prow * 64, to_bf16(0.0));
     for (int r = 0; r < 2 * p; ++r)
         for (int j = 0; j < 64; ++j) {
             const double2 w = p2m[(size_t)(r / 2) * 64 + j];
             split16(r & 1 ? w.y : w.x, p2m16[(size_t)r * 64 + j], p2m16[(size_t)(prow + r) * 64 + j]);
+            splitb16(r & 1 ? w.y : w.x, p2mb16[(size_t)r * 64 + j], p2mb16[(size_t)(prow + r) * 64 + j]);
         }
     // kernel table in 8 column-shifted copies: copy c, row r, entry j = T[r][j + c]
     std::vector<_Float16> kt16((size_t)2 * 8 * 31 * 40, (_Float16)0.0f);
+    std::vector<__bf16> ktb16((size_t)2 * 8 * 31 * 40, to_bf16(0.0));
     for (int c = 0; c < 8; ++c)
         for (int r = 0; r < 31; ++r)
-            for (int j = 0; j + c <= 30 && j < 40; ++j)
+            for (int j = 0; j + c <= 30 && j < 40; ++j) {
                 split16(kt[(size_t)r * 31 + j + c], kt16[((size_t)c * 31 + r) * 40 + j],
                         kt16[((size_t)(8 + c) * 31 + r) * 40 + j]);
+                splitb16(kt[(size_t)r * 31 + j + c], ktb16[((size_t)c * 31 + r) * 40 + j],
+                         ktb16[((size_t)(8 + c) * 31 + r) * 40 + j]);
+            }
     std::vector<float2> hank32(hank.size());
     for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
     int st;
     if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) ||
-        (st = upload(pl, &pl->tab.ktab16, kt16)) || (st = upload(pl, &pl->tab.p2m16, p2m16)) || (st = upload(pl, &pl->tab.hank32, hank32)) ||
+        (st = upload(pl, &pl->tab.ktab16, kt16)) || (st = upload(pl, &pl->tab.p2m16, p2m16)) ||
+        (st = upload(pl, &pl->tab.ktabb16, ktb16)) || (st = upload(pl, &pl->tab.p2mb16, p2mb16)) ||
+        (st = upload(pl, &pl->tab.hank32, hank32)) ||
         (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
         (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
@@ -288,7 +319,8 @@ static int build_levels_and_work(fmm_plan *pl)
 
 static void release(fmm_plan *pl)
 {
-    void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+    void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.ktabb16,
+                    pl->tab.p2mb16, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->ring_cells, pl->ring_p2m_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,
@@ -326,16 +358,18 @@ int fmm_setup(const fmm_problem *prob, const fmm_params *prm, void *stream, fmm_
     if (prm->p < kPMin || prm->p > kPMax)
         return fail(nullptr, FMM_ERR_ARG, "p must be in [2, 20]");
     if (prm->leaf != 64) return fail(nullptr, FMM_ERR_ARG, "leaf must be 64");
-    if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32 && prm->prec != FMM_SPLIT_FP16)
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "prec must be FMM_FP64, FMM_FP32 or FMM_SPLIT_FP16");
-    if (prm->prec == FMM_SPLIT_FP16 && prob->kind != FMM_GRID)
-        return fail(nullptr, FMM_ERR_UNSUPPORTED, "FMM_SPLIT_FP16 is built for GRID plans");
+    const bool split = prm->prec == FMM_SPLIT_FP16 || prm->prec == FMM_SPLIT_BF16;
+    if (prm->prec != FMM_FP64 && prm->prec != FMM_FP32 && !split)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED,
+                    "prec must be FMM_FP64, FMM_FP32, FMM_SPLIT_BF16 or FMM_SPLIT_FP16");
+    if (split && prob->kind != FMM_GRID)
+        return fail(nullptr, FMM_ERR_UNSUPPORTED, "split-precision plans are built for GRID plans");
     if (!(prm->self_eps >= 0.0) || !std::isfinite(prm->self_eps))
         return fail(nullptr, FMM_ERR_ARG, "self_eps must be finite and >= 0");
     if (!(prm->theta == 0.0 || (prm->theta >= kThetaMin && prm->theta <= 1.0)))
         return fail(nullptr, FMM_ERR_ARG, "theta must be 0 (interaction lists) or in [0.3, 1]");
     const int Kt = near_radius(prm->theta);
-    if (Kt > 1 && (prm->prec == FMM_SPLIT_FP16 || prm->p > kThetaPMax ||
+    if (Kt > 1 && (split || prm->p > kThetaPMax ||
                    (prm->prec == FMM_FP32 && prob->kind != FMM_GRID)))
         return fail(nullptr, FMM_ERR_UNSUPPORTED,
                     "theta < 1/sqrt(2) is built for FP64 plans and FP32 grid plans, with p <= 12");

@@ -922,30 +922,57 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
     }
 }
 
-// Split-FP16 variant of the leaf stage: the contraction of k_leaf_mfma32 on
-// the FP16 matrix cores (v_mfma_f32_16x16x32_f16, K = 32 source positions =
-// four source rows per product).  Each operand is an FP16 pair x = hi + lo:
-// the kernel table T and the P2M weights were split at setup, the charges
-// are scaled per block by a power of two (so that |q| <= 1 over the staged
-// tile) and split here; hi*hi + hi*lo + lo*hi is summed in FP32 and folded
-// into FP64 per leaf offset.  The A fragment of a lane is 8 consecutive
-// entries of one T row starting at column 8 ox - tx + 15; T sits in LDS in
-// 8 copies shifted by c = 7 - tx columns so that this start is 16-byte
-// aligned, rows 20 dwords apart and copies 648 dwords apart (= 8 mod 64),
-// which spreads a 16-lane read over distinct banks.  The q tile is
-// [leaf][pos] with 72 halves per leaf.  MFMA lane layout (16x16x32 f16):
-// A[l%16][8(l/16)+i], B[8(l/16)+i][l%16], D[4(l/16)+i][l%16].
+// Split-precision variants of the leaf stage: the contraction of
+// k_leaf_mfma32 on the 16-bit matrix cores (v_mfma_f32_16x16x32_f16 or
+// _bf16, K = 32 source positions = four source rows per product).  Each
+// operand is a pair x = hi + lo of 16-bit numbers: the kernel table T and
+// the P2M weights were split at setup, the charges are scaled per block by
+// a power of two (so that |q| <= 1 over the staged tile) and split here.
+// FP16 pairs (11 significant bits each, about 2^-22 together) sum
+// hi*hi + hi*lo + lo*hi; BF16 pairs (8 bits each, about 2^-16 together) also
+// take lo*lo, which is as large as their representation error.  Products
+// accumulate in FP32 and are folded into FP64 per leaf offset.  The A
+// fragment of a lane is 8 consecutive entries of one T row starting at
+// column 8 ox - tx + 15; T sits in LDS in 8 copies shifted by c = 7 - tx
+// columns so that this start is 16-byte aligned, rows 20 dwords apart and
+// copies 648 dwords apart (= 8 mod 64), which spreads a 16-lane read over
+// distinct banks.  The q tile is [leaf][pos] with 72 halves per leaf.  MFMA
+// lane layout (16x16x32, both types): A[l%16][8(l/16)+i], B[8(l/16)+i][l%16],
+// D[4(l/16)+i][l%16].
 constexpr int kT16Row = 40, kT16Copy = 31 * 40, kT16Pitch = 1296, kQ16Leaf = 72;
 
-template <int P>
-__global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const _Float16 *__restrict__ kt16,
-                                                     const _Float16 *__restrict__ w16)
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename H> struct Split16;
+template <> struct Split16<_Float16> {
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    static constexpr bool kLoLo = false;
+    __device__ static _Float16 cvt(double x) { return (_Float16)x; }
+    __device__ static f4_t mfma(v8 a, v8 b, f4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Split16<__bf16> {
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    static constexpr bool kLoLo = true;
+    __device__ static __bf16 cvt(double x) { return (__bf16)(float)x; }
+    __device__ static f4_t mfma(v8 a, v8 b, f4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int P, typename H>
+__global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__restrict__ kt16,
+                                                     const H *__restrict__ w16)
 {
-    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-    typedef float f4 __attribute__((ext_vector_type(4)));
+    using S = Split16<H>;
+    typedef typename S::v8 h8;
+    typedef f4_t f4;
     constexpr int MTP = (2 * P + 15) / 16;
-    __shared__ __align__(16) _Float16 st[2][8 * kT16Pitch];
-    __shared__ __align__(16) _Float16 sqh[100 * kQ16Leaf], sql[100 * kQ16Leaf];
+    __shared__ __align__(16) H st[2][8 * kT16Pitch];
+    __shared__ __align__(16) H sqh[100 * kQ16Leaf], sql[100 * kQ16Leaf];
     __shared__ double smax[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -982,9 +1009,9 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const _Float16 
         const int yy = e / 80, xx = e - yy * 80;
         const int at = ((yy >> 3) * 10 + (xx >> 3)) * kQ16Leaf + (yy & 7) * 8 + (xx & 7);
         const double x = v[i] * scale;
-        const _Float16 hi = (_Float16)x;
+        const H hi = S::cvt(x);
         sqh[at] = hi;
-        sql[at] = (_Float16)(x - (double)hi);
+        sql[at] = S::cvt(x - (double)(float)hi);
     }
     __syncthreads();
     const int g = lane >> 4, m16 = lane & 15;
@@ -1017,9 +1044,10 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const _Float16 
                 const int ai = aoff + (4 * ks - 2 * mt) * kT16Row;
                 const h8 ah = *(const h8 *)&st[0][ai];
                 const h8 al = *(const h8 *)&st[1][ai];
-                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c[mt], 0, 0, 0);
-                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c[mt], 0, 0, 0);
-                c[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c[mt], 0, 0, 0);
+                if constexpr (S::kLoLo) c[mt] = S::mfma(al, bl, c[mt]);
+                c[mt] = S::mfma(ah, bl, c[mt]);
+                c[mt] = S::mfma(al, bh, c[mt]);
+                c[mt] = S::mfma(ah, bh, c[mt]);
             }
         }
 #pragma unroll
@@ -1040,9 +1068,10 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const _Float16 
                 const size_t wi = (size_t)(16 * mt + m16) * 64 + 32 * ks + 8 * g;
                 const h8 wh = *(const h8 *)&w16[wi];
                 const h8 wl = *(const h8 *)&w16[(size_t)16 * MTP * 64 + wi];
-                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bl, pm[mt], 0, 0, 0);
-                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wl, bh, pm[mt], 0, 0, 0);
-                pm[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wh, bh, pm[mt], 0, 0, 0);
+                if constexpr (S::kLoLo) pm[mt] = S::mfma(wl, bl, pm[mt]);
+                pm[mt] = S::mfma(wh, bl, pm[mt]);
+                pm[mt] = S::mfma(wl, bh, pm[mt]);
+                pm[mt] = S::mfma(wh, bh, pm[mt]);
             }
         }
     }
@@ -1641,8 +1670,11 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8);
         if (pl->prec == FMM_SPLIT_FP16)
-            hipLaunchKernelGGL(k_leaf_mfma16<P>, gl, dim3(256), 0, s, a, pl->tab.ktab16,
+            hipLaunchKernelGGL((k_leaf_mfma16<P, _Float16>), gl, dim3(256), 0, s, a, pl->tab.ktab16,
                                pl->tab.p2m16);
+        else if (pl->prec == FMM_SPLIT_BF16)
+            hipLaunchKernelGGL((k_leaf_mfma16<P, __bf16>), gl, dim3(256), 0, s, a, pl->tab.ktabb16,
+                               pl->tab.p2mb16);
         else if (fp32 && pl->K > 1)
             launch_leaf_wide_mfma32<P>(pl, gl, a, s);
         else if (fp32)

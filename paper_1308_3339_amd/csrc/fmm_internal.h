@@ -78,6 +78,8 @@ struct FmmTables {
     float *p2m32;     // [16 ceil(2p/16)][64] P2M weights as real rows (2k: Re, 2k+1: Im), FP32
     _Float16 *ktab16; // [hi, lo][8 shifted copies][31 rows][40]: ktab split in two FP16 halves
     _Float16 *p2m16;  // [hi, lo][16 ceil(2p/16)][64]: p2m32 split in two FP16 halves
+    __bf16 *ktabb16;  // as ktab16, split in two BF16 halves
+    __bf16 *p2mb16;   // as p2m16, split in two BF16 halves
     float2 *hank32;   // FP32 copy of hank (precision variant)
 };
 

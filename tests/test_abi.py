@@ -61,12 +61,29 @@ def test_setup_rejects_bad_arguments(kw, frag):
     assert frag in msg
 
 
-def test_setup_rejects_unbuilt_precision():
-    code, ptr, msg = _setup_raw(prec=3)
+def test_precision_enum_values():
+    # fmm_precision as declared in include/fmmprec.h
+    src = open(os.path.join(ROOT, "include", "fmmprec.h")).read()
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(FMM_(?:FP64|FP32|SPLIT_BF16|SPLIT_FP16))\s*=\s*(\d+)", src))
+    assert vals == {"FMM_FP64": 0, "FMM_FP32": 1, "FMM_SPLIT_BF16": 2, "FMM_SPLIT_FP16": 3}
+    assert (fp.FMM_FP64, fp.FMM_FP32, fp.FMM_SPLIT_BF16, fp.FMM_SPLIT_FP16) == (0, 1, 2, 3)
+
+
+@pytest.mark.parametrize("prec", [4, -1])
+def test_setup_rejects_unbuilt_precision(prec):
+    code, ptr, msg = _setup_raw(prec=prec)
     assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
 
 
+@pytest.mark.parametrize("prec", [2, 3])
+def test_split_precision_needs_a_grid(prec):
+    code, ptr, msg = _setup_raw(kind=1, n=100, prec=prec)
+    assert code == fp.FMM_ERR_UNSUPPORTED and not ptr
+    assert "GRID" in msg
+
+
 @pytest.mark.parametrize("kw", [dict(theta=0.4, prec=1, kind=1), dict(theta=0.4, prec=2),
+                                dict(theta=0.4, prec=3),
                                 dict(theta=0.3, p=11), dict(theta=0.4, p=14)])
 def test_setup_rejects_unbuilt_theta_combinations(kw):
     # small theta: FP64 plans and FP32 grid plans with p <= 12 only, and the M2L

@@ -1,12 +1,17 @@
 """Precision variants against the FP64 oracle: FMM_FP32 (P2P and P2M as FP32
-matrix-core contractions, M2L in FP32) and FMM_SPLIT_FP16 (P2P and P2M as
-FP16 hi+lo products on the matrix cores, M2L in FP32); everything else FP64.
+matrix-core contractions, M2L in FP32), FMM_SPLIT_FP16 and FMM_SPLIT_BF16
+(P2P and P2M as 16-bit hi+lo products on the matrix cores, M2L in FP32);
+everything else FP64.
 
 The variant changes the preconditioner only by rounding, so:
   * per-stage error against the FP64 oracle (volume potential, ring
-    potential, boundary density, z) <= 1e-5 relative (max-norm); the FP32
-    sums are 24-term partials folded into FP64, the FMM truncation at p = 10
-    is ~1e-6, so a few 1e-6 is the expected level;
+    potential, boundary density, z) <= 1e-5 relative (max-norm) for FP32 and
+    split FP16; the FP32 sums are 64-term partials folded into FP64, the FMM
+    truncation at p = 10 is ~1e-6, so a few 1e-6 is the expected level.
+    Split BF16 represents each operand to 2^-16 (1.5e-5) relative, so a
+    product carries up to 2^-15; the bar is 5e-5, a little above that per
+    product error (the near field's terms are mostly of one sign: the log
+    kernel is negative over the whole near field, so sums cancel little);
   * the flexible outer iteration still reaches the FP64 true residual
     <= 1e-8, within two iterations of the FP64 preconditioner, and the
     solution agrees with the oracle's within 1e-6.
@@ -42,7 +47,8 @@ def relmax(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-PRECS = ("FMM_FP32", "FMM_SPLIT_FP16")
+PRECS = ("FMM_FP32", "FMM_SPLIT_FP16", "FMM_SPLIT_BF16")
+STAGE_BAR = {"FMM_FP32": 1e-5, "FMM_SPLIT_FP16": 1e-5, "FMM_SPLIT_BF16": 5e-5}
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -66,7 +72,7 @@ def test_fp32_stages_against_fp64_oracle(n, prec):
             "z": relmax(zg, zo)}
     say("  per-stage rel err vs FP64 oracle", errs)
     for k, v in errs.items():
-        assert v <= 1e-5, k
+        assert v <= STAGE_BAR[prec], k
 
 
 @pytest.mark.parametrize("prec", PRECS)
