@@ -253,6 +253,44 @@ static int leaf_coord(double v, double v0, double side, int nl)
     return (int)f;
 }
 
+/* Morton index of leaf (lx, ly) at level L: bit b of lx goes to bit 2b and
+ * bit b of ly to bit 2b + 1 (x bits in the even positions). */
+static int64_t morton_of(int lx, int ly, int L)
+{
+    int64_t m = 0;
+    for (int b = 0; b < L; ++b) {
+        m |= (int64_t)((lx >> b) & 1) << (2 * b);
+        m |= (int64_t)((ly >> b) & 1) << (2 * b + 1);
+    }
+    return m;
+}
+
+/* Points bucketed by leaf (Sec. 5.1 tree construction on the uniform tree):
+ * a stable counting sort by leaf key, key = row-major index ly * 2^L + lx
+ * (order 0) or the Morton index (order 1).  scount (4^L + 1) receives the
+ * first sorted position of each key and sorder (ns) the original index of
+ * each sorted position; points of one leaf keep their original order. */
+int orc_bucket_points(int L, double x0, double y0, double side, int order, int ns,
+                      const double *sx, const double *sy, int *scount, int *sorder)
+{
+    if (L < 0 || L > 15 || ns < 0 || (order != 0 && order != 1)) return -1;
+    int nl = 1 << L;
+    int64_t nleaf = (int64_t)nl * nl;
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ns > 0 ? ns : 1));
+    int64_t *fill = (int64_t *)calloc((size_t)nleaf, sizeof(int64_t));
+    for (int64_t c = 0; c <= nleaf; ++c) scount[c] = 0;
+    for (int j = 0; j < ns; ++j) {
+        int lx = leaf_coord(sx[j], x0, side, nl), ly = leaf_coord(sy[j], y0, side, nl);
+        key[j] = order ? morton_of(lx, ly, L) : (int64_t)ly * nl + lx;
+        scount[key[j] + 1]++;
+    }
+    for (int64_t c = 0; c < nleaf; ++c) scount[c + 1] += scount[c];
+    for (int j = 0; j < ns; ++j) sorder[scount[key[j]] + fill[key[j]]++] = j;
+    free(key);
+    free(fill);
+    return 0;
+}
+
 /* Fills up to 27 (sx, sy) pairs of the M2L list of cell (ix, iy) at level l;
  * returns the count.  Cells outside [0, 2^l)^2 do not exist. */
 int orc_m2l_list(int l, int ix, int iy, int *out)

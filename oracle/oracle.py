@@ -85,6 +85,10 @@ def lib():
         L.orc_dtt_lists.argtypes = [ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(ctypes.c_int64), _ip, _ip]
         L.orc_dtt_lists.restype = ctypes.c_int
+        L.orc_bucket_points.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp,
+                                        _ip, _ip]
+        L.orc_bucket_points.restype = ctypes.c_int
         L.orc_stencil.argtypes = [ctypes.c_int, _dp, _dp]
         L.orc_grid_points.argtypes = [ctypes.c_int, _dp, _dp]
         L.orc_ring_points.argtypes = [ctypes.c_int, _dp, _dp]
@@ -203,6 +207,22 @@ def fmm(L, x0, y0, side, p, sx, sy, q, tx, ty, self_log=0.0, theta=None):
     if rc != 0:
         raise ValueError("orc_fmm rejected its arguments")
     return u
+
+
+def bucket_points(L, x0, y0, side, x, y, morton=True):
+    """Stable counting sort of the points by leaf (Sec. 5.1): returns
+    (start, order) with start[k] the first sorted position of leaf key k
+    (4^L + 1 entries; key = Morton index, or row-major ly 2^L + lx) and
+    order[i] the original index of sorted position i."""
+    x, y = _f64(x), _f64(y)
+    start = np.zeros((1 << (2 * L)) + 1, dtype=np.int32)
+    order = np.zeros(max(len(x), 1), dtype=np.int32)
+    rc = lib().orc_bucket_points(L, float(x0), float(y0), float(side), 1 if morton else 0, len(x),
+                                 _ptr(x), _ptr(y), start.ctypes.data_as(_ip),
+                                 order.ctypes.data_as(_ip))
+    if rc != 0:
+        raise ValueError("orc_bucket_points rejected its arguments")
+    return start, order[:len(x)]
 
 
 def dtt_lists(L, theta):
