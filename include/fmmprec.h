@@ -170,6 +170,16 @@ int fmm_setup(const fmm_problem *problem, const fmm_params *params, void *stream
  * alias q. */
 int fmm_apply(fmm_plan *plan, const double *q, double *u, int nrhs, void *stream);
 
+/* The tree order of a POINTS plan (Sec. 5.1, built on the device by
+ * fmm_setup): points sorted by leaf, leaves in Morton order (bit b of the
+ * leaf column at bit 2b, bit b of the leaf row at bit 2b + 1), points of
+ * one leaf in their original order.  perm: N int32 (DEVICE), perm[i] = the
+ * caller's index of the point at sorted position i; leaf_start: 4^L + 1
+ * int32 (DEVICE), leaf_start[m] = first sorted position of the leaf with
+ * Morton index m, leaf_start[4^L] = N, L = ceil(log4(N/64)) (at least 0).
+ * Either pointer may be NULL (not both).  Asynchronous on `stream`. */
+int fmm_points_order(fmm_plan *plan, int32_t *perm, int32_t *leaf_start, void *stream);
+
 /* z = P^{-1} r (PCApply, Sec. 3.3 Fig. 1), GRID plans only:
  *   q = h^2 r (midpoint rule for the volume integral of Sec. 4.1),
  *   phi = FMM volume potential of q at the interior and ring nodes,

@@ -22,7 +22,7 @@ exported_symbols = (
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
     "fmm_stencil_var_apply", "precond_gmres_solve_var", "precond_gmres_solve_batch", "fmm_tune",
-    "fmm_bumps_grad_noalloc",
+    "fmm_bumps_grad_noalloc", "fmm_points_order",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -110,6 +110,8 @@ def load_library():
     L.fmm_bumps_grad.restype = i32
     L.fmm_bumps_grad_noalloc.argtypes = [vp, i32, dp, dp, dp, dp, dp, dp, dp, dp, dp, vp]
     L.fmm_bumps_grad_noalloc.restype = i32
+    L.fmm_points_order.argtypes = [vp, vp, vp, vp]
+    L.fmm_points_order.restype = i32
     L.fmm_destroy.argtypes = [vp]
     L.fmm_destroy.restype = i32
     L.fmm_last_error.argtypes = [vp]
@@ -149,6 +151,18 @@ def _dptr(t, name, numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _iptr(t, name, numel):
+    """Device pointer of a contiguous int32 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise TypeError("%s must be an int32 CUDA tensor" % name)
+    if not t.is_contiguous() or t.numel() < numel:
+        raise ValueError("%s must be contiguous with >= %d elements" % (name, numel))
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _check(code, plan_ptr):
     if code < 0:
         msg = load_library().fmm_last_error(plan_ptr)
@@ -183,6 +197,24 @@ def fmm_apply(plan, q, u, nrhs=1, stream=None):
     N = plan.npts
     code = load_library().fmm_apply(plan._ptr, _dptr(q, "q", N * nrhs), _dptr(u, "u", N * nrhs),
                                     nrhs, _stream(stream))
+    return _check(code, plan._ptr)
+
+
+def points_levels(N):
+    """L = ceil(log4(N / 64)) of a POINTS plan with N points."""
+    L = 0
+    while (64 << (2 * L)) < N and L < 12:
+        L += 1
+    return L
+
+
+def fmm_points_order(plan, perm=None, leaf_start=None, stream=None):
+    """Copies the plan's tree order: perm (N int32) and leaf_start
+    (4^L + 1 int32, leaves in Morton order)."""
+    nleaf = 1 << (2 * points_levels(plan.n))
+    code = load_library().fmm_points_order(plan._ptr, _iptr(perm, "perm", plan.n),
+                                           _iptr(leaf_start, "leaf_start", nleaf + 1),
+                                           _stream(stream))
     return _check(code, plan._ptr)
 
 
@@ -373,6 +405,7 @@ class Plan:
     bumps_eval = fmm_bumps_eval
     bumps_grad = fmm_bumps_grad
     bumps_grad_noalloc = fmm_bumps_grad_noalloc
+    points_order = fmm_points_order
     profile = fmm_profile
     profile_read = fmm_profile_read
 

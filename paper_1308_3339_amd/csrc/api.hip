@@ -520,6 +520,22 @@ int fmm_apply(fmm_plan *pl, const double *q, double *u, int nrhs, void *stream)
     return FMM_OK;
 }
 
+int fmm_points_order(fmm_plan *pl, int32_t *perm, int32_t *leaf_start, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_POINTS) return fail(pl, FMM_ERR_ARG, "the point order needs a POINTS plan");
+    if (!perm && !leaf_start) return fail(pl, FMM_ERR_ARG, "perm and leaf_start are both NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nleaf = (size_t)pl->nl * pl->nl;
+    if (perm)
+        FMM_HIP(pl, hipMemcpyAsync(perm, pl->perm, (size_t)pl->n * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+    if (leaf_start)
+        FMM_HIP(pl, hipMemcpyAsync(leaf_start, pl->leaf_start, (nleaf + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+    return FMM_OK;
+}
+
 int fmm_precond_apply(fmm_plan *pl, const double *r, double *z, int nrhs, void *stream)
 {
     if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");

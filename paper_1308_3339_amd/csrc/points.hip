@@ -2,14 +2,17 @@
 // G(x_i - x_j), G = -(1/2pi) log r, on a uniform quadtree over a given root
 // square with L = ceil(log4(N/64)) levels.
 //
-// Setup bins the points into leaves (stable counting sort by leaf, leaves in
-// row-major order) and keeps the sorted coordinates on the device.  An
-// application gathers the charges into leaf order, builds leaf multipoles,
-// reuses the level-generic M2M, M2L and L2L kernels of the grid path, and
-// finishes with one block per target leaf: the sources of the near leaves
-// around it (3x3 with the list rule, the disk of a MAC theta) are staged
-// through LDS in chunks, four waves split the sources, and the local
-// expansion is evaluated at each target.  FMM_FP32 plans run that near
+// Setup (tree.hip) sorts the points into leaves in Morton order on the
+// device and keeps the sorted coordinates there.  An application gathers the
+// charges into that order, builds leaf multipoles, reuses the level-generic
+// M2M, M2L and L2L kernels of the grid path (whose expansions are indexed by
+// row-major cell), and finishes with one block per target leaf: the sources
+// of the near leaves around it (3x3 with the list rule, the disk of a MAC
+// theta) are staged through LDS in chunks of their concatenated leaf
+// segments, four waves split the sources, and the local expansion is
+// evaluated at each target.  Blocks walk the leaves in Morton order, and
+// consecutive Morton ranges go to the same accelerator die (XCD), so the
+// near leaves a die stages are mostly its own.  FMM_FP32 plans run that near
 // field pairwise in FP32 (the paper's P2P of Secs. 5.3 and 7.1: a polynomial
 // logarithm and Kahan-compensated sums); the far field stays FP64.
 #include <algorithm>
@@ -29,6 +32,87 @@ int points_m2l_down(fmm_plan *pl, hipStream_t s);
 __device__ __forceinline__ double2 pcmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Morton index of leaf (lx, ly) and back (x bits even, y bits odd)
+__device__ __forceinline__ uint32_t spread2(uint32_t v)
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+__device__ __forceinline__ uint32_t compact2(uint32_t v)
+{
+    v &= 0x55555555u;
+    v = (v | (v >> 1)) & 0x33333333u;
+    v = (v | (v >> 2)) & 0x0f0f0f0fu;
+    v = (v | (v >> 4)) & 0x00ff00ffu;
+    v = (v | (v >> 8)) & 0x0000ffffu;
+    return v;
+}
+__device__ __forceinline__ int morton2(int lx, int ly) { return (int)(spread2(lx) | (spread2(ly) << 1)); }
+
+// Leaf of block b when leaves are walked in Morton order: the launch's
+// blocks are dealt round-robin to the eight dies, so block b takes leaf
+// (b mod 8) * (nleaf / 8) + b / 8 and each die works through one contiguous
+// Morton range (a compact square of the domain).
+__device__ __forceinline__ int leaf_of_block(int b, int nleaf)
+{
+    return (nleaf >= 64) ? (b & 7) * (nleaf >> 3) + (b >> 3) : b;
+}
+
+// Near-field sources of a target leaf: the concatenation of the sorted
+// segments of its near leaves (rows |b| <= K, columns |a| <= kx(|b|)), in a
+// fixed order.  seg_s[c] is the first sorted position of candidate c and
+// seg_p[c] its offset in the concatenation (empty segments allowed);
+// seg_p[nc] is the total.
+constexpr int kMaxNearLeaves = (2 * kMaxK + 1) * (2 * kMaxK + 1);
+
+__device__ __forceinline__ int near_segments(const int *__restrict__ start, int lx, int ly, int nl,
+                                             int K, int kxp, int *seg_s, int *seg_p)
+{
+    const int side = 2 * K + 1, nc = side * side;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int b = c / side - K, a = c % side - K;
+        const int kb = ((kxp >> (4 * (b < 0 ? -b : b))) & 15) - 1;
+        const int qx = lx + a, qy = ly + b;
+        int s0 = 0, len = 0;
+        if ((a < 0 ? -a : a) <= kb && qx >= 0 && qx < nl && qy >= 0 && qy < nl) {
+            const int m = morton2(qx, qy);
+            s0 = start[m];
+            len = start[m + 1] - s0;
+        }
+        seg_s[c] = s0;
+        seg_p[c] = len;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int c = 0; c < nc; ++c) {
+            const int len = seg_p[c];
+            seg_p[c] = run;
+            run += len;
+        }
+        seg_p[nc] = run;
+    }
+    __syncthreads();
+    return nc;
+}
+
+// sorted position of element e of the concatenation: the last candidate
+// whose offset is <= e (an empty segment shares its offset with the next)
+__device__ __forceinline__ int near_source(const int *seg_s, const int *seg_p, int nc, int e)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_p[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return seg_s[lo] + (e - seg_p[lo]);
 }
 
 __global__ void k_gather(const double *__restrict__ q, const int *__restrict__ perm,
@@ -56,14 +140,15 @@ __global__ __launch_bounds__(256) void k_p2m_points(const double *__restrict__ p
                                                     double2 *__restrict__ M, int nl, double x0,
                                                     double y0, double w)
 {
-    const int leaf = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (leaf >= nl * nl) return;
-    const int lx = leaf % nl, ly = leaf / nl;
+    const int m = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (m >= nl * nl) return;
+    const int lx = (int)compact2(m), ly = (int)compact2((uint32_t)m >> 1);
+    const int leaf = ly * nl + lx;
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
     double2 acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = make_double2(0.0, 0.0);
-    for (int j = start[leaf] + lane; j < start[leaf + 1]; j += 64) {
+    for (int j = start[m] + lane; j < start[m + 1]; j += 64) {
         const double c = qs[j];
         const double2 tau = make_double2((px[j] - cx) * iw, (py[j] - cy) * iw);
         double2 pw = make_double2(1.0, 0.0);
@@ -105,11 +190,13 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
 {
     __shared__ double sx[kChunk], sy[kChunk], sqv[kChunk];
     __shared__ double red[3][64];
+    __shared__ int seg_s[kMaxNearLeaves], seg_p[kMaxNearLeaves + 1];
     const int nl = 1 << L;
-    const int leaf = blockIdx.x;
-    const int lx = leaf % nl, ly = leaf / nl;
+    const int m = leaf_of_block(blockIdx.x, nl * nl);
+    const int lx = (int)compact2(m), ly = (int)compact2((uint32_t)m >> 1);
+    const int leaf = ly * nl + lx;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t0 = start[leaf], t1 = start[leaf + 1];
+    const int t0 = start[m], t1 = start[m + 1];
     double2 Lc[P];
     if (far) {
         const int64_t ncell = (int64_t)nl * nl;
@@ -118,6 +205,8 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
         for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + leaf];
     }
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
+    const int nc = near_segments(start, lx, ly, nl, K, kxp, seg_s, seg_p);
+    const int ns = seg_p[nc];
     // targets in slices of 64; sources of the near leaves (the 3x3 block with
     // the list rule, the disk of radius K with a MAC theta) in chunks through LDS
     for (int tb = t0; tb < t1; tb += 64) {
@@ -125,27 +214,21 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
         const bool tv = t < t1;
         const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
         double acc = 0.0;
-        for (int b = -K; b <= K; ++b) {
-            const int qy = ly + b, kb = ((kxp >> (4 * (b < 0 ? -b : b))) & 15) - 1;
-            if (qy < 0 || qy >= nl || kb < 0) continue;
-            const int qx0 = max(lx - kb, 0), qx1 = min(lx + kb, nl - 1);
-            // the leaves of one row of the near set are contiguous in the sorted order
-            const int s0 = start[qy * nl + qx0], s1 = start[qy * nl + qx1 + 1];
-            for (int cb = s0; cb < s1; cb += kChunk) {
-                const int cnt = min(kChunk, s1 - cb);
-                __syncthreads();
-                for (int e = threadIdx.x; e < cnt; e += 256) {
-                    sx[e] = px[cb + e];
-                    sy[e] = py[cb + e];
-                    sqv[e] = qs[cb + e];
-                }
-                __syncthreads();
-                if (tv) {
-                    for (int e = wv; e < cnt; e += 4) {
-                        const double dx = tx - sx[e], dy = ty - sy[e];
-                        const double r2 = dx * dx + dy * dy;
-                        if (r2 > 0.0) acc = fma(sqv[e], log(sqrt(r2)), acc);
-                    }
+        for (int cb = 0; cb < ns; cb += kChunk) {
+            const int cnt = min(kChunk, ns - cb);
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt; e += 256) {
+                const int j = near_source(seg_s, seg_p, nc, cb + e);
+                sx[e] = px[j];
+                sy[e] = py[j];
+                sqv[e] = qs[j];
+            }
+            __syncthreads();
+            if (tv) {
+                for (int e = wv; e < cnt; e += 4) {
+                    const double dx = tx - sx[e], dy = ty - sy[e];
+                    const double r2 = dx * dx + dy * dy;
+                    if (r2 > 0.0) acc = fma(sqv[e], log(sqrt(r2)), acc);
                 }
             }
         }
@@ -209,11 +292,13 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
 {
     __shared__ float sx[kChunk], sy[kChunk], sqv[kChunk];
     __shared__ double red[3][64];
+    __shared__ int seg_s[kMaxNearLeaves], seg_p[kMaxNearLeaves + 1];
     const int nl = 1 << L;
-    const int leaf = blockIdx.x;
-    const int lx = leaf % nl, ly = leaf / nl;
+    const int m = leaf_of_block(blockIdx.x, nl * nl);
+    const int lx = (int)compact2(m), ly = (int)compact2((uint32_t)m >> 1);
+    const int leaf = ly * nl + lx;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t0 = start[leaf], t1 = start[leaf + 1];
+    const int t0 = start[m], t1 = start[m + 1];
     double2 Lc[P];
     if (far) {
         const int64_t ncell = (int64_t)nl * nl;
@@ -222,36 +307,33 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
         for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + leaf];
     }
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
+    const int nc = near_segments(start, lx, ly, nl, K, kxp, seg_s, seg_p);
+    const int ns = seg_p[nc];
     for (int tb = t0; tb < t1; tb += 64) {
         const int t = tb + lane;
         const bool tv = t < t1;
         const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
         const float txf = (float)(tx - cx), tyf = (float)(ty - cy);
         float ks = 0.0f, kc = 0.0f;   // Kahan sum of q log2(r^2) and its compensation
-        for (int b = -K; b <= K; ++b) {
-            const int qy = ly + b, kb = ((kxp >> (4 * (b < 0 ? -b : b))) & 15) - 1;
-            if (qy < 0 || qy >= nl || kb < 0) continue;
-            const int qx0 = max(lx - kb, 0), qx1 = min(lx + kb, nl - 1);
-            const int s0 = start[qy * nl + qx0], s1 = start[qy * nl + qx1 + 1];
-            for (int cb = s0; cb < s1; cb += kChunk) {
-                const int cnt = min(kChunk, s1 - cb);
-                __syncthreads();
-                for (int e = threadIdx.x; e < cnt; e += 256) {
-                    sx[e] = (float)(px[cb + e] - cx);
-                    sy[e] = (float)(py[cb + e] - cy);
-                    sqv[e] = (float)qs[cb + e];
-                }
-                __syncthreads();
-                if (tv) {
-                    for (int e = wv; e < cnt; e += 4) {
-                        const float dx = txf - sx[e], dy = tyf - sy[e];
-                        const float r2 = fmaf(dx, dx, dy * dy);
-                        if (r2 >= FLT_MIN) {
-                            const float y = fmaf(sqv[e], log2_poly(r2), -kc);
-                            const float tsum = ks + y;
-                            kc = (tsum - ks) - y;
-                            ks = tsum;
-                        }
+        for (int cb = 0; cb < ns; cb += kChunk) {
+            const int cnt = min(kChunk, ns - cb);
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt; e += 256) {
+                const int j = near_source(seg_s, seg_p, nc, cb + e);
+                sx[e] = (float)(px[j] - cx);
+                sy[e] = (float)(py[j] - cy);
+                sqv[e] = (float)qs[j];
+            }
+            __syncthreads();
+            if (tv) {
+                for (int e = wv; e < cnt; e += 4) {
+                    const float dx = txf - sx[e], dy = tyf - sy[e];
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    if (r2 >= FLT_MIN) {
+                        const float y = fmaf(sqv[e], log2_poly(r2), -kc);
+                        const float tsum = ks + y;
+                        kc = (tsum - ks) - y;
+                        ks = tsum;
                     }
                 }
             }
@@ -275,48 +357,6 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
             us[t] = -(acc + farv) * kInv2Pi;
         }
     }
-}
-
-int points_setup(fmm_plan *pl, const double *dx, const double *dy, hipStream_t s)
-{
-    const int64_t N = pl->n;
-    if (N > (int64_t)1 << 30) return fail(pl, FMM_ERR_ARG, "POINTS n must be <= 2^30");
-    std::vector<double> hx(N), hy(N);
-    FMM_HIP(pl, hipMemcpyAsync(hx.data(), dx, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FMM_HIP(pl, hipMemcpyAsync(hy.data(), dy, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    FMM_HIP(pl, hipStreamSynchronize(s));
-    const int nl = pl->nl;
-    const int64_t nleaf = (int64_t)nl * nl;
-    std::vector<int> leaf(N), start(nleaf + 1, 0), perm(N);
-    for (int64_t i = 0; i < N; ++i) {
-        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]))
-            return fail(pl, FMM_ERR_ARG, "POINTS coordinates must be finite");
-        double fx = std::floor((hx[i] - pl->x0) / pl->side * nl);
-        double fy = std::floor((hy[i] - pl->y0) / pl->side * nl);
-        fx = std::min(std::max(fx, 0.0), (double)(nl - 1));
-        fy = std::min(std::max(fy, 0.0), (double)(nl - 1));
-        leaf[i] = (int)fy * nl + (int)fx;
-        start[leaf[i] + 1]++;
-    }
-    for (int64_t c = 0; c < nleaf; ++c) start[c + 1] += start[c];
-    std::vector<int> fill(start.begin(), start.end() - 1);
-    for (int64_t i = 0; i < N; ++i) perm[fill[leaf[i]]++] = (int)i;   // stable: ties by index
-    std::vector<double> sx(N), sy(N);
-    for (int64_t i = 0; i < N; ++i) {
-        sx[i] = hx[perm[i]];
-        sy[i] = hy[perm[i]];
-    }
-    FMM_HIP(pl, hipMalloc(&pl->perm, N * sizeof(int)));
-    FMM_HIP(pl, hipMalloc(&pl->leaf_start, (nleaf + 1) * sizeof(int)));
-    FMM_HIP(pl, hipMalloc(&pl->px, N * sizeof(double)));
-    FMM_HIP(pl, hipMalloc(&pl->py, N * sizeof(double)));
-    FMM_HIP(pl, hipMalloc(&pl->qs, N * sizeof(double)));
-    FMM_HIP(pl, hipMalloc(&pl->us, N * sizeof(double)));
-    FMM_HIP(pl, hipMemcpy(pl->perm, perm.data(), N * sizeof(int), hipMemcpyHostToDevice));
-    FMM_HIP(pl, hipMemcpy(pl->leaf_start, start.data(), (nleaf + 1) * sizeof(int), hipMemcpyHostToDevice));
-    FMM_HIP(pl, hipMemcpy(pl->px, sx.data(), N * sizeof(double), hipMemcpyHostToDevice));
-    FMM_HIP(pl, hipMemcpy(pl->py, sy.data(), N * sizeof(double), hipMemcpyHostToDevice));
-    return FMM_OK;
 }
 
 template <int P>
