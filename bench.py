@@ -62,9 +62,13 @@ def stage_rooflines(n, p, prof):
       LEAF    leaf_kernel_flops (near-field pairs + P2M), FP64 VALU;
       M2L     8 p^2 flops per translation (p^2 complex multiply-adds), FP64 VALU;
       BEM     the eight folded (n/2)^2 FP64 halves of the boundary inverse, HBM;
-      ARNOLDI step j reads z, v_0..v_j twice and writes two vectors: (2j+6) 8N bytes, HBM.
-    The tree passes (M2M, L2L, RING, PASS2) and the residuals (STENCIL) are bound by
-    the latency of their dependent steps; only their time is given."""
+      ARNOLDI step j reads z, v_0..v_j twice and writes two vectors: (2j+6) 8N bytes, HBM;
+      PASS2   the final sweep over the grid: z read and written (16 N bytes) and the
+              leaf-level local expansions of both passes read (2 x 16 p bytes per
+              leaf); the ring-source kernels before it touch only the boundary band, HBM;
+      STENCIL a residual r = b - A x reads b and x and writes r: 24 N bytes, HBM.
+    The tree passes (M2M, L2L, RING) are bound by the latency of their dependent
+    steps; only their time is given."""
     L = (n // 8).bit_length() - 1
     N = n * n
     out = {}
@@ -80,6 +84,11 @@ def stage_rooflines(n, p, prof):
             work, unit, peak, bound = 8.0 * (n // 2) ** 2 * 8 * cnt / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
         elif name == "ARNOLDI":
             work, unit, peak, bound = sum((2 * j + 6) * 8.0 * N for j in range(cnt)) / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
+        elif name == "PASS2":
+            nleaf = (n // 8) ** 2
+            work, unit, peak, bound = (16.0 * N + 2 * 16.0 * p * nleaf) * cnt / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
+        elif name == "STENCIL":
+            work, unit, peak, bound = 24.0 * N * cnt / 1e12, "TB/s", PEAK_HBM_TBS, "hbm"
         else:
             out[name] = {"ms_per_solve": round(ms, 4), "calls": cnt, "bound": "latency"}
             continue
@@ -99,6 +108,40 @@ def leaf_kernel_hash():
     return hashlib.sha256(src[i:j].encode()).hexdigest()
 
 
+def kernel_source_hash(fname, head):
+    """sha256 of a kernel's source text, from the line that declares it to the
+    closing brace of its body."""
+    src = open(os.path.join(ROOT, "paper_1308_3339_amd", "csrc", fname)).read()
+    i = src.index(head)
+    j = src.index("\n}\n", i)
+    return hashlib.sha256(src[i:j].encode()).hexdigest()
+
+
+POINTS_ISA_FILE = os.path.join(ROOT, "profiles", "k_leaf_points_isa.md")
+POINTS_HEADS = {"fp64": ("points.hip", "__global__ __launch_bounds__(256) void k_leaf_points("),
+                "fp32": ("points.hip", "__global__ __launch_bounds__(256) void k_leaf_points_f32(")}
+
+
+def points_isa_counts():
+    """VALU instructions per near-field pair of the point leaf kernels, from the
+    committed count of their inner loops in the AMD assembly, when it was taken
+    on the current kernel sources ({kind: (valu, flops)} or {})."""
+    if not os.path.exists(POINTS_ISA_FILE):
+        return {}
+    txt = open(POINTS_ISA_FILE).read()
+    out = {}
+    for kind, (fname, head) in POINTS_HEADS.items():
+        m = re.search(r"%s_sha256:\s*([0-9a-f]{64})\s+%s_valu_per_pair:\s*(\d+)\s+%s_flops_per_pair:\s*(\d+)"
+                      % (kind, kind, kind), txt)
+        if m and m.group(1) == kernel_source_hash(fname, head):
+            out[kind] = (int(m.group(2)), int(m.group(3)))
+    return out
+
+
+# VALU issue: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instructions per second
+PEAK_VALU_TINSTR = 39.32
+
+
 def traffic_from_profile(src_hash):
     """HBM bytes per leaf-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
@@ -113,21 +156,26 @@ def traffic_from_profile(src_hash):
     return float(m_f.group(1)) + float(m_w.group(1))
 
 
-def cpu_baseline(n, p, f, iters):
-    """The oracle (plain C, FP64, OpenMP) on a bounded sample: one volume-FMM
-    application at the full grid size (the dominant per-iteration cost of
-    the oracle's preconditioner), scaled by the GPU solve's iteration count.
-    The oracle's boundary solve, second pass and Arnoldi are not in the
-    sample, so the scaled rate is an upper bound on the oracle's solves/s."""
+def cpu_baseline(n, p, f):
+    """The oracle (plain C, FP64, OpenMP over independent targets) on the same
+    workload: its preconditioner setup (the LU factors of the 4n x 4n boundary
+    matrix) timed on its own, one preconditioner application on the right-hand
+    side (both FMM passes and the LU solve; its ring potential, boundary
+    density and output are kept to measure the GPU plans against), and one
+    whole right-preconditioned FGMRES(30) solve to 1e-8 (modified Gram-Schmidt
+    Arnoldi, one preconditioner application per iteration), setup excluded.
+    value = 1 / solve time."""
     import oracle as o
-    h = 1.0 / (n + 1)
-    q = f * h * h
-    times = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        o.grid_fmm(n, p, q)
-        times.append(time.perf_counter() - t0)
-    t = sorted(times)[1]
+    t0 = time.perf_counter()
+    pc = o.Preconditioner(n, p=p)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    zo, phio, sigo = pc.apply(f, stages=True)
+    t_apply = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    xo, info = o.fgmres(n, f, pc)
+    t_solve = time.perf_counter() - t0
+    pc.close()
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -137,12 +185,16 @@ def cpu_baseline(n, p, f, iters):
                     break
     except OSError:
         pass
-    return {"value": 1.0 / (t * max(iters, 1)), "unit": "solves/s", "cores": o.max_threads(),
-            "kind": "oracle", "cpu": model, "nproc": os.cpu_count(),
-            "sample": "oracle volume-FMM apply at %dx%d, p=%d, same f (median of 3: %.2f s "
-                      "wall), scaled by the GPU solve's %d iterations; excludes the oracle's "
-                      "boundary solve, second pass and Arnoldi" % (n, n, p, t, iters),
-            "sample_seconds": 3 * t}
+    out = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": o.max_threads(), "kind": "oracle",
+           "cpu": model, "nproc": os.cpu_count(),
+           "sample": "one whole oracle solve of the benchmark problem (%dx%d, p=%d, same f, "
+                     "FGMRES(30) to 1e-8: %d iterations, %.2f s wall), its setup (boundary LU, "
+                     "%.2f s) excluded; one oracle preconditioner application takes %.2f s"
+                     % (n, n, p, info["iters"], t_solve, t_setup, t_apply),
+           "setup_s": round(t_setup, 3), "precond_apply_s": round(t_apply, 3),
+           "solve_s": round(t_solve, 3), "iters": info["iters"],
+           "true_rel_res": info["true_rel_res"]}
+    return out, {"z": zo, "phi": phio, "sigma": sigo, "x": xo}
 
 
 def adjoint_block(fp, inputs, torch, steps, warmup):
@@ -252,8 +304,14 @@ def points_block(fp, inputs, torch, steps, warmup):
     xd, yd, qd = (torch.from_numpy(v).to(dev) for v in (x, y, q))
     out = {}
     res = {}
+    isa = points_isa_counts()
     for name, prec in (("fp64", fp.FMM_FP64), ("fp32", fp.FMM_FP32)):
-        with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=xd, y=yd, prec=prec) as pl:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pl = fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=p, x=xd, y=yd, prec=prec)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        with pl:
             u = torch.empty(N, dtype=torch.float64, device=dev)
             for _ in range(max(warmup, 1)):
                 pl.apply(qd, u)
@@ -270,15 +328,100 @@ def points_block(fp, inputs, torch, steps, warmup):
             pl.profile(())
             leaf_ms = lms / max(ln, 1)
             res[name] = u.clone()
+            gps = pairs / (leaf_ms * 1e-3)
             out[name] = {"apply_ms": round(ms, 4), "mpoints_per_s": round(N / (ms * 1e-3) / 1e6, 2),
+                         "setup_s": round(setup_s, 4),
                          "leaf_ms": round(leaf_ms, 4),
-                         "near_gpairs_per_s": round(pairs / (leaf_ms * 1e-3) / 1e9, 2)}
+                         "near_gpairs_per_s": round(gps / 1e9, 2)}
+            if name in isa:
+                valu, flops = isa[name]
+                peak = PEAK_FP64_VALU_TFLOPS if name == "fp64" else PEAK_FP32_VALU_TFLOPS
+                out[name]["leaf_roofline"] = {
+                    "bound": "alu", "kernel": "k_leaf_points" + ("_f32" if name == "fp32" else ""),
+                    "flops_per_pair": flops, "achieved": round(gps * flops / 1e12, 3),
+                    "unit": "TFLOP/s", "peak": peak, "frac": round(gps * flops / 1e12 / peak, 4),
+                    "valu_instr_per_pair": valu,
+                    "valu_issue_frac": round(gps * valu / 1e12 / PEAK_VALU_TINSTR, 4)}
     diff = float((res["fp32"] - res["fp64"]).abs().max() / res["fp64"].abs().max())
     return {"workload": "%d uniform random points in the unit square (seeds %d, %d), q ~ U(-1,1), "
                         "p=%d, list rule, L=%d" % (N, inputs.SEED_POINTS_XY, inputs.SEED_POINTS_Q, p, L),
             "near_pairs": pairs, "fp64": out["fp64"], "fp32": out["fp32"],
             "fp32_max_rel_diff_vs_fp64": diff,
             "fp32_speedup": round(out["fp64"]["apply_ms"] / out["fp32"]["apply_ms"], 3)}
+
+
+def direct_sum_sampled(torch, n, q, idx, dev):
+    """Exact grid sum u_i = -(1/2pi) [sum_{j != i} q_j log(h |i - j|) + q_i log(eps_s h)]
+    at the sampled nodes idx, in FP64 with plain torch operations (a reference
+    for the measurement, not part of the measured path)."""
+    h = 1.0 / (n + 1)
+    eps_s = math.exp(-0.57721566490153286061) / (2.0 * math.sqrt(2.0))
+    qd = torch.as_tensor(q, device=dev)
+    jj = torch.arange(n * n, device=dev)
+    gx = ((jj % n) + 1).to(torch.float64) * h
+    gy = ((jj // n) + 1).to(torch.float64) * h
+    out = []
+    for i in idx:
+        r2 = (gx - gx[i]) ** 2 + (gy - gy[i]) ** 2
+        r2[i] = 1.0
+        lg = 0.5 * torch.log(r2)
+        lg[i] = math.log(eps_s * h)
+        out.append(-(qd * lg).sum() / (2.0 * math.pi))
+    return torch.stack(out).cpu().numpy()
+
+
+def psweep_block(fp, inputs, torch, steps, warmup):
+    """The plain FP64 method at 1024 x 1024 (16 bumps, seed 1) for p in
+    {6, 8, 10, 12, 14}: solves/s to 1e-8, iterations, the bare FMM rate, and
+    the FMM's error against the exact grid sum (relative L2 at 512 sampled
+    nodes, random charges U(-1, 1), seed 77)."""
+    import numpy as np
+    n = 1024
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(inputs.gaussian_bumps(n, 16, seed=inputs.SEED_BUMPS_1024)).to(dev)
+    qh = inputs.random_charges(n * n, seed=77)
+    q = torch.from_numpy(qh).to(dev)
+    idx = inputs.target_subset(n * n, 512, seed=78)
+    ref = direct_sum_sampled(torch, n, qh, idx, dev)
+    u = torch.zeros_like(f)
+    w = torch.empty_like(f)
+    rows = {}
+    for p in (6, 8, 10, 12, 14):
+        with fp.fmm_setup(n=n, p=p, bem=1) as pl:
+            pl.tune()
+            for _ in range(max(warmup, 1)):
+                u.zero_()
+                pl.solve(f, u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                u.zero_()
+                info = pl.solve(f, u)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            pl.stencil_apply(u, w)
+            rel = float(torch.linalg.vector_norm(f - w) / torch.linalg.vector_norm(f))
+            uq = torch.empty_like(q)
+            pl.apply(q, uq)
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(10):
+                pl.apply(q, uq)
+            e1.record(st)
+            e1.synchronize()
+            ams = e0.elapsed_time(e1) / 10
+            ug = uq.cpu().numpy()[idx]
+            err = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
+        rows[str(p)] = {"solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(1000 * dt, 4),
+                        "iters": info["iters"], "true_rel_res": rel,
+                        "fmm_apply_ms": round(ams, 4),
+                        "fmm_mpoints_per_s": round(n * n / (ams * 1e-3) / 1e6, 1),
+                        "fmm_rel_l2_err_vs_direct": err}
+    return {"workload": "1024x1024 grid, f = 16 Gaussian bumps (seed %d), FMM-BEM preconditioner, "
+                        "FGMRES(30) to 1e-8, FP64; FMM error on random charges (seed 77) at 512 "
+                        "sampled nodes (seed 78) against the exact sum" % inputs.SEED_BUMPS_1024,
+            "by_p": rows}
 
 
 def batched_block(fp, inputs, torch, steps, warmup, prec=None):
@@ -341,6 +484,45 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
             "tuned_vector_blocks": {str(k): v for k, v in sorted(tuned.items())}}
 
 
+def trace_summary(path, top=40):
+    """Markdown tables from a rocprofv3 kernel trace (csv): total, calls and
+    average duration per kernel, then per kernel and launch shape (grid in
+    threads) for the kernels of the FMM and Krylov stages."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    by_k, by_shape = {}, {}
+    def short(name):
+        # drop the argument list of a demangled kernel name
+        depth, cut = 0, len(name)
+        for i, ch in enumerate(name):
+            if ch == "<":
+                depth += 1
+            elif ch == ">":
+                depth -= 1
+            elif ch == "(" and depth == 0:
+                cut = i
+                break
+        return name[:cut]
+
+    for r in rows:
+        name = short(r["Kernel_Name"])
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0
+        shape = (int(r.get("Grid_Size_X", 0) or 0), int(r.get("Grid_Size_Y", 0) or 0))
+        by_k.setdefault(name, []).append(dur)
+        by_shape.setdefault((name, shape), []).append(dur)
+    total = sum(sum(v) for v in by_k.values())
+    out = ["| Kernel | Calls | Total us | Average us | % |", "|---|---:|---:|---:|---:|"]
+    for name, v in sorted(by_k.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        out.append("| `%s` | %d | %.1f | %.2f | %.2f |" % (name, len(v), sum(v), sum(v) / len(v),
+                                                          100.0 * sum(v) / total))
+    out += ["", "| Kernel | Grid (x, y) | Launches | Average us |", "|---|---|---:|---:|"]
+    for (name, shape), v in sorted(by_shape.items(), key=lambda kv: (kv[0][0], -kv[0][1][0])):
+        if "fmmprec" not in name or len(v) < 2 and sum(v) < 100:
+            continue
+        out.append("| `%s` | %d, %d | %d | %.2f |" % (name, shape[0], shape[1], len(v), sum(v) / len(v)))
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,7 +535,12 @@ def main():
                     help="counter-collection mode: one 512 MiB elementwise y = x*1 (the "
                          "calibration kernel of known size: 512 MiB read, 512 MiB written), "
                          "then 3 FMM applies, 3 preconditioner applies and one solve")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print markdown tables of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -474,8 +661,20 @@ def main():
 
     iters = infos[-1]["iters"]
 
+    # preconditioner stages on the right-hand side f (ring potential, boundary
+    # density, output), kept per plan to set against the oracle's
+    def stages_of(pl):
+        zz, ph, sg = torch.empty_like(f), torch.empty(4 * n, dtype=torch.float64, device=dev), \
+            torch.empty(4 * n, dtype=torch.float64, device=dev)
+        pl.precond_stages(f, zz, ph, sg)
+        torch.cuda.synchronize()
+        return {"z": zz.cpu().numpy(), "phi": ph.cpu().numpy(), "sigma": sg.cpu().numpy()}
+
+    gpu_stages = {"fp64": stages_of(plan)}
+    gpu_solutions = {"fp64": u.cpu().numpy()}
+
     # precision variants: same solve and tolerance, reduced-precision P2P/P2M/M2L
-    def variant_block(prec, label, peak, mfma_per_flop):
+    def variant_block(prec, desc, peak, mfma_per_flop, label):
         pl = fp.fmm_setup(n=n, p=p, bem=1, prec=prec)
         pl.tune()
         for _ in range(args.warmup):
@@ -494,6 +693,8 @@ def main():
         plan.precond_apply(q, z64)
         pl.precond_apply(q, zv)
         perr = float((zv - z64).abs().max() / z64.abs().max())
+        gpu_stages[label] = stages_of(pl)
+        gpu_solutions[label] = u.cpu().numpy()
         pl.profile(fp.STAGES)
         u.zero_()
         pl.solve(f, u)
@@ -508,7 +709,7 @@ def main():
         m2l_avg = m2l_ms_v / max(m2l_n_v, 1)
         m2l_flops = 8.0 * p * p * m2l_translations((n // 8).bit_length() - 1)
         m2l_ach = m2l_flops / (m2l_avg * 1e-3) / 1e12 if m2l_avg > 0 else 0.0
-        return {"prec": label, "solves_per_s": round(args.steps / tv, 4),
+        return {"prec": desc, "solves_per_s": round(args.steps / tv, 4),
                 "ms_per_step": round(1000.0 * tv / args.steps, 4),
                 "speedup_vs_fp64": round((args.steps / tv) / solves_per_s, 3),
                 "iters": inf["iters"], "true_rel_res": relv,
@@ -599,13 +800,14 @@ def main():
     log("mac theta fp32: %.2f solves/s, %d iterations" % (mac32["solves_per_s"], mac32["iters"]))
     log("precision variants")
     variant = variant_block(fp.FMM_FP32, "P2P and P2M as FP32 MFMA contractions, M2L in FP32; "
-                            "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1)
+                            "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1, "fp32")
     variant16 = variant_block(fp.FMM_SPLIT_FP16, "P2P and P2M as FP16 hi+lo MFMA products "
                               "(hi*hi + hi*lo + lo*hi, FP32 accumulation), M2L in FP32; M2M, L2L, "
-                              "L2P, boundary, stencil, Arnoldi FP64", 2500.0, 3)
+                              "L2P, boundary, stencil, Arnoldi FP64", 2500.0, 3, "split_fp16")
     variantb16 = variant_block(fp.FMM_SPLIT_BF16, "P2P and P2M as BF16 hi+lo MFMA products "
                                "(hi*hi + hi*lo + lo*hi + lo*lo, FP32 accumulation), M2L in FP32; "
-                               "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 2500.0, 4)
+                               "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 2500.0, 4,
+                               "split_bf16")
     log("fp32 variant %.2f solves/s, split-fp16 %.2f, split-bf16 %.2f" % (
         variant["solves_per_s"], variant16["solves_per_s"], variantb16["solves_per_s"]))
     log("variable coefficient")
@@ -624,12 +826,27 @@ def main():
     adjoint = adjoint_block(fp, inputs, torch, args.steps, args.warmup)
     log("adjoint %.2f gradients/s, fd err %.2e" % (adjoint["gradients_per_s"],
                                                    adjoint["centre_grad_rel_err_vs_central_fd"]))
+    log("1024^2 p sweep")
+    psweep = psweep_block(fp, inputs, torch, args.steps, args.warmup)
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(n, p, f_host, iters)
-        log("cpu baseline %.2f s" % cpu["sample_seconds"])
-        cpu.pop("sample_seconds")
+        import numpy as np
+        log("cpu baseline (oracle solve) ...")
+        cpu, ref = cpu_baseline(n, p, f_host)
+        log("cpu baseline: setup %.2f s, solve %.2f s" % (cpu["setup_s"], cpu["solve_s"]))
+        # every plan's preconditioner stages on f and its solution against the oracle's
+        relmax = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+        for key, blk in (("fp64", None), ("fp32", variant), ("split_fp16", variant16),
+                         ("split_bf16", variantb16)):
+            g = gpu_stages[key]
+            err = {"phi_ring": relmax(g["phi"], ref["phi"]), "sigma": relmax(g["sigma"], ref["sigma"]),
+                   "z": relmax(g["z"], ref["z"]),
+                   "solution_rel_l2": float(np.linalg.norm(gpu_solutions[key] - ref["x"])
+                                            / np.linalg.norm(ref["x"]))}
+            if blk is None:
+                stage_err_fp64 = err
+            else:
+                blk["stage_rel_err_vs_fp64_oracle"] = err
 
     res = {
         "metric": "FMM-precond GMRES solves/s to 1e-8 rel. residual, 2048^2 grid; FMM Mpoints/s",
@@ -661,6 +878,8 @@ def main():
         "stage_rooflines": stage_roof,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "stage_rel_err_vs_fp64_oracle": stage_err_fp64 if cpu else None,
+        "p_sweep_1024": psweep,
         "variant_fp32": variant,
         "variant_split_fp16": variant16,
         "variant_split_bf16": variantb16,
