@@ -427,11 +427,14 @@ def psweep_block(fp, inputs, torch, steps, warmup):
 def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     """64 independent solves of uneven sizes (16 each of 128^2, 256^2, 512^2,
     1024^2; instance k has 16 bumps seeded 1000 + k), p = 10, FGMRES(30) to
-    1e-8.  Each plan's vector kernels are autotuned first; the batch runs with
-    HIP-graph replay of the Arnoldi steps (captured in the warm-up).  Reports
+    1e-8.  Each plan's vector kernels are autotuned first.  The batch runs as
+    four groups of 16 same-size instances (one launch per stage for a group,
+    Givens rotations and convergence flags on the device), the steps and
+    cycle ends replayed from HIP graphs captured in the warm-up.  Reports
     instances/s over the whole batch and the p50/p99 of the per-instance
-    completion times, next to the same 64 solves run one after another and
-    the batch without graphs."""
+    completion times, next to the batch without graphs, the separate layout
+    (one solve per plan on its own stream, host Givens) and the same 64
+    solves run one after another."""
     sizes = [s for s in (128, 256, 512, 1024) for _ in range(16)]
     dev = torch.device("cuda:0")
     plans = [fp.fmm_setup(n=n, p=10, bem=1, prec=fp.FMM_FP64 if prec is None else prec)
@@ -443,12 +446,12 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     for pl in plans:
         tuned[pl.n] = pl.tune()
 
-    def run(graphs):
+    def run(graphs, separate=False):
         for u in us:
             u.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = fp.precond_gmres_solve_batch(plans, fs, us, graphs=graphs)
+        out = fp.precond_gmres_solve_batch(plans, fs, us, graphs=graphs, separate=separate)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, out
 
@@ -462,6 +465,8 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     iters = [r["iters"] for r in out["results"]]
     ok = all(r["converged"] for r in out["results"])
     tn = min(run(False)[0] for _ in range(2))
+    run(True, True)
+    tsep = min(run(True, True)[0] for _ in range(2))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pl, f, u in zip(plans, fs, us):
@@ -480,6 +485,7 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
             "p50_ms": round(pct(0.5), 3), "p99_ms": round(pct(0.99), 3),
             "all_converged": ok, "iters_min_max": [min(iters), max(iters)],
             "no_graphs_instances_per_s": round(64.0 / tn, 2),
+            "separate_plans_instances_per_s": round(64.0 / tsep, 2),
             "sequential_instances_per_s": round(64.0 / ts, 2),
             "tuned_vector_blocks": {str(k): v for k, v in sorted(tuned.items())}}
 

@@ -217,20 +217,40 @@ int precond_gmres_solve(fmm_plan *plan, const double *f, const double *g, double
  * i solves A u[i] = f[i] on plans[i] (zero ring data) with the settings of
  * precond_gmres_solve.  plans, f, u, res and elapsed_ms are HOST arrays of
  * count entries (f[i], u[i] device arrays as for precond_gmres_solve; res
- * and elapsed_ms may be NULL); the plans must be distinct (each owns the
- * workspace of its solve).  Every plan runs on a stream of its own, created
- * on first use, after the work already on `stream`; a host loop advances
- * whichever solve's last chunk has completed, so small and large grids
- * overlap on the GPU.  elapsed_ms[i] = host time from the call to the end of
- * solve i.  flags: FMM_BATCH_GRAPHS replays each Arnoldi step (the whole
- * preconditioner, both orthogonalisation sweeps and the scalar copy) from a
- * HIP graph captured on the plan the first time that step runs.  `stream`
- * waits for every instance before later work.  Returns FMM_OK when every
- * instance converged, FMM_NOT_CONVERGED when one did not, or an error. */
-enum { FMM_BATCH_GRAPHS = 1 };
+ * and elapsed_ms may be NULL); the plans must be distinct.  Instances whose
+ * plans describe the same problem (n, p, prec, theta, self_eps, bem) are
+ * solved as groups of up to 16: every launch of an Arnoldi step (the whole
+ * preconditioner, both orthogonalisation sweeps) covers the group, and the
+ * Givens rotations and convergence tests run on the device, so a finished
+ * instance turns the group's later launches into no-ops for itself.  A group
+ * runs on the plan of its first instance (whose workspace then holds the
+ * group's Krylov bases) and on that plan's stream, after the work already on
+ * `stream`; a host loop advances whichever group's last step has completed,
+ * so groups of different sizes overlap on the GPU.  elapsed_ms[i] = host
+ * time from the call to the end of the cycle in which instance i converged.
+ * flags: FMM_BATCH_GRAPHS replays each step (and each cycle's end) of a
+ * group from a HIP graph captured the first time it runs;
+ * FMM_BATCH_SEPARATE runs one solve per plan instead (each on its own
+ * stream, Givens rotations on the host), the layout before groups.
+ * `stream` waits for every instance before later work.  Returns FMM_OK when
+ * every instance converged, FMM_NOT_CONVERGED when one did not, or an
+ * error. */
+enum { FMM_BATCH_GRAPHS = 1, FMM_BATCH_SEPARATE = 2 };
 int precond_gmres_solve_batch(fmm_plan *const *plans, int32_t count, const double *const *f,
                               double *const *u, const gmres_params *prm, gmres_result *res,
                               double *elapsed_ms, int32_t flags, void *stream);
+
+/* nrhs right-hand sides on one plan at once (GRID plans; the many
+ * right-hand sides of Sec. 3.1's solve): f and u hold nrhs grids of n*n
+ * doubles back to back (u: initial guesses on entry, solutions on exit),
+ * res (HOST, may be NULL) nrhs results.  Solved in groups of up to 16 as in
+ * precond_gmres_solve_batch (one launch per stage for the group, Givens
+ * rotations and convergence tests on the device); flags: FMM_BATCH_GRAPHS.
+ * Synchronises `stream`.  Arguments and return codes otherwise as for
+ * precond_gmres_solve. */
+int precond_gmres_solve_multi(fmm_plan *plan, int32_t nrhs, const double *f, double *u,
+                              const gmres_params *prm, gmres_result *res, int32_t flags,
+                              void *stream);
 
 /* Autotuner: times the Krylov sweeps of this plan's grid with candidate
  * block counts (64 .. 4096) and keeps the fastest for later solves; the

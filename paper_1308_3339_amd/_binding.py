@@ -14,7 +14,7 @@ FMM_OK, FMM_NOT_CONVERGED = 0, 1
 FMM_ERR_ARG, FMM_ERR_DEVICE, FMM_ERR_ALLOC, FMM_ERR_NUMERIC, FMM_ERR_UNSUPPORTED = -1, -2, -3, -4, -5
 FMM_GRID, FMM_POINTS = 0, 1
 FMM_FP64, FMM_FP32, FMM_SPLIT_BF16, FMM_SPLIT_FP16 = 0, 1, 2, 3
-FMM_BATCH_GRAPHS = 1
+FMM_BATCH_GRAPHS, FMM_BATCH_SEPARATE = 1, 2
 
 # every symbol include/fmmprec.h declares
 exported_symbols = (
@@ -22,7 +22,7 @@ exported_symbols = (
     "precond_gmres_solve", "fmm_destroy", "fmm_last_error", "fmm_version", "fmm_profile",
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
     "fmm_stencil_var_apply", "precond_gmres_solve_var", "precond_gmres_solve_batch", "fmm_tune",
-    "fmm_bumps_grad_noalloc", "fmm_points_order",
+    "fmm_bumps_grad_noalloc", "fmm_points_order", "precond_gmres_solve_multi",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -94,6 +94,9 @@ def load_library():
                                             ctypes.POINTER(gmres_result),
                                             ctypes.POINTER(ctypes.c_double), i32, vp]
     L.precond_gmres_solve_batch.restype = i32
+    L.precond_gmres_solve_multi.argtypes = [vp, i32, dp, dp, ctypes.POINTER(gmres_params),
+                                            ctypes.POINTER(gmres_result), i32, vp]
+    L.precond_gmres_solve_multi.restype = i32
     L.fmm_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
     L.fmm_tune.restype = i32
     L.fmm_stencil_var_apply.argtypes = [vp, dp, dp, dp, dp, vp]
@@ -254,8 +257,26 @@ def precond_gmres_solve(plan, f, u, g=None, tol=1e-8, restart=30, maxit=600, str
             "true_rel_res": res.true_rel_res}
 
 
-def precond_gmres_solve_batch(plans, fs, us, tol=1e-8, restart=30, maxit=600, graphs=True,
+def precond_gmres_solve_multi(plan, f, u, nrhs, tol=1e-8, restart=30, maxit=600, graphs=True,
                               stream=None):
+    """nrhs stacked right-hand sides on one plan (f, u: nrhs * n*n).  Returns
+    {"status", "results": [per-instance dict]}."""
+    N = plan.npts
+    prm = gmres_params(tol, restart, maxit)
+    res = (gmres_result * nrhs)()
+    code = load_library().precond_gmres_solve_multi(plan._ptr, nrhs, _dptr(f, "f", N * nrhs),
+                                                    _dptr(u, "u", N * nrhs), ctypes.byref(prm), res,
+                                                    FMM_BATCH_GRAPHS if graphs else 0,
+                                                    _stream(stream))
+    _check(code, plan._ptr)
+    return {"status": code,
+            "results": [{"converged": r.true_rel_res <= tol, "iters": r.iters,
+                         "restarts": r.restarts, "est_rel_res": r.est_rel_res,
+                         "true_rel_res": r.true_rel_res} for r in res]}
+
+
+def precond_gmres_solve_batch(plans, fs, us, tol=1e-8, restart=30, maxit=600, graphs=True,
+                              stream=None, separate=False):
     """Solves A u_i = f_i on plans[i] for every i at once (distinct GRID plans).
     Returns {"status", "results": [per-instance dict], "elapsed_ms": [...]}."""
     count = len(plans)
@@ -269,8 +290,9 @@ def precond_gmres_solve_batch(plans, fs, us, tol=1e-8, restart=30, maxit=600, gr
     res = (gmres_result * count)()
     el = (ctypes.c_double * count)()
     L = load_library()
-    code = L.precond_gmres_solve_batch(P, count, F, U, ctypes.byref(prm), res, el,
-                                       FMM_BATCH_GRAPHS if graphs else 0, _stream(stream))
+    flags = (FMM_BATCH_GRAPHS if graphs else 0) | (FMM_BATCH_SEPARATE if separate else 0)
+    code = L.precond_gmres_solve_batch(P, count, F, U, ctypes.byref(prm), res, el, flags,
+                                       _stream(stream))
     if code < 0:
         msgs = [L.fmm_last_error(p._ptr) for p in plans] + [L.fmm_last_error(None)]
         msg = next((m.decode() for m in msgs if m), "")
@@ -399,6 +421,7 @@ class Plan:
     stencil_apply = fmm_stencil_apply
     solve = precond_gmres_solve
     solve_adjoint = precond_gmres_solve_adjoint
+    solve_multi = precond_gmres_solve_multi
     stencil_var_apply = fmm_stencil_var_apply
     tune = fmm_tune
     solve_var = precond_gmres_solve_var

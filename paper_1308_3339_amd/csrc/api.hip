@@ -299,21 +299,67 @@ static int build_levels_and_work(fmm_plan *pl)
         pl->n_ring_p2m = (int)bc.size();
         if ((st = upload(pl, &pl->ring_p2m_cells, bc))) return st;
     }
-    if (off > 0) {
-        const size_t bytes = (size_t)off * sizeof(double2);
-        FMM_HIP(pl, hipMalloc(&pl->ws.M, bytes));
-        FMM_HIP(pl, hipMalloc(&pl->ws.Lt, bytes));
-        FMM_HIP(pl, hipMalloc(&pl->ws.Lm, bytes));
+    return ensure_rhs(pl, 1);
+}
+
+RhsSet plan_rhs(const fmm_plan *pl, int64_t sv, const int *act)
+{
+    RhsSet rh;
+    rh.sv = sv;
+    rh.se = pl->exp_elems;
+    rh.sr = 4 * pl->n;
+    rh.sb = 3 * pl->n;
+    rh.act = act;
+    return rh;
+}
+
+int ensure_rhs(fmm_plan *pl, int nr)
+{
+    if (nr <= pl->rhs_cap) return FMM_OK;
+    drop_step_graphs(pl);
+    double2 **exps[] = {&pl->ws.M, &pl->ws.Lt, &pl->ws.Lm, &pl->ws.M2, &pl->ws.Lt2, &pl->ws.Lm2};
+    for (double2 **e : exps)
+        if (*e) {
+            (void)hipFree(*e);
+            *e = nullptr;
+        }
+    double **rings[] = {&pl->phi_ring, &pl->ring_q};
+    for (double **r : rings)
+        if (*r) {
+            (void)hipFree(*r);
+            *r = nullptr;
+        }
+    double2 **bhs[] = {&pl->bhat, &pl->shat};
+    for (double2 **b : bhs)
+        if (*b) {
+            (void)hipFree(*b);
+            *b = nullptr;
+        }
+    pl->rhs_cap = 0;
+    if (pl->exp_elems > 0) {
+        const size_t bytes = (size_t)pl->exp_elems * nr * sizeof(double2);
+        if (hipMalloc(&pl->ws.M, bytes) != hipSuccess || hipMalloc(&pl->ws.Lt, bytes) != hipSuccess ||
+            hipMalloc(&pl->ws.Lm, bytes) != hipSuccess)
+            return fail(pl, FMM_ERR_ALLOC, "expansion workspace allocation failed");
         if (pl->kind == FMM_GRID && pl->bem) {
             // the boundary-source pass writes only border tiles of M2 and only
             // the boundary band of Lm2: everything else must stay zero
-            FMM_HIP(pl, hipMalloc(&pl->ws.M2, bytes));
+            if (hipMalloc(&pl->ws.M2, bytes) != hipSuccess || hipMalloc(&pl->ws.Lt2, bytes) != hipSuccess ||
+                hipMalloc(&pl->ws.Lm2, bytes) != hipSuccess)
+                return fail(pl, FMM_ERR_ALLOC, "expansion workspace allocation failed");
             FMM_HIP(pl, hipMemset(pl->ws.M2, 0, bytes));
-            FMM_HIP(pl, hipMalloc(&pl->ws.Lt2, bytes));
-            FMM_HIP(pl, hipMalloc(&pl->ws.Lm2, bytes));
             FMM_HIP(pl, hipMemset(pl->ws.Lm2, 0, bytes));
         }
     }
+    if (pl->kind == FMM_GRID) {
+        const size_t n = (size_t)pl->n;
+        if (hipMalloc(&pl->phi_ring, 4 * n * nr * sizeof(double)) != hipSuccess ||
+            hipMalloc(&pl->ring_q, 4 * n * nr * sizeof(double)) != hipSuccess ||
+            hipMalloc(&pl->bhat, 3 * n * nr * sizeof(double2)) != hipSuccess ||
+            hipMalloc(&pl->shat, 3 * n * nr * sizeof(double2)) != hipSuccess)
+            return fail(pl, FMM_ERR_ALLOC, "ring workspace allocation failed");
+    }
+    pl->rhs_cap = nr;
     return FMM_OK;
 }
 
@@ -330,6 +376,7 @@ static void release(fmm_plan *pl)
         if (p) (void)hipFree(p);
     if (pl->hpin) (void)hipHostFree(pl->hpin);
     drop_step_graphs(pl);
+    release_group(pl);
     if (pl->bevent) (void)hipEventDestroy(pl->bevent);
     for (hipEvent_t e : pl->sevent)
         if (e) (void)hipEventDestroy(e);
@@ -512,9 +559,20 @@ int fmm_apply(fmm_plan *pl, const double *q, double *u, int nrhs, void *stream)
     if (q == u) return fail(pl, FMM_ERR_ARG, "u must not alias q");
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (pl->kind == FMM_GRID) ? (size_t)pl->n * pl->n : (size_t)pl->n;
+    if (pl->kind == FMM_GRID) {
+        // the nrhs grids as one launch sequence, in chunks the workspace holds
+        for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsChunk) {
+            const int nr = std::min(kMaxRhsChunk, nrhs - r0);
+            int st = ensure_rhs(pl, nr);
+            if (st == FMM_OK)
+                st = grid_volume_fmm(pl, q + r0 * N, 1.0, u + r0 * N, nullptr, false,
+                                     plan_rhs(pl, (int64_t)N, nullptr), nr, s);
+            if (st != FMM_OK) return st;
+        }
+        return FMM_OK;
+    }
     for (int r = 0; r < nrhs; ++r) {
-        int st = (pl->kind == FMM_GRID) ? grid_volume_fmm(pl, q + r * N, 1.0, u + r * N, nullptr, false, s)
-                                        : points_fmm(pl, q + r * N, u + r * N, s);
+        int st = points_fmm(pl, q + r * N, u + r * N, s);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;
@@ -544,8 +602,10 @@ int fmm_precond_apply(fmm_plan *pl, const double *r, double *z, int nrhs, void *
     if (r == z) return fail(pl, FMM_ERR_ARG, "z must not alias r");
     hipStream_t s = (hipStream_t)stream;
     const size_t N = (size_t)pl->n * pl->n;
-    for (int k = 0; k < nrhs; ++k) {
-        int st = precond_apply_one(pl, r + k * N, z + k * N, nullptr, nullptr, s);
+    if (nrhs == 1) return precond_apply_one(pl, r, z, nullptr, nullptr, s);
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsChunk) {
+        const int nr = std::min(kMaxRhsChunk, nrhs - r0);
+        int st = precond_apply_rhs(pl, r + r0 * N, z + r0 * N, nr, (int64_t)N, nullptr, s);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;
@@ -565,12 +625,7 @@ int fmm_stencil_apply(fmm_plan *pl, const double *v, double *w, int nrhs, void *
     if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
     if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "stencil needs a GRID plan");
     if (!v || !w || nrhs < 1 || v == w) return fail(pl, FMM_ERR_ARG, "v/w NULL, aliased or nrhs < 1");
-    const size_t N = (size_t)pl->n * pl->n;
-    for (int k = 0; k < nrhs; ++k) {
-        int st = stencil_apply(pl, v + k * N, w + k * N, (hipStream_t)stream);
-        if (st != FMM_OK) return st;
-    }
-    return FMM_OK;
+    return stencil_apply(pl, v, w, nrhs, (hipStream_t)stream);
 }
 
 int precond_gmres_solve(fmm_plan *pl, const double *f, const double *g, double *u,
@@ -631,14 +686,57 @@ int precond_gmres_solve_batch(fmm_plan *const *plans, int32_t count, const doubl
         for (int k = 0; k < i; ++k)
             if (plans[k] == pl) return fail(pl, FMM_ERR_ARG, "a plan appears twice in the batch");
     }
-    if (flags & ~FMM_BATCH_GRAPHS) return fail(plans[0], FMM_ERR_ARG, "unknown flags");
+    if (flags & ~(FMM_BATCH_GRAPHS | FMM_BATCH_SEPARATE)) return fail(plans[0], FMM_ERR_ARG, "unknown flags");
     gmres_params q{1e-8, 30, 600};
     if (prm) q = *prm;
     if (!(q.tol > 0.0) || !std::isfinite(q.tol)) return fail(plans[0], FMM_ERR_ARG, "tol must be > 0");
     if (q.restart < 1 || q.restart > 32) return fail(plans[0], FMM_ERR_ARG, "restart must be in [1, 32]");
     if (q.maxit < 1) return fail(plans[0], FMM_ERR_ARG, "maxit must be >= 1");
     return gmres_solve_batch(plans, count, f, u, &q, res, elapsed_ms, (flags & FMM_BATCH_GRAPHS) != 0,
+                             (flags & FMM_BATCH_SEPARATE) != 0,
                              (hipStream_t)stream);
+}
+
+int precond_gmres_solve_multi(fmm_plan *pl, int32_t nrhs, const double *f, double *u,
+                              const gmres_params *prm, gmres_result *res, int32_t flags, void *stream)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (pl->kind != FMM_GRID) return fail(pl, FMM_ERR_ARG, "solve needs a GRID plan");
+    if (!f || !u || nrhs < 1) return fail(pl, FMM_ERR_ARG, "f or u is NULL, or nrhs < 1");
+    if (f == u) return fail(pl, FMM_ERR_ARG, "u must not alias f");
+    if (flags & ~FMM_BATCH_GRAPHS) return fail(pl, FMM_ERR_ARG, "unknown flags");
+    gmres_params q{1e-8, 30, 600};
+    if (prm) q = *prm;
+    if (!(q.tol > 0.0) || !std::isfinite(q.tol)) return fail(pl, FMM_ERR_ARG, "tol must be > 0");
+    if (q.restart < 1 || q.restart > 32) return fail(pl, FMM_ERR_ARG, "restart must be in [1, 32]");
+    if (q.maxit < 1) return fail(pl, FMM_ERR_ARG, "maxit must be >= 1");
+    const size_t N = (size_t)pl->n * pl->n;
+    const bool graphs = (flags & FMM_BATCH_GRAPHS) && !pl->prof_mask;
+    // the solve runs on the plan's own stream (graphs cannot be captured on
+    // the null stream), ordered after the work on `stream`
+    hipStream_t caller = (hipStream_t)stream;
+    if (!pl->bstream) FMM_HIP(pl, hipStreamCreateWithFlags(&pl->bstream, hipStreamNonBlocking));
+    if (!pl->bevent) FMM_HIP(pl, hipEventCreateWithFlags(&pl->bevent, hipEventDisableTiming));
+    FMM_HIP(pl, hipEventRecord(pl->bevent, caller));
+    FMM_HIP(pl, hipStreamWaitEvent(pl->bstream, pl->bevent, 0));
+    int overall = FMM_OK;
+    for (int r0 = 0; r0 < nrhs; r0 += kMaxRhsChunk) {
+        const int nr = std::min(kMaxRhsChunk, nrhs - r0);
+        std::vector<const double *> fp(nr);
+        std::vector<double *> up(nr);
+        for (int r = 0; r < nr; ++r) {
+            fp[r] = f + (r0 + r) * N;
+            up[r] = u + (r0 + r) * N;
+        }
+        const int st = gmres_solve_group(pl, nr, fp.data(), up.data(), &q, res ? res + r0 : nullptr,
+                                         graphs, pl->bstream);
+        if (st < 0) return st;
+        if (st != FMM_OK) overall = st;
+    }
+    FMM_HIP(pl, hipEventRecord(pl->bevent, pl->bstream));
+    FMM_HIP(pl, hipStreamWaitEvent(caller, pl->bevent, 0));
+    FMM_HIP(pl, hipStreamSynchronize(caller));
+    return overall;
 }
 
 int fmm_tune(fmm_plan *pl, void *stream, int32_t *vec_blocks)

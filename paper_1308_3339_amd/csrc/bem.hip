@@ -170,48 +170,79 @@ __global__ __launch_bounds__(256) void k_bem_fold(const double *__restrict__ X0,
 //   y = 0: X0 even . e0,  1: X0 odd . o0,  2: X2 even . e2,  3: X2 odd . o2,
 //   4: even part of mode 1 = Re X1 even . e1 + i Im X1 (odd -> even) . o1,
 //   5: odd part of mode 1  = i Im X1 (even -> odd) . e1 + Re X1 odd . o1.
+// Several right-hand sides share one read of the inverse: blockIdx.z takes
+// up to NRB of them (rh.sb apart), each accumulated in the same order as a
+// lone right-hand side, so every result is the same bit for bit.
+constexpr int kGemvRhs = 8;
+
+template <int NRB>
 __global__ __launch_bounds__(256) void k_bem_gemv(const double *__restrict__ Xh,
                                                   const double2 *__restrict__ bh,
-                                                  double2 *__restrict__ sh, int n)
+                                                  double2 *__restrict__ sh, int n, RhsSet rh,
+                                                  int nr)
 {
     const int m = n >> 1;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int which = blockIdx.y;
+    const int r0 = blockIdx.z * NRB;
     if (row >= m) return;
+    bool on[NRB];
+#pragma unroll
+    for (int c = 0; c < NRB; ++c) on[c] = r0 + c < nr && rhs_active(rh, r0 + c);
     const size_t hs = (size_t)m * m;
-    double ax = 0.0, ay = 0.0;
+    double ax[NRB], ay[NRB];
+#pragma unroll
+    for (int c = 0; c < NRB; ++c) ax[c] = ay[c] = 0.0;
     if (which < 4) {
         const double *X = Xh + which * hs + (size_t)row * m;
-        const double2 *bv = bh + which * m;
-        for (int j = lane; j < m; j += 64) ax = fma(X[j], bv[j].x, ax);
+        const double2 *bv = bh + which * m + r0 * rh.sb;
+        for (int j = lane; j < m; j += 64) {
+            const double x = X[j];
+#pragma unroll
+            for (int c = 0; c < NRB; ++c)
+                if (on[c]) ax[c] = fma(x, bv[c * rh.sb + j].x, ax[c]);
+        }
     } else {
         // which 4: Re part acts on e1, Im part (odd -> even) on o1; which 5:
         // Im part (even -> odd) on e1, Re part on o1
         const double *R = Xh + (which == 4 ? kH1RE : kH1RO) * hs + (size_t)row * m;
         const double *I = Xh + (which == 4 ? kH1IEO : kH1IOE) * hs + (size_t)row * m;
-        const double2 *br = bh + 2 * n + (which == 4 ? 0 : m);   // input of the Re part
-        const double2 *bi = bh + 2 * n + (which == 4 ? m : 0);   // input of the Im part
+        const double2 *br = bh + 2 * n + (which == 4 ? 0 : m) + r0 * rh.sb;   // input of the Re part
+        const double2 *bi = bh + 2 * n + (which == 4 ? m : 0) + r0 * rh.sb;   // input of the Im part
         for (int j = lane; j < m; j += 64) {
             const double xr = R[j], xi = I[j];
-            const double2 u = br[j], v = bi[j];
-            // xr u + i xi v
-            ax = fma(xr, u.x, fma(-xi, v.y, ax));
-            ay = fma(xr, u.y, fma(xi, v.x, ay));
+#pragma unroll
+            for (int c = 0; c < NRB; ++c)
+                if (on[c]) {
+                    const double2 u = br[c * rh.sb + j], v = bi[c * rh.sb + j];
+                    // xr u + i xi v
+                    ax[c] = fma(xr, u.x, fma(-xi, v.y, ax[c]));
+                    ay[c] = fma(xr, u.y, fma(xi, v.x, ay[c]));
+                }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        ax += __shfl_xor(ax, o);
-        ay += __shfl_xor(ay, o);
+#pragma unroll
+    for (int c = 0; c < NRB; ++c) {
+        if (!on[c]) continue;
+        double x = ax[c], y = ay[c];
+        for (int o = 32; o > 0; o >>= 1) {
+            x += __shfl_xor(x, o);
+            y += __shfl_xor(y, o);
+        }
+        if (lane == 0) sh[(r0 + c) * rh.sb + which * m + row] = make_double2(x, y);
     }
-    if (lane == 0) sh[which * m + row] = make_double2(ax, ay);
 }
 
 // sigma (ring_sigma) and the ring charges h sigma at every node; the
 // boundary-source pass computes them itself when the tree has levels >= 2
 __global__ void k_bem_sigma(const double2 *__restrict__ sh, double *__restrict__ rq,
-                            double *__restrict__ sig_out, int n, double h)
+                            double *__restrict__ sig_out, int n, double h, RhsSet rh)
 {
+    if (!rhs_active(rh, blockIdx.z)) return;
+    sh += blockIdx.z * rh.sb;
+    rq += blockIdx.z * rh.sr;
+    if (sig_out) sig_out += blockIdx.z * rh.sr;
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= 4 * n) return;
     const int s = t / n, k = t - s * n;
@@ -228,10 +259,6 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
     FMM_HIP(pl, hipMalloc(&pl->X0, nn * sizeof(double)));
     FMM_HIP(pl, hipMalloc(&pl->X2, nn * sizeof(double)));
     FMM_HIP(pl, hipMalloc(&pl->X1, nn * sizeof(double2)));
-    FMM_HIP(pl, hipMalloc(&pl->phi_ring, 4 * (size_t)n * sizeof(double)));
-    FMM_HIP(pl, hipMalloc(&pl->ring_q, 4 * (size_t)n * sizeof(double)));
-    FMM_HIP(pl, hipMalloc(&pl->bhat, 3 * (size_t)n * sizeof(double2)));
-    FMM_HIP(pl, hipMalloc(&pl->shat, 3 * (size_t)n * sizeof(double2)));
     FMM_HIP(pl, hipMalloc(&tmp, nn * sizeof(double2)));
     FMM_HIP(pl, hipMalloc(&rk, (size_t)n * sizeof(double2)));
     const dim3 g2((n + 63) / 64, (n + 3) / 4), g1((n + 255) / 256);
@@ -280,16 +307,20 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
 // volume pass) into pl->shat.  With levels >= 2 the boundary-source pass
 // forms sigma and the charges from pl->shat inside its P2M; otherwise they
 // are formed here (pl->ring_q, and sigma_out when given).
-int bem_apply(fmm_plan *pl, double *sigma_out, hipStream_t s)
+int bem_apply(fmm_plan *pl, double *sigma_out, const RhsSet &rh, int nr, hipStream_t s)
 {
     const int n = (int)pl->n;
     StageTimer t(pl, FMM_STAGE_BEM, s);
     const int m = n / 2;
-    hipLaunchKernelGGL(k_bem_gemv, dim3((m + 3) / 4, 6), dim3(256), 0, s, pl->Xh, pl->bhat,
-                       pl->shat, n);
+    if (nr == 1)
+        hipLaunchKernelGGL(k_bem_gemv<1>, dim3((m + 3) / 4, 6, 1), dim3(256), 0, s, pl->Xh, pl->bhat,
+                           pl->shat, n, rh, nr);
+    else
+        hipLaunchKernelGGL(k_bem_gemv<kGemvRhs>, dim3((m + 3) / 4, 6, (nr + kGemvRhs - 1) / kGemvRhs),
+                           dim3(256), 0, s, pl->Xh, pl->bhat, pl->shat, n, rh, nr);
     if (pl->L < 2)
-        hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256), dim3(256), 0, s, pl->shat,
-                           pl->ring_q, sigma_out, n, pl->h);
+        hipLaunchKernelGGL(k_bem_sigma, dim3((4 * n + 255) / 256, 1, nr), dim3(256), 0, s, pl->shat,
+                           pl->ring_q, sigma_out, n, pl->h, rh);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }

@@ -152,8 +152,10 @@ __device__ __forceinline__ void m2m_chain(const double2 *sA, double2 *s0, double
 template <int P>
 __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
                                                 const double2 *__restrict__ A, LevelInfo lv,
-                                                int l_in)
+                                                int l_in, RhsSet rh)
 {
+    if (!rhs_active(rh, blockIdx.z)) return;
+    M += blockIdx.z * rh.se;
     __shared__ double2 sA[4 * P * P];
     __shared__ double2 s0[P * 64], s1[P * 16], s2[P * 4], s3[P];
     const int nc = 1 << l_in, tw = nc < 8 ? nc : 8, nt = nc / tw;
@@ -201,9 +203,12 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                                              const int4 *__restrict__ offs,
                                              const double *__restrict__ a_n,
                                              const double *__restrict__ b_k, int nlist,
-                                             int halo)
+                                             int halo, RhsSet rh)
 {
     using C = typename Cplx<R>::T;
+    if (!rhs_active(rh, blockIdx.z)) return;
+    M += blockIdx.z * rh.se;
+    Lm += blockIdx.z * rh.se;
     extern __shared__ __align__(16) unsigned char sm_raw[];
     C *sm = reinterpret_cast<C *>(sm_raw);   // [P][RW*RW] parity split; later [P][256] reduction
     const M2LItem it = items[blockIdx.x];
@@ -424,8 +429,11 @@ template <int P>
 __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
                                               double2 *__restrict__ Lt,
                                               const double2 *__restrict__ B, LevelInfo lv, int r,
-                                              int m, int root)
+                                              int m, int root, RhsSet rh)
 {
+    if (!rhs_active(rh, blockIdx.z)) return;
+    Lm += blockIdx.z * rh.se;
+    Lt += blockIdx.z * rh.se;
     __shared__ double2 sB[4 * P * P];
     __shared__ double2 sm2l[P * 84];          // M2L sums of the 4 + 16 + 64 descendants
     __shared__ double2 buf0[P * 64], buf1[P * 64];
@@ -464,6 +472,7 @@ __device__ __forceinline__ constexpr int leaf_tile_idx(int pos, int r, int c)
 }
 
 struct LeafArgs {
+    RhsSet rh;            // right-hand side blockIdx.z: strides and active mask
     const double *q;
     double qscale;
     double *u;
@@ -486,9 +495,33 @@ __device__ __forceinline__ int near_kx(int kxp, int b)
     return ((kxp >> (4 * b)) & 15) - 1;
 }
 
+// The arrays of right-hand side blockIdx.z (on = false when that right-hand
+// side is inactive: the whole block leaves).  The kernels keep a itself in
+// the kernel arguments and take these four pointers from here.
+struct LeafPtrs {
+    bool on;
+    const double *q;
+    double *u;
+    double2 *M;
+    const double2 *Lt;
+};
+__device__ __forceinline__ LeafPtrs rhs_ptrs(const LeafArgs &a)
+{
+    const int r = blockIdx.z;
+    LeafPtrs p;
+    p.on = rhs_active(a.rh, r);
+    p.q = a.q ? a.q + r * a.rh.sv : nullptr;
+    p.u = a.u ? a.u + r * a.rh.sv : nullptr;
+    p.M = a.M ? a.M + r * a.rh.se : nullptr;
+    p.Lt = a.Lt ? a.Lt + r * a.rh.se : nullptr;
+    return p;
+}
+
 template <int P>
 __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
     __shared__ double sq[6400];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -503,7 +536,7 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
             const int e = tid + 512 * i;
             const int yy = e / 80, xx = e - yy * 80;
             const int gx = X0 + xx, gy = Y0 + yy;
-            v[i] = (e < 6400 && gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+            v[i] = (e < 6400 && gx >= 0 && gx < n && gy >= 0 && gy < n) ? pp.q[(size_t)gy * n + gx] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < 13; ++i) {
@@ -540,10 +573,10 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
             }
         }
     }
-    if (a.M) {
+    if (pp.M) {
         // P2M: wave w computes coefficients w, w + 8, ... of the 64 leaves
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = a.M + a.lv.off[a.L];
+        double2 *Ml = pp.M + a.lv.off[a.L];
         for (int k = wave; k < P; k += 8) {
             const double2 *__restrict__ Wk = a.p2m + k * 64;
             double mx = 0.0, my = 0.0;
@@ -559,7 +592,7 @@ __global__ __launch_bounds__(512) void k_leaf_grid(LeafArgs a)
     }
     if (!active) return;
     const double qs = -a.qscale * kInv2Pi;
-    double *ur = a.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
+    double *ur = pp.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
 #pragma unroll
     for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
 }
@@ -589,6 +622,8 @@ struct WideTile {
 template <int P, int K>
 __global__ __launch_bounds__(512) void k_leaf_wide(LeafArgs a)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
     using W = WideTile<K>;
     __shared__ double sq[W::SIZE];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -604,7 +639,7 @@ __global__ __launch_bounds__(512) void k_leaf_wide(LeafArgs a)
             const int e = base + tid + 512 * i;
             const int yy = e / PW, xx = e - yy * PW;
             const int gx = X0 + xx, gy = Y0 + yy;
-            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? pp.q[(size_t)gy * n + gx] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -642,9 +677,9 @@ __global__ __launch_bounds__(512) void k_leaf_wide(LeafArgs a)
             }
         }
     }
-    if (a.M) {
+    if (pp.M) {
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = a.M + a.lv.off[a.L];
+        double2 *Ml = pp.M + a.lv.off[a.L];
         for (int k = wave; k < P; k += 8) {
             const double2 *__restrict__ Wk = a.p2m + k * 64;
             double mx = 0.0, my = 0.0;
@@ -660,7 +695,7 @@ __global__ __launch_bounds__(512) void k_leaf_wide(LeafArgs a)
     }
     if (!active) return;
     const double qs = -a.qscale * kInv2Pi;
-    double *ur = a.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
+    double *ur = pp.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
 #pragma unroll
     for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
 }
@@ -689,6 +724,8 @@ template <int P>
 __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__restrict__ kt32,
                                                      const float *__restrict__ w32)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
     typedef float f4 __attribute__((ext_vector_type(4)));
     constexpr int MTP = (2 * P + 15) / 16;      // P2M row tiles
     __shared__ float sq[mq_idx(63, 9, 9) + 1];
@@ -705,7 +742,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
             const int e = tid + 256 * i;
             const int yy = e / 80, xx = e - yy * 80;
             const int gx = X0 + xx, gy = Y0 + yy;
-            v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)a.q[(size_t)gy * n + gx] : 0.0f;
+            v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)pp.q[(size_t)gy * n + gx] : 0.0f;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -762,7 +799,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
     f4 pm[MTP];
 #pragma unroll
     for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (a.M) {
+    if (pp.M) {
         const float *Bb = sq + bbase;
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
@@ -779,13 +816,13 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
     // D row m = 4 g + i of tile mt is target t = 16 mt + 4 g + i: ty = 2 mt + g / 2, tx = 4 (g & 1) + i
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+        double *ur = pp.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
     }
-    if (a.M) {
+    if (pp.M) {
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = a.M + a.lv.off[a.L];
+        double2 *Ml = pp.M + a.lv.off[a.L];
         // D rows 16 mt + 4 g + {0,1} and {2,3} are (Re, Im) of coefficients 8 mt + 2 g + {0, 1}
 #pragma unroll
         for (int mt = 0; mt < MTP; ++mt)
@@ -814,6 +851,8 @@ template <int P, int K>
 __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const float *__restrict__ kt32,
                                                           const float *__restrict__ w32)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
     typedef float f4 __attribute__((ext_vector_type(4)));
     constexpr int TW = 8 + 2 * K, PS = TW * 72, KC = 8 * K + 7, KS = 2 * KC + 1, TS = KS;
     constexpr int MTP = (2 * P + 15) / 16;      // P2M row tiles
@@ -834,7 +873,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
             const int e = base + tid + 256 * i;
             const int yy = e / PW, xx = e - yy * PW;
             const int gx = X0 + xx, gy = Y0 + yy;
-            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)a.q[(size_t)gy * n + gx] : 0.0f;
+            v[i] = (e < NE && gx >= 0 && gx < n && gy >= 0 && gy < n) ? (float)pp.q[(size_t)gy * n + gx] : 0.0f;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -885,7 +924,7 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
     f4 pm[MTP];
 #pragma unroll
     for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (a.M) {
+    if (pp.M) {
         const float *Bb = sq + bbase;
 #pragma unroll 4
         for (int kk = 0; kk < 16; ++kk) {
@@ -902,13 +941,13 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
     // D row m = 4 g + i of tile mt is target t = 16 mt + 4 g + i: ty = 2 mt + g / 2, tx = 4 (g & 1) + i
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+        double *ur = pp.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
     }
-    if (a.M) {
+    if (pp.M) {
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = a.M + a.lv.off[a.L];
+        double2 *Ml = pp.M + a.lv.off[a.L];
         // D rows 16 mt + 4 g + {0,1} and {2,3} are (Re, Im) of coefficients 8 mt + 2 g + {0, 1}
 #pragma unroll
         for (int mt = 0; mt < MTP; ++mt)
@@ -967,6 +1006,8 @@ template <int P, typename H>
 __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__restrict__ kt16,
                                                      const H *__restrict__ w16)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
     using S = Split16<H>;
     typedef typename S::v8 h8;
     typedef f4_t f4;
@@ -986,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
         const int e = tid + 256 * i;
         const int yy = e / 80, xx = e - yy * 80;
         const int gx = X0 + xx, gy = Y0 + yy;
-        v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? a.q[(size_t)gy * n + gx] : 0.0;
+        v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? pp.q[(size_t)gy * n + gx] : 0.0;
         mx = fmax(mx, fabs(v[i]));
     }
     // kernel table: 2 x 8 copies of 31 rows x 40 halves, copied in 16-byte units
@@ -1058,7 +1099,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     f4 pm[MTP];
 #pragma unroll
     for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (a.M) {
+    if (pp.M) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             const h8 bh = *(const h8 *)&sqh[bbase + 32 * ks];
@@ -1080,13 +1121,13 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     const double qs = -a.qscale * iscale * kInv2Pi;
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-        double *ur = a.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+        double *ur = pp.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
 #pragma unroll
         for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
     }
-    if (a.M) {
+    if (pp.M) {
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = a.M + a.lv.off[a.L];
+        double2 *Ml = pp.M + a.lv.off[a.L];
         const double ms = a.qscale * iscale;
 #pragma unroll
         for (int mt = 0; mt < MTP; ++mt)
@@ -1149,6 +1190,10 @@ template <int P>
 __global__ __launch_bounds__(512) void k_ring_targets(LeafArgs a, double *__restrict__ phi,
                                                       double2 *__restrict__ bh)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
+    phi += blockIdx.z * a.rh.sr;
+    if (bh) bh += blockIdx.z * a.rh.sb;
     __shared__ double val[8];
     const int kq = blockIdx.x, v = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = a.n, nl = a.nl, m = n >> 1;
@@ -1165,7 +1210,7 @@ __global__ __launch_bounds__(512) void k_ring_targets(LeafArgs a, double *__rest
             if (qx < 0 || qy < 0 || qx >= nl || qy >= nl) continue;
             const int gx = qx * 8 + ia, gy = qy * 8 + jb;
             const int dx = abs(Ix - (gx + 1)), dy = abs(Iy - (gy + 1));
-            near = fma(a.q[(size_t)gy * n + gx], a.rtab[dy * a.rs + dx], near);
+            near = fma(pp.q[(size_t)gy * n + gx], a.rtab[dy * a.rs + dx], near);
         }
     }
     near = wave_sum(near);
@@ -1173,7 +1218,7 @@ __global__ __launch_bounds__(512) void k_ring_targets(LeafArgs a, double *__rest
         double far = 0.0;
         if (a.far) {
             const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)ly * nl + lx;
-            const double2 *Ll = a.Lt + a.lv.off[a.L];
+            const double2 *Ll = pp.Lt + a.lv.off[a.L];
             double2 Lc[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) Lc[k] = Ll[k * ncell + cell];
@@ -1224,8 +1269,13 @@ __global__ __launch_bounds__(256) void k_p2m_ring(const int4 *__restrict__ cells
                                                   double *__restrict__ rq,
                                                   double *__restrict__ sig_out,
                                                   double2 *__restrict__ M, LevelInfo lv, int n,
-                                                  int L)
+                                                  int L, RhsSet rh)
 {
+    if (!rhs_active(rh, blockIdx.z)) return;
+    sh += blockIdx.z * rh.sb;
+    rq += blockIdx.z * rh.sr;
+    if (sig_out) sig_out += blockIdx.z * rh.sr;
+    M += blockIdx.z * rh.se;
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (w >= ncells) return;
     const int4 it = cells[w];
@@ -1293,11 +1343,15 @@ __global__ __launch_bounds__(256) void k_m2l_ring(const int4 *__restrict__ items
                                                   const double2 *__restrict__ hank,
                                                   const int4 *__restrict__ offs,
                                                   const double *__restrict__ a_n,
-                                                  const double *__restrict__ b_k, int nlist)
+                                                  const double *__restrict__ b_k, int nlist,
+                                                  RhsSet rh)
 {
     // one item per block; wave w takes list entries w, w+4, ... and the four
     // partial sums are added in LDS in a fixed order
     __shared__ double2 red[3][P][64];
+    if (!rhs_active(rh, blockIdx.z)) return;
+    M += blockIdx.z * rh.se;
+    Lm += blockIdx.z * rh.se;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int4 it = items[blockIdx.x];   // (level, side | depth << 2, start, end)
     const int l = it.x, side = it.y & 3, d = it.y >> 2, nc = 1 << l;
@@ -1422,6 +1476,10 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
                                                  const double2 *__restrict__ B, int chain,
                                                  const double2 *__restrict__ Lvol)
 {
+    const LeafPtrs pp = rhs_ptrs(a);
+    if (!pp.on) return;
+    if (Lm) Lm += blockIdx.z * a.rh.se;
+    if (Lvol) Lvol += blockIdx.z * a.rh.se;
     __shared__ double2 sB[4 * P * P];
     __shared__ double2 sm2l[P * 84];
     __shared__ double2 buf0[P * 64], buf1[P * 64];
@@ -1442,7 +1500,7 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
     if (chain) {
         const int r = a.L - 3, nr = 1 << r;
         const double2 *top =
-            chain == 2 ? nullptr : a.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x;
+            chain == 2 ? nullptr : pp.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x;
         sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1,
                             top, (int64_t)nr * nr, nullptr, sanc);
         if (Lvol) {
@@ -1455,12 +1513,12 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
     } else {
         constexpr int R = rounds256(P * 64);
         double2 v[R];
-        if (a.Lt) fetch(v, P * cnt, [&](int t) { return leaf_coef(a.Lt, t); });
+        if (pp.Lt) fetch(v, P * cnt, [&](int t) { return leaf_coef(pp.Lt, t); });
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int t = threadIdx.x + 256 * r;
             if (t < P * cnt) {
-                double2 y = a.Lt ? v[r] : make_double2(0.0, 0.0);
+                double2 y = pp.Lt ? v[r] : make_double2(0.0, 0.0);
                 if (Lvol) {
                     y.x += vv[r].x;
                     y.y += vv[r].y;
@@ -1496,7 +1554,7 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int yy = y0 + 4 * (2 * j + cls);
-                a.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far[j] * kInv2Pi;
+                pp.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far[j] * kInv2Pi;
             }
         }
         return;
@@ -1514,7 +1572,7 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
             far = fma(c.x, pk.x, fma(-c.y, pk.y, far));
             pk = cmul(pk, tau);
         }
-        a.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far * kInv2Pi;
+        pp.u[(size_t)(ly0 * 8 + yy) * n + lx0 * 8 + xx] += -far * kInv2Pi;
     }
 }
 
@@ -1523,8 +1581,11 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
 __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
                                                     const double *__restrict__ rq,
                                                     const double *__restrict__ rtab, int n, int nl,
-                                                    int K, int kxp, int rs)
+                                                    int K, int kxp, int rs, RhsSet rh)
 {
+    if (!rhs_active(rh, blockIdx.z)) return;
+    u += blockIdx.z * rh.sv;
+    rq += blockIdx.z * rh.sr;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int B = 8 * (K + 1);
     int gx, gy;
@@ -1553,15 +1614,17 @@ __global__ __launch_bounds__(256) void k_pass2_near(double *__restrict__ u,
 }
 
 // ---------------------------------------------------------------------------
-// host drivers
+// host drivers.  Every launch covers the nr right-hand sides of rh in its
+// third grid dimension.
 // ---------------------------------------------------------------------------
 template <int P>
-static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, hipStream_t s)
+static void run_m2m_from(fmm_plan *pl, double2 *M, int l_in, const RhsSet &rh, int nr, hipStream_t s)
 {
     // each launch lifts the multipoles three levels, from l_in down to 2
     for (int l = l_in; l > 2; l -= 3) {
         const int nc = 1 << l, tw = std::min(nc, 8), nt = nc / tw;
-        hipLaunchKernelGGL(k_m2m_up<P>, dim3(nt * nt), dim3(256), 0, s, M, pl->tab.m2m, pl->lv, l);
+        hipLaunchKernelGGL(k_m2m_up<P>, dim3(nt * nt, 1, nr), dim3(256), 0, s, M, pl->tab.m2m, pl->lv,
+                           l, rh);
     }
 }
 
@@ -1586,7 +1649,8 @@ static std::vector<DownChunk> down_chunks(int L)
 
 template <int P>
 static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
-                       const M2LItem *items, int nitems, hipStream_t s, bool timed)
+                       const M2LItem *items, int nitems, const RhsSet &rh, int nr, hipStream_t s,
+                       bool timed)
 {
     const int rw = 16 + 4 * pl->K;
     const size_t shm = (size_t)P * rw * rw * sizeof(double2);
@@ -1595,25 +1659,26 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
         // reduced-precision grid plans translate in FP32; point clouds take only
         // their near field in FP32 (Sec. 7.1) and keep M2L in FP64
         if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
-            hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems), dim3(768), shm / 2, s, items, M, Lm,
-                               pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
-                               pl->tab.m2l_b, pl->nlist, 2 * pl->K);
+            hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(768), shm / 2, s, items, M,
+                               Lm, pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
+                               pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
         else
-            hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems), dim3(768), shm, s, items, M, Lm,
-                               pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
-                               pl->tab.m2l_b, pl->nlist, 2 * pl->K);
+            hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems, 1, nr), dim3(768), shm, s, items, M,
+                               Lm, pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
+                               pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (const auto &c : down_chunks(pl->L))
-        hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, Lm, Lt, pl->tab.l2l,
-                           pl->lv, c.r, c.m, c.root);
+        hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r), 1, nr), dim3(256), 0, s, Lm, Lt,
+                           pl->tab.l2l, pl->lv, c.r, c.m, c.root, rh);
     return FMM_OK;
 }
 
 static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *u,
-                          const double2 *Lt, bool far)
+                          const double2 *Lt, bool far, const RhsSet &rh)
 {
     LeafArgs a;
+    a.rh = rh;
     a.q = q;
     a.qscale = qscale;
     a.u = u;
@@ -1659,16 +1724,17 @@ static void launch_leaf_wide_mfma32(fmm_plan *pl, dim3 gl, const LeafArgs &a, hi
 
 template <int P>
 static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, double *u,
-                             double *ring_out, bool defer_l2p, hipStream_t s)
+                             double *ring_out, bool defer_l2p, const RhsSet &rh, int nr,
+                             hipStream_t s)
 {
     const int nl = pl->nl;
     const bool far = pl->L >= 2;
     const bool fp32 = pl->prec == FMM_FP32;
-    LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far);
+    LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far, rh);
     if (far) a.M = pl->ws.M;
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
-        dim3 gl((nl + 7) / 8, (nl + 7) / 8);
+        dim3 gl((nl + 7) / 8, (nl + 7) / 8, nr);
         if (pl->prec == FMM_SPLIT_FP16)
             hipLaunchKernelGGL((k_leaf_mfma16<P, _Float16>), gl, dim3(256), 0, s, a, pl->tab.ktab16,
                                pl->tab.p2m16);
@@ -1688,20 +1754,21 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     if (far) {
         {
             StageTimer t(pl, FMM_STAGE_M2M, s);
-            run_m2m_from<P>(pl, pl->ws.M, pl->L, s);
+            run_m2m_from<P>(pl, pl->ws.M, pl->L, rh, nr, s);
         }
-        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s, true);
+        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, rh, nr,
+                       s, true);
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
-        hipLaunchKernelGGL(k_ring_targets<P>, dim3(pl->n / 2), dim3(512), 0, s, a, ring_out,
+        hipLaunchKernelGGL(k_ring_targets<P>, dim3(pl->n / 2, 1, nr), dim3(512), 0, s, a, ring_out,
                            pl->bem ? pl->bhat : nullptr);
     }
     if (far && !defer_l2p) {
         StageTimer t(pl, FMM_STAGE_L2L, s);
         const int tw = std::min(nl, 8);
-        LeafArgs b = leaf_args(pl, nullptr, 1.0, u, nullptr, far);
-        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, b, nullptr,
+        LeafArgs b = leaf_args(pl, nullptr, 1.0, u, nullptr, far, rh);
+        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw, nr), dim3(256), 0, s, b, nullptr,
                            nullptr, 0, pl->ws.Lt);
     }
     FMM_HIP(pl, hipGetLastError());
@@ -1710,7 +1777,7 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
 
 template <int P>
 static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, double *sigma_out,
-                                  hipStream_t s)
+                                  const RhsSet &rh, int nr, hipStream_t s)
 {
     const int L = pl->L, nl = pl->nl;
     const bool far = L >= 2;
@@ -1718,14 +1785,14 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, dou
     if (far) {
         // upward: ring charges -> every boundary cell of levels 2..L
         const int tw = std::min(nl, 8);
-        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((pl->n_ring_p2m + 3) / 4), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_p2m_ring<P>, dim3((pl->n_ring_p2m + 3) / 4, 1, nr), dim3(256), 0, s,
                            pl->ring_p2m_cells, pl->n_ring_p2m, pl->shat, pl->h, pl->ring_q,
-                           sigma_out, pl->ws.M2, pl->lv, (int)pl->n, L);
+                           sigma_out, pl->ws.M2, pl->lv, (int)pl->n, L, rh);
         // M2L from boundary cells into the (2K+2)-cell band of every level
-        hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_m2l_ring<P>, dim3(pl->n_ring_cells, 1, nr), dim3(256), 0, s,
                            pl->ring_cells, pl->n_ring_cells, pl->ws.M2, pl->ws.Lm2, pl->lv,
                            pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
-                           pl->nlist);
+                           pl->nlist, rh);
         // downward: levels 2..L-3 by k_down, the last three inside the far-field
         // kernel, whose blocks build their level-(L-3) root from the ancestors
         // when L - 3 <= 5 (then no k_down launch at all)
@@ -1734,30 +1801,32 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, dou
         const int chain_mode = !chain ? 0 : (last <= kMaxAncestorLevel ? 2 : 1);
         if (chain_mode != 2)
             for (const auto &c : down_chunks(last))
-                hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r)), dim3(256), 0, s, pl->ws.Lm2,
-                                   pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.root);
-        const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far);
-        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw), dim3(256), 0, s, a, pl->ws.Lm2,
+                hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r), 1, nr), dim3(256), 0, s,
+                                   pl->ws.Lm2, pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.root,
+                                   rh);
+        const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far, rh);
+        hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw, nr), dim3(256), 0, s, a, pl->ws.Lm2,
                            pl->tab.l2l, chain_mode, with_volume ? pl->ws.Lt : nullptr);
     }
     const int n = (int)pl->n, B = 8 * (pl->K + 1);
     const int64_t nband = n <= 2 * B ? (int64_t)n * n : (int64_t)4 * B * n - 4 * B * B;
-    hipLaunchKernelGGL(k_pass2_near, dim3((unsigned)((nband + 255) / 256)), dim3(256), 0, s, u,
-                       pl->ring_q, pl->tab.rtab, n, nl, pl->K, near_kx_packed(pl), 8 * pl->K + 9);
+    hipLaunchKernelGGL(k_pass2_near, dim3((unsigned)((nband + 255) / 256), 1, nr), dim3(256), 0, s,
+                       u, pl->ring_q, pl->tab.rtab, n, nl, pl->K, near_kx_packed(pl), 8 * pl->K + 9,
+                       rh);
     FMM_HIP(pl, hipGetLastError());
     return FMM_OK;
 }
 
 int grid_volume_fmm(fmm_plan *pl, const double *q, double qscale, double *u, double *ring_out,
-                    bool defer_l2p, hipStream_t s)
+                    bool defer_l2p, const RhsSet &rh, int nr, hipStream_t s)
 {
-    FMM_DISPATCH_P(pl->p, grid_volume_fmm_p, pl, q, qscale, u, ring_out, defer_l2p, s);
+    FMM_DISPATCH_P(pl->p, grid_volume_fmm_p, pl, q, qscale, u, ring_out, defer_l2p, rh, nr, s);
 }
 
 int grid_ring_source_fmm(fmm_plan *pl, double *u, bool with_volume, double *sigma_out,
-                         hipStream_t s)
+                         const RhsSet &rh, int nr, hipStream_t s)
 {
-    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, sigma_out, s);
+    FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, sigma_out, rh, nr, s);
 }
 
 // level-generic stages reused by point-cloud plans
@@ -1765,15 +1834,15 @@ template <int P>
 static int points_up_p(fmm_plan *pl, hipStream_t s)
 {
     StageTimer t(pl, FMM_STAGE_M2M, s);
-    run_m2m_from<P>(pl, pl->ws.M, pl->L, s);
+    run_m2m_from<P>(pl, pl->ws.M, pl->L, RhsSet{}, 1, s);
     return FMM_OK;
 }
 
 template <int P>
 static int points_down_p(fmm_plan *pl, hipStream_t s)
 {
-    return run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, s,
-                          true);
+    return run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items,
+                          RhsSet{}, 1, s, true);
 }
 
 int points_upward_rest(fmm_plan *pl, hipStream_t s)

@@ -35,6 +35,9 @@ constexpr double kThetaMin = 0.3;
 constexpr int kMaxK = 4;
 constexpr int kThetaPMax = 12;   // largest p built for theta < 1/sqrt(2)
 constexpr int64_t kM2LMaxLds = 160 * 1024;
+// right-hand sides one launch sequence takes at most (larger counts run in
+// chunks of this many; each needs its own expansion workspace)
+constexpr int kMaxRhsChunk = 16;
 
 // Near radius in leaves of a MAC theta on the uniform tree: two cells of one
 // level, radius r = w/sqrt2 each, are well separated when 2r < theta |d| w,
@@ -47,6 +50,21 @@ inline int near_radius(double theta)
     int k = 1;
     while ((double)((k + 1) * (k + 1)) <= lim) ++k;
     return k;
+}
+
+// The right-hand sides of one launch, selected by blockIdx.z: the grid
+// vectors of right-hand side r start r*sv doubles on, its expansions r*se
+// double2, its ring arrays (4n) r*sr doubles and its boundary-solve products
+// (3n) r*sb double2.  act (device, may be null) holds a nonzero flag for each
+// right-hand side still to be computed; the blocks of the others return at
+// once, so a captured launch sequence serves any subset of them.
+struct RhsSet {
+    int64_t sv = 0, se = 0, sr = 0, sb = 0;
+    const int *act = nullptr;
+};
+__device__ __forceinline__ bool rhs_active(const RhsSet &rh, int r)
+{
+    return !rh.act || rh.act[r] != 0;
 }
 
 // Work item of the all-levels M2L launch: a tile of target cells at a level.
@@ -132,6 +150,10 @@ struct fmm_plan {
     double x0 = 0.0, y0 = 0.0, side = 1.0;  // tree root square
     fmmprec::LevelInfo lv{};
     int64_t exp_elems = 0;                  // double2 elements per expansion buffer
+    // right-hand sides the workspace holds side by side (expansions, ring
+    // potential, boundary-solve products, ring charges); one per plan at
+    // setup, more when a call stacks several (ensure_rhs)
+    int rhs_cap = 0;
 
     fmmprec::FmmTables tab{};
     fmmprec::Workspace ws{};
@@ -184,6 +206,22 @@ struct fmm_plan {
     hipEvent_t bevent = nullptr;
     std::vector<hipGraphExec_t> step_exec;
 
+    // group solves (many right-hand sides of this plan's size at once,
+    // krylov.hip): capacity g_cap instances with restart g_m
+    int g_cap = 0, g_m = 0;
+    int64_t g_vs = 0;             // doubles per instance in g_basis: V (m+1) then Z (m)
+    double *g_basis = nullptr;
+    double *g_b = nullptr, *g_x = nullptr, *g_w = nullptr;   // g_cap grids each
+    double *g_part = nullptr, *g_dscal = nullptr;
+    void *g_state = nullptr;      // per-instance solver state (device)
+    int *g_flags = nullptr;       // [run | fin | status] per instance (device)
+    int *g_host = nullptr;        // pinned mirror: run, then status per instance
+    std::vector<hipGraphExec_t> g_step_exec;   // step j of a group solve
+    hipGraphExec_t g_end_exec = nullptr;      // end of a cycle
+    int g_graph_nr = 0;           // instance count, maxit and tol the graphs were captured for
+    int g_graph_maxit = 0;        // (the restart length is fixed by g_m)
+    double g_graph_tol = 0.0;
+
     // stage timing (fmm_profile)
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;          // created on first enable
@@ -230,17 +268,25 @@ struct StageTimer {
 };
 
 // ---- FMM stages (fmm_grid.hip / fmm_points.hip) ----
+// Every stage runs for the nr right-hand sides of rh at once (blockIdx.z):
+// q, u (and sigma_out) hold nr arrays rh.sv (rh.sr) apart, and the plan's
+// workspace must hold nr of them (ensure_rhs).
 // q -> u for grid plans: u = -(1/2pi) [ qscale * near(q) + far ], optionally
 // also the ring potential.  With defer_l2p the far field is left in the
 // leaf-level local expansions (plan->ws.Lt) for grid_ring_source_fmm to add.
 int grid_volume_fmm(fmm_plan *plan, const double *q, double qscale, double *u,
-                    double *ring_out, bool defer_l2p, hipStream_t s);
+                    double *ring_out, bool defer_l2p, const RhsSet &rh, int nr, hipStream_t s);
 // second pass: the boundary density from the boundary solve's products
 // (plan->shat; also written to plan->ring_q as charges h sigma and to
 // sigma_out when given), add its potential to u (and the deferred far field
 // of the volume pass when with_volume)
 int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, double *sigma_out,
-                         hipStream_t s);
+                         const RhsSet &rh, int nr, hipStream_t s);
+// workspace for nr right-hand sides (grows only; drops captured graphs that
+// hold the old addresses)
+int ensure_rhs(fmm_plan *plan, int nr);
+// the right-hand-side set of nr stacked arrays of length sv on this plan
+RhsSet plan_rhs(const fmm_plan *plan, int64_t sv, const int *act);
 int m2l_kernel_setup(fmm_plan *plan);
 int points_fmm(fmm_plan *plan, const double *q, double *u, hipStream_t s);
 // Gaussian-bump source model and its parameter gradients (adjoint.hip)
@@ -257,10 +303,10 @@ int points_setup(fmm_plan *plan, const double *dx, const double *dy, hipStream_t
 
 // ---- boundary correction (bem.hip) ----
 int bem_setup(fmm_plan *plan, hipStream_t s);
-int bem_apply(fmm_plan *plan, double *sigma_out, hipStream_t s);
+int bem_apply(fmm_plan *plan, double *sigma_out, const RhsSet &rh, int nr, hipStream_t s);
 
 // ---- Krylov (krylov.hip) ----
-int stencil_apply(fmm_plan *plan, const double *v, double *w, hipStream_t s);
+int stencil_apply(fmm_plan *plan, const double *v, double *w, int nr, hipStream_t s);
 int gmres_solve(fmm_plan *plan, const double *f, const double *g, double *u,
                 const gmres_params *prm, gmres_result *res, hipStream_t s,
                 const double *ax = nullptr, const double *ay = nullptr);
@@ -268,11 +314,20 @@ int stencil_var_apply(fmm_plan *plan, const double *ax, const double *ay, const 
                       double *w, hipStream_t s);
 int gmres_solve_batch(fmm_plan *const *plans, int count, const double *const *f, double *const *u,
                       const gmres_params *prm, gmres_result *res, double *elapsed_ms, bool graphs,
-                      hipStream_t caller);
+                      bool separate, hipStream_t caller);
 int tune_vector_blocks(fmm_plan *plan, hipStream_t s, int *chosen);
 void drop_step_graphs(fmm_plan *plan);
 int precond_apply_one(fmm_plan *plan, const double *r, double *z, double *phi_ring,
                       double *sigma, hipStream_t s);
+// z = P^{-1} r for nr stacked right-hand sides (N apart), those of act only
+int precond_apply_rhs(fmm_plan *plan, const double *r, double *z, int nr, int64_t stride,
+                      const int *act, hipStream_t s);
+// nr stacked solves on one plan (f, u: nr grids of n*n), every launch of a
+// step covering all instances (device-side Givens rotations and convergence
+// flags); graphs: replay captured steps
+int gmres_solve_group(fmm_plan *plan, int nr, const double *const *f, double *const *u,
+                      const gmres_params *prm, gmres_result *res, bool graphs, hipStream_t s);
+void release_group(fmm_plan *plan);
 
 // Boundary density at node k of side s from the products of the boundary
 // solve: sh = [mode 0: even | odd][mode 2: even | odd][mode 1: even | odd]

@@ -1,9 +1,18 @@
-"""Batched uneven solves (precond_gmres_solve_batch) and the autotuner.
+"""Batched and multi-right-hand-side solves, and the autotuner.
 
-  * a mixed-size batch gives, per instance, bitwise the solution of the
-    same plan's single solve (same kernels, fixed-order reductions), with
-    and without HIP-graph replay of the Arnoldi steps, and again on a
-    second and third batch (graphs replayed, eager work in between);
+Grouped batches (the default of precond_gmres_solve_batch) and
+precond_gmres_solve_multi run the instances of one problem size as a group:
+every launch covers the group, the Givens rotations and convergence tests
+run on the device.  So:
+  * each instance of a mixed-size batch equals its plan's single solve: the
+    same iteration count, the solution within 1e-10 relative (the device's
+    rotations round differently from the host's); repeated batches, with and
+    without HIP graphs and with eager work in between, give the same
+    solutions bit for bit;
+  * the separate layout (FMM_BATCH_SEPARATE: one solve per plan, host
+    rotations) gives, per instance, the single solve bit for bit;
+  * a zero right-hand side gives u = 0 and an instance that runs out of
+    iterations reports not converged while the others converge;
   * one instance against the oracle's solve;
   * the tuned vector-kernel block count is one of the candidates and keeps
     solutions within rounding of the untuned ones;
@@ -39,7 +48,11 @@ def host(t):
     return t.cpu().numpy()
 
 
-SIZES = (64, 128, 32, 256, 64, 128)
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+SIZES = (64, 128, 32, 256, 64, 128, 64)
 
 
 def _setup(sizes, p=10):
@@ -49,27 +62,42 @@ def _setup(sizes, p=10):
     return plans, fs
 
 
-def test_batch_equals_single_solves_and_replays():
+def _single(plans, fs):
+    import torch
+    out = []
+    for pl, f in zip(plans, fs):
+        u = torch.zeros_like(f)
+        info = pl.solve(f, u)
+        assert info["converged"]
+        out.append((host(u), info["iters"]))
+    return out
+
+
+def test_grouped_batch_equals_single_solves_and_replays():
     import torch
 
     import paper_1308_3339_amd as fp
-    say("case batch vs single, sizes", SIZES)
+    say("case grouped batch vs single, sizes", SIZES)
     plans, fs = _setup(SIZES)
     try:
-        single = []
-        for pl, f in zip(plans, fs):
-            u = torch.zeros_like(f)
-            info = pl.solve(f, u)
-            assert info["converged"]
-            single.append((host(u), info["iters"]))
+        single = _single(plans, fs)
+        first = None
         for graphs in (False, True, True, True):
             us = [torch.zeros_like(f) for f in fs]
             out = fp.precond_gmres_solve_batch(plans, fs, us, graphs=graphs)
             assert out["status"] == fp.FMM_OK
-            for i, (u, r) in enumerate(zip(us, out["results"])):
-                assert r["iters"] == single[i][1]
-                assert np.array_equal(host(u), single[i][0]), (graphs, i)
+            sols = [host(u) for u in us]
+            for i, (u, r) in enumerate(zip(sols, out["results"])):
+                assert r["iters"] == single[i][1], (graphs, i)
+                assert rel(u, single[i][0]) <= 1e-10, (graphs, i)
+                assert r["true_rel_res"] <= 1e-8
+            if first is None:
+                first = sols
+            else:
+                for i in range(len(sols)):
+                    assert np.array_equal(sols[i], first[i]), (graphs, i)
             say("  graphs=%s iters" % graphs, [r["iters"] for r in out["results"]],
+                "max rel diff vs single %.2e" % max(rel(u, single[i][0]) for i, u in enumerate(sols)),
                 "elapsed ms", [round(e, 2) for e in out["elapsed_ms"]])
             # eager work on the same plans between replays
             w = torch.empty_like(fs[0])
@@ -79,12 +107,97 @@ def test_batch_equals_single_solves_and_replays():
             pl.close()
 
 
+def test_separate_batch_equals_single_solves_bitwise():
+    import torch
+
+    import paper_1308_3339_amd as fp
+    say("case separate batch vs single")
+    plans, fs = _setup(SIZES[:4])
+    try:
+        single = _single(plans, fs)
+        for graphs in (False, True, True):
+            us = [torch.zeros_like(f) for f in fs]
+            out = fp.precond_gmres_solve_batch(plans, fs, us, graphs=graphs, separate=True)
+            assert out["status"] == fp.FMM_OK
+            for i, (u, r) in enumerate(zip(us, out["results"])):
+                assert r["iters"] == single[i][1]
+                assert np.array_equal(host(u), single[i][0]), (graphs, i)
+    finally:
+        for pl in plans:
+            pl.close()
+
+
+def test_multi_rhs_solve_matches_single_solves():
+    import torch
+
+    import paper_1308_3339_amd as fp
+    n, nr = 128, 5
+    say("case solve_multi n=128 nrhs=5")
+    F = np.stack([inputs.gaussian_bumps(n, 16, seed=940 + k) for k in range(nr)])
+    with fp.fmm_setup(n=n, p=10) as plan:
+        single = []
+        for k in range(nr):
+            u = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+            info = plan.solve(dev(F[k]), u)
+            single.append((host(u), info["iters"]))
+        for graphs in (False, True, True):
+            U = torch.zeros(nr * n * n, dtype=torch.float64, device="cuda")
+            out = plan.solve_multi(dev(F.reshape(-1)), U, nr, graphs=graphs)
+            assert out["status"] == fp.FMM_OK
+            Ug = host(U).reshape(nr, -1)
+            for k in range(nr):
+                assert out["results"][k]["iters"] == single[k][1]
+                assert rel(Ug[k], single[k][0]) <= 1e-10
+        say("  iters", [r["iters"] for r in out["results"]])
+
+
+def test_multi_rhs_apply_and_stencil_equal_single_calls():
+    import torch
+    n, nr = 64, 4
+    say("case precond_apply / fmm_apply / stencil nrhs=4")
+    import paper_1308_3339_amd as fp
+    R = np.stack([inputs.random_charges(n * n, seed=950 + k) for k in range(nr)])
+    with fp.fmm_setup(n=n, p=10, bem=1) as plan:
+        for name in ("precond_apply", "apply", "stencil_apply"):
+            Z = torch.empty(nr * n * n, dtype=torch.float64, device="cuda")
+            getattr(plan, name)(dev(R.reshape(-1)), Z, nrhs=nr)
+            Zg = host(Z).reshape(nr, -1)
+            for k in range(nr):
+                z = torch.empty(n * n, dtype=torch.float64, device="cuda")
+                getattr(plan, name)(dev(R[k]), z)
+                assert np.array_equal(host(z), Zg[k]), (name, k)
+
+
+def test_group_zero_rhs_and_iteration_limit():
+    import torch
+
+    import paper_1308_3339_amd as fp
+    n = 64
+    say("case group: zero right-hand side, maxit")
+    F = np.stack([inputs.gaussian_bumps(n, 16, seed=960), np.zeros(n * n),
+                  inputs.gaussian_bumps(n, 16, seed=961)])
+    with fp.fmm_setup(n=n, p=10) as plan:
+        U = dev(np.ones(3 * n * n))
+        out = plan.solve_multi(dev(F.reshape(-1)), U, 3)
+        Ug = host(U).reshape(3, -1)
+        assert out["status"] == fp.FMM_OK
+        assert np.all(Ug[1] == 0.0) and out["results"][1]["iters"] == 0
+        for k in (0, 2):
+            res = np.linalg.norm(F[k] - o.stencil(n, Ug[k])) / np.linalg.norm(F[k])
+            assert res <= 1e-8
+        U = torch.zeros(3 * n * n, dtype=torch.float64, device="cuda")
+        out = plan.solve_multi(dev(F.reshape(-1)), U, 3, maxit=3)
+        assert out["status"] == fp.FMM_NOT_CONVERGED
+        assert all(r["iters"] <= 3 for r in out["results"])
+        assert not out["results"][0]["converged"]
+
+
 def test_batch_instance_matches_oracle():
     import torch
 
     import paper_1308_3339_amd as fp
     say("case batch vs oracle")
-    plans, fs = _setup((32, 64))
+    plans, fs = _setup((32, 64, 64))
     try:
         us = [torch.zeros_like(f) for f in fs]
         fp.precond_gmres_solve_batch(plans, fs, us)
