@@ -131,6 +131,11 @@ static int build_tables(fmm_plan *pl)
     if (K == 1 && pl->nlist != 27) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
     std::vector<int4> offs;
     for (int w = 0; w < 4; ++w) offs.insert(offs.end(), cls[w].begin(), cls[w].end());
+    // the generators again in list order, [class][list entry][2p - 1], so
+    // that M2L finds an entry's generators without first loading its offset
+    std::vector<double2> hankl(offs.size() * (size_t)nh);
+    for (size_t e = 0; e < offs.size(); ++e)
+        for (int m = 0; m < nh; ++m) hankl[e * nh + m] = hank[(size_t)offs[e].z * nh + m];
     std::vector<double> an(p), bk(p);
     for (int k = 0; k < p; ++k) {
         an[k] = ((k & 1) ? -1.0 : 1.0) / factorial(k);
@@ -222,13 +227,15 @@ static int build_tables(fmm_plan *pl)
                 splitb16(kt[(size_t)r * 31 + j + c], ktb16[((size_t)c * 31 + r) * 40 + j],
                          ktb16[((size_t)(8 + c) * 31 + r) * 40 + j]);
             }
-    std::vector<float2> hank32(hank.size());
+    std::vector<float2> hank32(hank.size()), hankl32(hankl.size());
     for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
+    for (size_t i = 0; i < hankl.size(); ++i) hankl32[i] = float2{(float)hankl[i].x, (float)hankl[i].y};
     int st;
     if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) ||
         (st = upload(pl, &pl->tab.ktab16, kt16)) || (st = upload(pl, &pl->tab.p2m16, p2m16)) ||
         (st = upload(pl, &pl->tab.ktabb16, ktb16)) || (st = upload(pl, &pl->tab.p2mb16, p2mb16)) ||
-        (st = upload(pl, &pl->tab.hank32, hank32)) ||
+        (st = upload(pl, &pl->tab.hank32, hank32)) || (st = upload(pl, &pl->tab.hankl, hankl)) ||
+        (st = upload(pl, &pl->tab.hankl32, hankl32)) ||
         (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
         (st = upload(pl, &pl->tab.hank, hank)) ||
         (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
@@ -366,7 +373,7 @@ int ensure_rhs(fmm_plan *pl, int nr)
 static void release(fmm_plan *pl)
 {
     void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.ktabb16,
-                    pl->tab.p2mb16, pl->tab.hank32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+                    pl->tab.p2mb16, pl->tab.hank32, pl->tab.hankl, pl->tab.hankl32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
                     pl->ring_cells, pl->ring_p2m_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,

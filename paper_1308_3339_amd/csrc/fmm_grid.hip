@@ -189,11 +189,15 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 // one list shape, so the offset and its Hankel generators are wave-uniform)
 // and third w>>2 of the class's nlist-entry list (27 with the list rule, more
 // with a MAC theta).  Sources (the tile plus a halo of 2K cells, 20x20 for
-// K = 1) are staged once in LDS, split by parity so that the per-offset LDS
-// reads of a wave are consecutive; the three thirds are summed in LDS in a
-// fixed order.  R is the arithmetic type of the translation (double, or
+// K = 1) are staged once in LDS, split by parity, each parity sub-grid
+// column-major: a 16-byte read of 8 columns x 2 rows of a wave's cells then
+// puts its 16 lanes on 16 distinct 16-byte bank groups (column stride
+// RH = 10, even, and rows one apart); the three thirds are summed in LDS in
+// a fixed order.  R is the arithmetic type of the translation (double, or
 // float for the FP32 variant; the level-scaled expansions and generators
 // stay far inside FP32 range for p <= 20), inputs and outputs are FP64.
+// hank holds the generators in list order ([class][entry][2P-1]), so the
+// address of an entry's generators does not wait for its offset to load.
 // ---------------------------------------------------------------------------
 template <int P, typename R>
 __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                 C c;
                 c.x = (R)(v[i].x * bk);
                 c.y = (R)(v[i].y * bk);
-                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1)] = c;
+                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sx >> 1) * RH + (sy >> 1)] = c;
             }
         }
     }
@@ -257,13 +261,14 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     const R logw = (R)lv.logw[l];
     const int chunk = (nlist + 2) / 3;
     const int4 *ol = offs + cls * nlist + grp * chunk;
+    const C *Hl = hank + (size_t)(cls * nlist + grp * chunk) * (2 * P - 1);
     const int nown = min(chunk, nlist - grp * chunk);
     if (active) {
         for (int o = 0; o < nown; ++o) {
             const int4 od = ol[o];
-            const C *H = hank + od.z * (2 * P - 1);
+            const C *H = Hl + o * (2 * P - 1);
             const int sx = ltx + od.x + halo, sy = lty + od.y + halo;
-            const int sidx = ((sy & 1) * 2 + (sx & 1)) * SUB + (sy >> 1) * RH + (sx >> 1);
+            const int sidx = ((sy & 1) * 2 + (sx & 1)) * SUB + (sx >> 1) * RH + (sy >> 1);
             C m[P];
 #pragma unroll
             for (int k = 0; k < P; ++k) m[k] = sm[k * RR + sidx];
@@ -1660,11 +1665,11 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
         // their near field in FP32 (Sec. 7.1) and keep M2L in FP64
         if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(768), shm / 2, s, items, M,
-                               Lm, pl->lv, pl->tab.hank32, pl->tab.m2l_off, pl->tab.m2l_a,
+                               Lm, pl->lv, pl->tab.hankl32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
         else
             hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems, 1, nr), dim3(768), shm, s, items, M,
-                               Lm, pl->lv, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a,
+                               Lm, pl->lv, pl->tab.hankl, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);

@@ -99,6 +99,8 @@ struct FmmTables {
     __bf16 *ktabb16;  // as ktab16, split in two BF16 halves
     __bf16 *p2mb16;   // as p2m16, split in two BF16 halves
     float2 *hank32;   // FP32 copy of hank (precision variant)
+    double2 *hankl;   // [4 parity classes][nlist][2p-1]: hank of each list entry, in list order
+    float2 *hankl32;  // FP32 copy of hankl
 };
 
 struct Workspace {
