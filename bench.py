@@ -389,6 +389,7 @@ def psweep_block(fp, inputs, torch, steps, warmup):
     for p in (6, 8, 10, 12, 14):
         with fp.fmm_setup(n=n, p=p, bem=1) as pl:
             pl.tune()
+            spl = pl.tune_m2l()
             for _ in range(max(warmup, 1)):
                 u.zero_()
                 pl.solve(f, u)
@@ -414,7 +415,7 @@ def psweep_block(fp, inputs, torch, steps, warmup):
             ug = uq.cpu().numpy()[idx]
             err = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
         rows[str(p)] = {"solves_per_s": round(1.0 / dt, 3), "ms_per_solve": round(1000 * dt, 4),
-                        "iters": info["iters"], "true_rel_res": rel,
+                        "iters": info["iters"], "true_rel_res": rel, "m2l_split": spl,
                         "fmm_apply_ms": round(ams, 4),
                         "fmm_mpoints_per_s": round(n * n / (ams * 1e-3) / 1e6, 1),
                         "fmm_rel_l2_err_vs_direct": err}
@@ -442,9 +443,10 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
     fs = [torch.from_numpy(inputs.gaussian_bumps(n, 16, seed=1000 + k)).to(dev)
           for k, n in enumerate(sizes)]
     us = [torch.zeros_like(f) for f in fs]
-    tuned = {}
+    tuned, splits = {}, {}
     for pl in plans:
         tuned[pl.n] = pl.tune()
+        splits[pl.n] = pl.tune_m2l()
 
     def run(graphs, separate=False):
         for u in us:
@@ -487,7 +489,8 @@ def batched_block(fp, inputs, torch, steps, warmup, prec=None):
             "no_graphs_instances_per_s": round(64.0 / tn, 2),
             "separate_plans_instances_per_s": round(64.0 / tsep, 2),
             "sequential_instances_per_s": round(64.0 / ts, 2),
-            "tuned_vector_blocks": {str(k): v for k, v in sorted(tuned.items())}}
+            "tuned_vector_blocks": {str(k): v for k, v in sorted(tuned.items())},
+            "tuned_m2l_split": {str(k): v for k, v in sorted(splits.items())}}
 
 
 def trace_summary(path, top=40):
@@ -578,7 +581,8 @@ def main():
     setup_s = time.perf_counter() - t0
     log("setup %.3f s" % setup_s)
     vec_blocks = plan.tune()     # autotuned Krylov vector-kernel grid (part of setup)
-    log("tuned vector blocks %d" % vec_blocks)
+    m2l_split = plan.tune_m2l()  # autotuned M2L tile shape (list shares per tile)
+    log("tuned vector blocks %d, M2L split %d" % (vec_blocks, m2l_split))
 
     if args.probe:
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
@@ -683,6 +687,7 @@ def main():
     def variant_block(prec, desc, peak, mfma_per_flop, label):
         pl = fp.fmm_setup(n=n, p=p, bem=1, prec=prec)
         pl.tune()
+        pl.tune_m2l()
         for _ in range(args.warmup):
             u.zero_()
             pl.solve(f, u)
@@ -741,6 +746,7 @@ def main():
         cores and M2L in FP32 (the single-precision P2P of Sec. 7.1)."""
         pl = fp.fmm_setup(n=n, p=p_t, bem=1, theta=theta, prec=prec)
         pl.tune()
+        pl.tune_m2l()
         for _ in range(args.warmup):
             u.zero_()
             pl.solve(f, u)
@@ -880,6 +886,7 @@ def main():
         "true_rel_res": rel_res,
         "setup_s": round(setup_s, 3),
         "tuned_vector_blocks": vec_blocks,
+        "tuned_m2l_split": m2l_split,
         "stages_ms_per_solve": stages,
         "stage_rooflines": stage_roof,
         "roofline": roofline,

@@ -258,6 +258,30 @@ int precond_gmres_solve_multi(fmm_plan *plan, int32_t nrhs, const double *f, dou
  * `stream`.  GRID plans only. */
 int fmm_tune(fmm_plan *plan, void *stream, int32_t *vec_blocks);
 
+/* M2L tile shape (Sec. 5.3 item 3, the translations of every level in one
+ * launch).  The launch has one block per 16 x 16 tile of target cells and
+ * list share: with split S each tile's interaction lists are cut into S
+ * shares of consecutive entries, S blocks translate one share each into
+ * their own part of the M2L sums, and the downward pass adds the S parts in
+ * order (so results are deterministic; they change with S only by the order
+ * of the additions).  S in {1, 2, 4, 8}; the plan starts with the smallest S
+ * that gives every second compute unit a block (2 S tiles >= compute units:
+ * the 2048^2 tree's 343 tiles take S = 1, the 1024^2 tree's 87 take S = 2).
+ * A call over nrhs stacked right-hand sides (or a group of a batch) takes
+ * S / nrhs (rounded down to a power of two, at least 1), since the
+ * right-hand sides already multiply the blocks; its results then agree with
+ * single calls to rounding rather than bit for bit.
+ *   fmm_tune_m2l: times the M2L and downward launches of the plan for each S
+ *     on `stream`, keeps the fastest, writes it to *split (HOST, may be
+ *     NULL); synchronises `stream`.
+ *   fmm_set_m2l_split: sets S (FMM_ERR_ARG otherwise); synchronises the
+ *     device (the buffer of M2L sums may grow).
+ *   fmm_get_m2l_split: the plan's current S into *split (HOST).
+ * Captured solver graphs of the plan are dropped by the first two. */
+int fmm_tune_m2l(fmm_plan *plan, void *stream, int32_t *split);
+int fmm_set_m2l_split(fmm_plan *plan, int32_t split);
+int fmm_get_m2l_split(const fmm_plan *plan, int32_t *split);
+
 /* Variable-coefficient operator of Sec. 6.4, -div(a grad u), in flux form
  * on the plan's grid (GRID plans only), zero Dirichlet data:
  *   h^2 (A v)_ij = ax[j][i+1] (v_ij - v_{i+1,j}) + ax[j][i] (v_ij - v_{i-1,j})

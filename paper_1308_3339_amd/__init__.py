@@ -12,5 +12,5 @@ from ._binding import (  # noqa: F401
     fmm_apply, fmm_destroy, fmm_last_error, fmm_precond_apply, fmm_precond_stages, fmm_profile, fmm_profile_read, fmm_setup,
     fmm_stencil_apply, fmm_version, library_path, load_library, precond_gmres_solve,
     precond_gmres_solve_adjoint, fmm_bumps_eval, fmm_bumps_grad, fmm_bumps_grad_noalloc, fmm_stencil_var_apply,
-    precond_gmres_solve_var, precond_gmres_solve_batch, fmm_tune, FMM_BATCH_GRAPHS, FMM_BATCH_SEPARATE, precond_gmres_solve_multi, fmm_points_order, points_levels,
+    precond_gmres_solve_var, precond_gmres_solve_batch, fmm_tune, fmm_tune_m2l, fmm_set_m2l_split, fmm_get_m2l_split, FMM_BATCH_GRAPHS, FMM_BATCH_SEPARATE, precond_gmres_solve_multi, fmm_points_order, points_levels,
 )

@@ -23,6 +23,7 @@ exported_symbols = (
     "fmm_profile_read", "precond_gmres_solve_adjoint", "fmm_bumps_eval", "fmm_bumps_grad",
     "fmm_stencil_var_apply", "precond_gmres_solve_var", "precond_gmres_solve_batch", "fmm_tune",
     "fmm_bumps_grad_noalloc", "fmm_points_order", "precond_gmres_solve_multi",
+    "fmm_tune_m2l", "fmm_set_m2l_split", "fmm_get_m2l_split",
 )
 
 STAGES = ("P2M", "M2M", "M2L", "L2L", "LEAF", "RING", "BEM", "PASS2", "STENCIL", "ARNOLDI")
@@ -99,6 +100,12 @@ def load_library():
     L.precond_gmres_solve_multi.restype = i32
     L.fmm_tune.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
     L.fmm_tune.restype = i32
+    L.fmm_tune_m2l.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
+    L.fmm_tune_m2l.restype = i32
+    L.fmm_set_m2l_split.argtypes = [vp, i32]
+    L.fmm_set_m2l_split.restype = i32
+    L.fmm_get_m2l_split.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.fmm_get_m2l_split.restype = i32
     L.fmm_stencil_var_apply.argtypes = [vp, dp, dp, dp, dp, vp]
     L.fmm_stencil_var_apply.restype = i32
     L.precond_gmres_solve_var.argtypes = [vp, dp, dp, dp, dp, ctypes.POINTER(gmres_params),
@@ -311,6 +318,25 @@ def fmm_tune(plan, stream=None):
     return out.value
 
 
+def fmm_tune_m2l(plan, stream=None):
+    """Times the M2L list splits 1, 2, 4, 8 on the plan, keeps the fastest; returns it."""
+    out = ctypes.c_int32(0)
+    _check(load_library().fmm_tune_m2l(plan._ptr, _stream(stream), ctypes.byref(out)), plan._ptr)
+    return out.value
+
+
+def fmm_set_m2l_split(plan, split):
+    """Sets the plan's M2L list split (1, 2, 4 or 8)."""
+    return _check(load_library().fmm_set_m2l_split(plan._ptr, int(split)), plan._ptr)
+
+
+def fmm_get_m2l_split(plan):
+    """The plan's current M2L list split."""
+    out = ctypes.c_int32(0)
+    _check(load_library().fmm_get_m2l_split(plan._ptr, ctypes.byref(out)), plan._ptr)
+    return out.value
+
+
 def fmm_stencil_var_apply(plan, ax, ay, v, w, stream=None):
     """w = A v for the variable-coefficient flux stencil (face values ax, ay)."""
     n, N = plan.n, plan.npts
@@ -424,6 +450,9 @@ class Plan:
     solve_multi = precond_gmres_solve_multi
     stencil_var_apply = fmm_stencil_var_apply
     tune = fmm_tune
+    tune_m2l = fmm_tune_m2l
+    set_m2l_split = fmm_set_m2l_split
+    m2l_split = property(fmm_get_m2l_split)
     solve_var = precond_gmres_solve_var
     bumps_eval = fmm_bumps_eval
     bumps_grad = fmm_bumps_grad

@@ -66,6 +66,8 @@ static int upload(fmm_plan *pl, T **dst, const std::vector<T> &src)
     return FMM_OK;
 }
 
+static int build_m2l_items(fmm_plan *pl);
+
 static int build_tables(fmm_plan *pl)
 {
     const int p = pl->p;
@@ -259,7 +261,8 @@ static int build_levels_and_work(fmm_plan *pl)
         pl->lv.logw[l] = std::log(pl->side / (double)(1 << l));
     }
     pl->exp_elems = off;
-    std::vector<M2LItem> all;
+    std::vector<M2LItem> &tiles = pl->m2l_tiles;
+    tiles.clear();
     std::vector<int4> ring;
     for (int l = L; l >= 2; --l) {
         const int nc = 1 << l, tw = std::min(16, nc), nt = nc / tw;
@@ -267,10 +270,10 @@ static int build_levels_and_work(fmm_plan *pl)
             for (int tx = 0; tx < nt; ++tx) {
                 M2LItem it;
                 it.level = l;
-                it.pad = 0;
+                it.part = 0;
                 it.tx0 = tx * tw;
                 it.ty0 = ty * tw;
-                all.push_back(it);
+                tiles.push_back(it);
             }
         // strips of cells whose lists can hold a boundary cell of level l (those
         // within 2K + 1 cells of the boundary): (level, side | depth << 2,
@@ -289,9 +292,9 @@ static int build_levels_and_work(fmm_plan *pl)
                     }
         }
     }
-    pl->n_m2l_items = (int)all.size();
     int st;
-    if (!all.empty() && (st = upload(pl, &pl->m2l_items, all))) return st;
+    if ((st = build_m2l_items(pl)) != FMM_OK || (st = set_m2l_split(pl, default_m2l_split(pl))) != FMM_OK)
+        return st;
     if (pl->kind == FMM_GRID && pl->bem && !ring.empty()) {
         pl->n_ring_cells = (int)ring.size();
         if ((st = upload(pl, &pl->ring_cells, ring))) return st;
@@ -346,8 +349,10 @@ int ensure_rhs(fmm_plan *pl, int nr)
     if (pl->exp_elems > 0) {
         const size_t bytes = (size_t)pl->exp_elems * nr * sizeof(double2);
         if (hipMalloc(&pl->ws.M, bytes) != hipSuccess || hipMalloc(&pl->ws.Lt, bytes) != hipSuccess ||
-            hipMalloc(&pl->ws.Lm, bytes) != hipSuccess)
+            hipMalloc(&pl->ws.Lm, bytes * pl->m2l_split) != hipSuccess)
             return fail(pl, FMM_ERR_ALLOC, "expansion workspace allocation failed");
+        pl->lm_parts = pl->m2l_split;
+        pl->lm_part = pl->exp_elems * nr;
         if (pl->kind == FMM_GRID && pl->bem) {
             // the boundary-source pass writes only border tiles of M2 and only
             // the boundary band of Lm2: everything else must stay zero
@@ -370,12 +375,65 @@ int ensure_rhs(fmm_plan *pl, int nr)
     return FMM_OK;
 }
 
+int default_m2l_split(const fmm_plan *pl)
+{
+    const int tiles = (int)pl->m2l_tiles.size();
+    int split = 1;
+    while (split < 8 && (int64_t)2 * split * tiles < pl->ncu) split *= 2;
+    return split;
+}
+
+int m2l_split_for(const fmm_plan *pl, int nr)
+{
+    int split = pl->m2l_split;
+    for (int r = nr; r > 1 && split > 1; r >>= 1) split >>= 1;
+    return split;
+}
+
+// the work items of every split, tile by tile, the shares of one tile next
+// to each other (they read the same sources, which then come from L2)
+static int build_m2l_items(fmm_plan *pl)
+{
+    for (int e = 0; e < 4; ++e) {
+        const int split = 1 << e;
+        std::vector<M2LItem> items;
+        items.reserve(pl->m2l_tiles.size() * split);
+        for (const M2LItem &t : pl->m2l_tiles)
+            for (int part = 0; part < split; ++part) {
+                M2LItem it = t;
+                it.part = part;
+                items.push_back(it);
+            }
+        if (items.empty()) continue;
+        const int st = upload(pl, &pl->m2l_items[e], items);
+        if (st != FMM_OK) return st;
+    }
+    return FMM_OK;
+}
+
+int set_m2l_split(fmm_plan *pl, int split)
+{
+    if (split != 1 && split != 2 && split != 4 && split != 8)
+        return fail(pl, FMM_ERR_ARG, "M2L split must be 1, 2, 4 or 8");
+    drop_step_graphs(pl);
+    if (pl->ws.Lm && split > pl->lm_parts) {
+        (void)hipFree(pl->ws.Lm);
+        pl->ws.Lm = nullptr;
+        const size_t bytes = (size_t)pl->exp_elems * pl->rhs_cap * split * sizeof(double2);
+        if (hipMalloc(&pl->ws.Lm, bytes) != hipSuccess)
+            return fail(pl, FMM_ERR_ALLOC, "M2L sum workspace allocation failed");
+        pl->lm_parts = split;
+    }
+    pl->m2l_split = split;
+    return FMM_OK;
+}
+
 static void release(fmm_plan *pl)
 {
     void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.ktabb16,
                     pl->tab.p2mb16, pl->tab.hank32, pl->tab.hankl, pl->tab.hankl32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
-                    pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items,
+                    pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items[0], pl->m2l_items[1], pl->m2l_items[2], pl->m2l_items[3],
                     pl->ring_cells, pl->ring_p2m_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,
                     pl->bhat, pl->shat, pl->perm, pl->leaf_start, pl->px, pl->py, pl->qs, pl->us,
                     pl->V, pl->Z, pl->w, pl->b, pl->partial, pl->dscal, pl->bump_part};
@@ -754,6 +812,31 @@ int fmm_tune(fmm_plan *pl, void *stream, int32_t *vec_blocks)
     const int st = tune_vector_blocks(pl, (hipStream_t)stream, &chosen);
     if (st == FMM_OK && vec_blocks) *vec_blocks = chosen;
     return st;
+}
+
+int fmm_tune_m2l(fmm_plan *pl, void *stream, int32_t *split)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    int chosen = 0;
+    const int st = tune_m2l_split(pl, (hipStream_t)stream, &chosen);
+    if (st == FMM_OK && split) *split = chosen;
+    return st;
+}
+
+int fmm_set_m2l_split(fmm_plan *pl, int32_t split)
+{
+    if (!pl) return fail(nullptr, FMM_ERR_ARG, "plan is NULL");
+    if (split != 1 && split != 2 && split != 4 && split != 8)
+        return fail(pl, FMM_ERR_ARG, "M2L split must be 1, 2, 4 or 8");
+    FMM_HIP(pl, hipDeviceSynchronize());
+    return set_m2l_split(pl, split);
+}
+
+int fmm_get_m2l_split(const fmm_plan *pl, int32_t *split)
+{
+    if (!pl || !split) return FMM_ERR_ARG;
+    *split = pl->m2l_split;
+    return FMM_OK;
 }
 
 int precond_gmres_solve_adjoint(fmm_plan *pl, const double *g, double *lambda,

@@ -185,10 +185,14 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 //   M'_0 = -M~_0, M'_k = M~_k/(k-1)!,
 //   H_0 = -(log|d^| + log w), H_m = (m-1)!/d^^m.
 // A block is a 16x16 tile of target cells (the whole level if it is
-// smaller) with 12 waves: wave w serves parity class w&3 (cells that share
+// smaller) and share item.part of nsplit of the interaction lists (its sums
+// go to part item.part of Lm, lm_part apart; the downward pass adds the
+// parts), with 12 waves: wave w serves parity class w&3 (cells that share
 // one list shape, so the offset and its Hankel generators are wave-uniform)
-// and third w>>2 of the class's nlist-entry list (27 with the list rule, more
-// with a MAC theta).  Sources (the tile plus a halo of 2K cells, 20x20 for
+// and third w>>2 of the block's share of the class's nlist-entry list (27
+// entries with the list rule, more with a MAC theta).  Splitting the lists
+// gives small trees enough blocks: a 1024^2 grid has 87 tiles for 256
+// compute units.  Sources (the tile plus a halo of 2K cells, 20x20 for
 // K = 1) are staged once in LDS, split by parity, each parity sub-grid
 // column-major: a 16-byte read of 8 columns x 2 rows of a wave's cells then
 // puts its 16 lanes on 16 distinct 16-byte bank groups (column stride
@@ -202,7 +206,8 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 template <int P, typename R>
 __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
                                              const double2 *__restrict__ M,
-                                             double2 *__restrict__ Lm, LevelInfo lv,
+                                             double2 *__restrict__ Lm, int64_t lm_part,
+                                             int nsplit, LevelInfo lv,
                                              const typename Cplx<R>::T *__restrict__ hank,
                                              const int4 *__restrict__ offs,
                                              const double *__restrict__ a_n,
@@ -259,10 +264,13 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k].x = acc[k].y = (R)0;
     const R logw = (R)lv.logw[l];
-    const int chunk = (nlist + 2) / 3;
-    const int4 *ol = offs + cls * nlist + grp * chunk;
-    const C *Hl = hank + (size_t)(cls * nlist + grp * chunk) * (2 * P - 1);
-    const int nown = min(chunk, nlist - grp * chunk);
+    // this block's share of the list: entries [lo, lo + cnt), in thirds
+    const int per = (nlist + nsplit - 1) / nsplit;
+    const int lo = it.part * per, cnt = max(0, min(per, nlist - lo));
+    const int chunk = (cnt + 2) / 3;
+    const int4 *ol = offs + cls * nlist + lo + grp * chunk;
+    const C *Hl = hank + (size_t)(cls * nlist + lo + grp * chunk) * (2 * P - 1);
+    const int nown = max(0, min(chunk, cnt - grp * chunk));
     if (active) {
         for (int o = 0; o < nown; ++o) {
             const int4 od = ol[o];
@@ -303,7 +311,7 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     }
     if (grp != 0 || !active) return;
     const int tx = it.tx0 + ltx, ty = it.ty0 + lty;
-    double2 *out = Lm + lv.off[l];
+    double2 *out = Lm + it.part * lm_part + lv.off[l];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         const double an = a_n[k];
@@ -334,50 +342,66 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 constexpr int kMaxAncestorLevel = 5;
 
 template <int P>
-__device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
+__device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm, int nsplit,
+                                                      int64_t lm_part,
                                                       double2 *__restrict__ Lt,
                                                       const double2 *__restrict__ B,
                                                       const LevelInfo &lv, int r, int m, int rx,
                                                       int ry, double2 *sB, double2 *sm2l,
                                                       double2 *buf0, double2 *buf1,
                                                       const double2 *__restrict__ top,
-                                                      int64_t top_stride,
+                                                      int64_t top_stride, bool top_m2l,
                                                       double2 *__restrict__ top_out,
                                                       double2 *sanc)
 {
     const bool anc = top == nullptr;
-    {
+    // the M2L sums are held in nsplit parts lm_part apart (one per share of
+    // the interaction lists): part 0 is stored, later parts are added in
+    // order, each part in one round trip (a thread adds into the LDS words
+    // it wrote itself, so the parts need no barrier between them)
+    for (int pp = 0; pp < nsplit; ++pp) {
+        const double2 *__restrict__ Lp = Lm + pp * lm_part;
+        const bool first = pp == 0;
+        const bool with_top = !anc && (first || top_m2l);
+        const double2 *__restrict__ tp = top_m2l ? top + pp * lm_part : top;
         // M2L sum k of the level-(2 + j) ancestor, t = j P + k
         auto anc_sum = [&](int t) {
             const int j = t / P, k = t - j * P, l = 2 + j, nc = 1 << l;
             const int ax = rx >> (r - l), ay = ry >> (r - l);
-            return Lm[lv.off[l] + k * (int64_t)nc * nc + (int64_t)ay * nc + ax];
+            return Lp[lv.off[l] + k * (int64_t)nc * nc + (int64_t)ay * nc + ax];
         };
         double2 va[rounds256((kMaxAncestorLevel - 1) * P)];
         fetch(va, anc ? (r - 1) * P : 0, anc_sum);
         auto m2l_sum = [&](int st, int t) {
             const int l = r + st, tw = 1 << st, nc = 1 << l;
             const int nn = t >> (2 * st), c = t & (tw * tw - 1);
-            return Lm[lv.off[l] + nn * (int64_t)nc * nc + (int64_t)(ry * tw + (c >> st)) * nc +
+            return Lp[lv.off[l] + nn * (int64_t)nc * nc + (int64_t)(ry * tw + (c >> st)) * nc +
                       rx * tw + (c & (tw - 1))];
         };
         double2 vb[rounds256(4 * P * P)], vt[1], v1[rounds256(4 * P)], v2[rounds256(16 * P)],
             v3[rounds256(64 * P)];
-        fetch(vb, 4 * P * P, [&](int t) { return B[t]; });
-        fetch(vt, anc ? 0 : P, [&](int t) { return top[t * top_stride]; });
+        fetch(vb, first ? 4 * P * P : 0, [&](int t) { return B[t]; });
+        fetch(vt, with_top ? P : 0, [&](int t) { return tp[t * top_stride]; });
         fetch(v1, m >= 1 ? 4 * P : 0, [&](int t) { return m2l_sum(1, t); });
         fetch(v2, m >= 2 ? 16 * P : 0, [&](int t) { return m2l_sum(2, t); });
         fetch(v3, m >= 3 ? 64 * P : 0, [&](int t) { return m2l_sum(3, t); });
-        put(vb, 4 * P * P, [&](int t, double2 x) { sB[t] = x; });
-        put(va, anc ? (r - 1) * P : 0, [&](int t, double2 x) { sanc[t] = x; });
-        put(vt, anc ? 0 : P, [&](int t, double2 x) {
-            buf0[t] = x;
-            if (top_out) top_out[t * top_stride] = x;
-        });
-        put(v1, m >= 1 ? 4 * P : 0, [&](int t, double2 x) { sm2l[(t >> 2) * 84 + (t & 3)] = x; });
-        put(v2, m >= 2 ? 16 * P : 0, [&](int t, double2 x) { sm2l[(t >> 4) * 84 + 4 + (t & 15)] = x; });
-        put(v3, m >= 3 ? 64 * P : 0, [&](int t, double2 x) { sm2l[(t >> 6) * 84 + 20 + (t & 63)] = x; });
+        auto st = [first](double2 &d, double2 x) {
+            if (first) {
+                d = x;
+            } else {
+                d.x += x.x;
+                d.y += x.y;
+            }
+        };
+        put(vb, first ? 4 * P * P : 0, [&](int t, double2 x) { sB[t] = x; });
+        put(va, anc ? (r - 1) * P : 0, [&](int t, double2 x) { st(sanc[t], x); });
+        put(vt, with_top ? P : 0, [&](int t, double2 x) { st(buf0[t], x); });
+        put(v1, m >= 1 ? 4 * P : 0, [&](int t, double2 x) { st(sm2l[(t >> 2) * 84 + (t & 3)], x); });
+        put(v2, m >= 2 ? 16 * P : 0, [&](int t, double2 x) { st(sm2l[(t >> 4) * 84 + 4 + (t & 15)], x); });
+        put(v3, m >= 3 ? 64 * P : 0, [&](int t, double2 x) { st(sm2l[(t >> 6) * 84 + 20 + (t & 63)], x); });
     }
+    // the root's whole expansion, by the threads that summed it (t < P <= 256)
+    if (top_out && !anc && (int)threadIdx.x < P) top_out[threadIdx.x * top_stride] = buf0[threadIdx.x];
     __syncthreads();
     if (anc) {
         // down the ancestors, one coefficient per thread, into buf0
@@ -429,10 +453,10 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm,
 
 // root: 1 = the root is a level-2 cell (its expansion is its M2L sum, also
 // stored), 0 = read the root's expansion from Lt, 2 = build it from the
-// ancestors (r <= 5)
+// ancestors (r <= 5).  The M2L sums are the nsplit parts of Lm, lm_part apart.
 template <int P>
-__global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
-                                              double2 *__restrict__ Lt,
+__global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm, int nsplit,
+                                              int64_t lm_part, double2 *__restrict__ Lt,
                                               const double2 *__restrict__ B, LevelInfo lv, int r,
                                               int m, int root, RhsSet rh)
 {
@@ -447,8 +471,8 @@ __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm,
     const int rx = blockIdx.x & (nr - 1), ry = blockIdx.x >> r;
     const int64_t gi = lv.off[r] + (int64_t)ry * nr + rx;
     const double2 *top = root == 2 ? nullptr : (root == 1 ? Lm : Lt) + gi;
-    down_levels<P>(Lm, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1, top, (int64_t)nr * nr,
-                   root == 1 ? Lt + gi : nullptr, sanc);
+    down_levels<P>(Lm, nsplit, lm_part, Lt, B, lv, r, m, rx, ry, sB, sm2l, buf0, buf1, top,
+                   (int64_t)nr * nr, root == 1, root == 1 ? Lt + gi : nullptr, sanc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1506,8 +1530,8 @@ __global__ __launch_bounds__(256) void k_far_l2p(LeafArgs a, const double2 *__re
         const int r = a.L - 3, nr = 1 << r;
         const double2 *top =
             chain == 2 ? nullptr : pp.Lt + a.lv.off[r] + (int64_t)blockIdx.y * nr + blockIdx.x;
-        sL = down_levels<P>(Lm, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l, buf0, buf1,
-                            top, (int64_t)nr * nr, nullptr, sanc);
+        sL = down_levels<P>(Lm, 1, 0, nullptr, B, a.lv, r, 3, blockIdx.x, blockIdx.y, sB, sm2l,
+                            buf0, buf1, top, (int64_t)nr * nr, false, nullptr, sanc);
         if (Lvol) {
             put(vv, P * cnt, [&](int t, double2 x) {
                 sL[t].x += x.x;
@@ -1653,28 +1677,31 @@ static std::vector<DownChunk> down_chunks(int L)
 }
 
 template <int P>
-static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
-                       const M2LItem *items, int nitems, const RhsSet &rh, int nr, hipStream_t s,
-                       bool timed)
+static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt, const RhsSet &rh,
+                       int nr, hipStream_t s, bool timed)
 {
     const int rw = 16 + 4 * pl->K;
     const size_t shm = (size_t)P * rw * rw * sizeof(double2);
+    const int ns = m2l_split_for(pl, nr);
+    const int nitems = (int)pl->m2l_tiles.size() * ns;
+    const M2LItem *items = pl->m2l_items[ns == 1 ? 0 : ns == 2 ? 1 : ns == 4 ? 2 : 3];
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
         // reduced-precision grid plans translate in FP32; point clouds take only
         // their near field in FP32 (Sec. 7.1) and keep M2L in FP64
         if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(768), shm / 2, s, items, M,
-                               Lm, pl->lv, pl->tab.hankl32, pl->tab.m2l_off, pl->tab.m2l_a,
+                               Lm, pl->lm_part, ns, pl->lv, pl->tab.hankl32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
         else
             hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems, 1, nr), dim3(768), shm, s, items, M,
-                               Lm, pl->lv, pl->tab.hankl, pl->tab.m2l_off, pl->tab.m2l_a,
+                               Lm, pl->lm_part, ns, pl->lv, pl->tab.hankl, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
     }
     StageTimer t(pl, timed ? FMM_STAGE_L2L : -1, s);
     for (const auto &c : down_chunks(pl->L))
-        hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r), 1, nr), dim3(256), 0, s, Lm, Lt,
+        hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r), 1, nr), dim3(256), 0, s, Lm, ns, pl->lm_part,
+                           Lt,
                            pl->tab.l2l, pl->lv, c.r, c.m, c.root, rh);
     return FMM_OK;
 }
@@ -1761,8 +1788,7 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
             StageTimer t(pl, FMM_STAGE_M2M, s);
             run_m2m_from<P>(pl, pl->ws.M, pl->L, rh, nr, s);
         }
-        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items, rh, nr,
-                       s, true);
+        run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, rh, nr, s, true);
     }
     if (ring_out) {
         StageTimer t(pl, FMM_STAGE_RING, s);
@@ -1807,7 +1833,7 @@ static int grid_ring_source_fmm_p(fmm_plan *pl, double *u, bool with_volume, dou
         if (chain_mode != 2)
             for (const auto &c : down_chunks(last))
                 hipLaunchKernelGGL(k_down<P>, dim3(1 << (2 * c.r), 1, nr), dim3(256), 0, s,
-                                   pl->ws.Lm2, pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.root,
+                                   pl->ws.Lm2, 1, (int64_t)0, pl->ws.Lt2, pl->tab.l2l, pl->lv, c.r, c.m, c.root,
                                    rh);
         const LeafArgs a = leaf_args(pl, nullptr, 1.0, u, pl->ws.Lt2, far, rh);
         hipLaunchKernelGGL(k_far_l2p<P>, dim3(nl / tw, nl / tw, nr), dim3(256), 0, s, a, pl->ws.Lm2,
@@ -1834,6 +1860,56 @@ int grid_ring_source_fmm(fmm_plan *pl, double *u, bool with_volume, double *sigm
     FMM_DISPATCH_P(pl->p, grid_ring_source_fmm_p, pl, u, with_volume, sigma_out, rh, nr, s);
 }
 
+template <int P>
+static int tune_m2l_split_p(fmm_plan *pl, hipStream_t s, int *chosen)
+{
+    int st = ensure_rhs(pl, 1);
+    if (st != FMM_OK) return st;
+    if (pl->L < 2 || pl->m2l_tiles.empty()) {
+        *chosen = pl->m2l_split;
+        return FMM_OK;
+    }
+    // finite multipoles to translate (values do not affect the timing)
+    FMM_HIP(pl, hipMemsetAsync(pl->ws.M, 0, (size_t)pl->exp_elems * sizeof(double2), s));
+    const RhsSet rh = plan_rhs(pl, pl->kind == FMM_GRID ? (int64_t)pl->n * pl->n : (int64_t)pl->n,
+                               nullptr);
+    hipEvent_t e0, e1;
+    FMM_HIP(pl, hipEventCreate(&e0));
+    FMM_HIP(pl, hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = pl->m2l_split;
+    for (int split : {1, 2, 4, 8}) {
+        FMM_HIP(pl, hipStreamSynchronize(s));
+        st = set_m2l_split(pl, split);
+        if (st != FMM_OK) break;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 4; ++rep) {
+            FMM_HIP(pl, hipEventRecord(e0, s));
+            run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, rh, 1, s, false);
+            FMM_HIP(pl, hipEventRecord(e1, s));
+            FMM_HIP(pl, hipEventSynchronize(e1));
+            float t = 0.0f;
+            FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
+            if (rep > 0) ms += t;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = split;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FMM_OK) return st;
+    st = set_m2l_split(pl, best);
+    if (st == FMM_OK) *chosen = best;
+    return st;
+}
+
+int tune_m2l_split(fmm_plan *pl, hipStream_t s, int *chosen)
+{
+    FMM_DISPATCH_P(pl->p, tune_m2l_split_p, pl, s, chosen);
+}
+
 // level-generic stages reused by point-cloud plans
 template <int P>
 static int points_up_p(fmm_plan *pl, hipStream_t s)
@@ -1846,8 +1922,7 @@ static int points_up_p(fmm_plan *pl, hipStream_t s)
 template <int P>
 static int points_down_p(fmm_plan *pl, hipStream_t s)
 {
-    return run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, pl->m2l_items, pl->n_m2l_items,
-                          RhsSet{}, 1, s, true);
+    return run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, RhsSet{}, 1, s, true);
 }
 
 int points_upward_rest(fmm_plan *pl, hipStream_t s)

@@ -70,7 +70,7 @@ __device__ __forceinline__ bool rhs_active(const RhsSet &rh, int r)
 // Work item of the all-levels M2L launch: a tile of target cells at a level.
 struct M2LItem {
     int32_t level;
-    int32_t pad;
+    int32_t part;   // share of the interaction lists (0 .. m2l_split-1), and part of Workspace::Lm
     int32_t tx0, ty0;
 };
 
@@ -106,7 +106,7 @@ struct FmmTables {
 struct Workspace {
     double2 *M = nullptr;    // multipoles, levels 2..L
     double2 *Lt = nullptr;   // local expansions, levels 2..L
-    double2 *Lm = nullptr;   // M2L sums, levels 2..L
+    double2 *Lm = nullptr;   // M2L sums, levels 2..L, in m2l_split parts lm_part apart
     // second (boundary-source) pass of the preconditioner
     double2 *M2 = nullptr;
     double2 *Lt2 = nullptr;
@@ -159,8 +159,13 @@ struct fmm_plan {
 
     fmmprec::FmmTables tab{};
     fmmprec::Workspace ws{};
-    fmmprec::M2LItem *m2l_items = nullptr;  // all tiles of levels 2..L
-    int n_m2l_items = 0;
+    // M2L work items for each split S = 1, 2, 4, 8 (entry log2 S): every tile
+    // of levels 2..L, S times (one item per list share)
+    fmmprec::M2LItem *m2l_items[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<fmmprec::M2LItem> m2l_tiles;  // the tiles themselves (host copy)
+    int m2l_split = 1;        // M2L blocks per tile for one right-hand side
+    int lm_parts = 0;         // parts Workspace::Lm holds (>= m2l_split once allocated)
+    int64_t lm_part = 0;      // double2 elements between parts of Lm (rhs_cap * exp_elems)
     int4 *ring_cells = nullptr;   // strips within 2K+1 cells of the boundary (see k_m2l_ring)
     int n_ring_cells = 0;
     int4 *ring_p2m_cells = nullptr;  // boundary cells of levels 2..L: (level, ix, iy, 0)
@@ -287,6 +292,17 @@ int grid_ring_source_fmm(fmm_plan *plan, double *u, bool with_volume, double *si
 // workspace for nr right-hand sides (grows only; drops captured graphs that
 // hold the old addresses)
 int ensure_rhs(fmm_plan *plan, int nr);
+// M2L list split: 1, 2, 4 or 8 blocks per tile (rebuilds the work items,
+// grows Lm, drops captured graphs); the default gives half the compute
+// units a block
+int set_m2l_split(fmm_plan *plan, int split);
+int default_m2l_split(const fmm_plan *plan);
+// the split a launch over nr right-hand sides takes: the plan's split for
+// one, shrunk by nr (rounded down to a power of two) since the right-hand
+// sides already multiply the blocks
+int m2l_split_for(const fmm_plan *plan, int nr);
+// times M2L + the downward launches for every split and keeps the fastest
+int tune_m2l_split(fmm_plan *plan, hipStream_t s, int *chosen);
 // the right-hand-side set of nr stacked arrays of length sv on this plan
 RhsSet plan_rhs(const fmm_plan *plan, int64_t sv, const int *act);
 int m2l_kernel_setup(fmm_plan *plan);

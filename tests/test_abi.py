@@ -103,6 +103,9 @@ def test_null_arguments():
     assert lib.fmm_destroy(None) == fp.FMM_OK
     assert lib.precond_gmres_solve_batch(None, 1, None, None, None, None, None, 0, None) == fp.FMM_ERR_ARG
     assert lib.fmm_tune(None, None, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_tune_m2l(None, None, None) == fp.FMM_ERR_ARG
+    assert lib.fmm_set_m2l_split(None, 2) == fp.FMM_ERR_ARG
+    assert lib.fmm_get_m2l_split(None, None) == fp.FMM_ERR_ARG
     assert lib.precond_gmres_solve_var(None, None, None, None, None, None, None, None) == fp.FMM_ERR_ARG
     assert lib.fmm_bumps_eval(None, 1, None, None, None, None, None, None) == fp.FMM_ERR_ARG
 

@@ -165,7 +165,13 @@ def test_multi_rhs_apply_and_stencil_equal_single_calls():
             for k in range(nr):
                 z = torch.empty(n * n, dtype=torch.float64, device="cuda")
                 getattr(plan, name)(dev(R[k]), z)
-                assert np.array_equal(host(z), Zg[k]), (name, k)
+                if name == "stencil_apply":
+                    assert np.array_equal(host(z), Zg[k]), (name, k)
+                else:
+                    # a stacked call takes a smaller M2L list split (the right-hand
+                    # sides already multiply the blocks): the M2L parts are added
+                    # in another grouping, so results agree to rounding
+                    assert rel(Zg[k], host(z)) <= 1e-14, (name, k)
 
 
 def test_group_zero_rhs_and_iteration_limit():

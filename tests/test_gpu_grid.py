@@ -99,7 +99,9 @@ def test_fmm_apply_multi_rhs_and_determinism():
         assert np.array_equal(U1, host(U2).reshape(3, -1))   # no atomics: bitwise repeat
         u1 = empty(n * n)
         plan.apply(dev(Q[1]), u1)
-        assert np.array_equal(host(u1), U1[1])
+        # one right-hand side takes a larger M2L list split than three stacked
+        # ones: the same sums in another grouping, equal to rounding
+        assert relmax(host(u1), U1[1]) <= 1e-14
     for k in range(3):
         assert relmax(U1[k], o.grid_fmm(n, p, Q[k])) <= 1e-12
 
