@@ -2,8 +2,8 @@
 
     python -m paper_1308_3339_amd.build        # or build() from Python
 
-Every .hip file under csrc/ is compiled to an object in _build/ (in
-parallel), then linked into paper_1308_3339_amd/libfmmprec.so.
+Every .hip and .cpp file under csrc/ is compiled to an object in _build/
+(in parallel), then linked into paper_1308_3339_amd/libfmmprec.so.
 """
 from __future__ import annotations
 
@@ -29,7 +29,8 @@ FLAGS = [
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    # the HIP sources and the plain C++ host setup (compiled by hipcc as host code)
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:

@@ -1,17 +1,7 @@
 // C ABI of the gfx950 FMM-preconditioned Poisson solver: argument checks,
 // plan setup (PCSetUp of Sec. 7.1 of arXiv:1308.3339) and the entry points.
-//
-// The operator tables are built here on the host, in FP64, from the
-// translation formulas of Sec. 5.3 rewritten for level-scaled expansions:
-//   M2M (item 2):  M~par_n = -M~_0 c^n/n + sum_{k=1..n} 2^-k c^(n-k) C(n-1,k-1) M~_k,
-//                  c = (child - parent centre)/w_parent
-//   L2L (item 4):  L~child_n = 2^-n sum_{k>=n} C(k,n) c^(k-n) L~par_k
-//   M2L (item 3):  Hankel generators H_0 = -log|d|, H_m = (m-1)!/d^m with
-//                  d = target minus source centre in cell widths, and the
-//                  scalings a_n = (-1)^n/n!, b_0 = -1, b_k = 1/(k-1)!
-//   P2M (item 1) / L2P (item 5) on the fixed 8x8 leaf pattern,
-//                  tau_j = (x_j - centre)/w_leaf
-//   near field     T(d) = log(h |d|) on the integer lattice, T(0) = log(eps h)
+// The operator tables, interaction lists and work lists are built on the
+// host by host_setup.cpp (plain C++) and uploaded here.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -20,6 +10,7 @@
 #include <vector>
 
 #include "fmm_internal.h"
+#include "host_setup.h"
 
 namespace fmmprec {
 
@@ -34,280 +25,70 @@ int fail(fmm_plan *plan, int code, const std::string &msg)
 
 int m2l_kernel_setup(fmm_plan *pl);  // fmm_grid.hip
 
-using cd = std::complex<double>;
+// layouts of the host-built tables and of the device vectors they fill
+static_assert(sizeof(host::C2) == sizeof(double2) && sizeof(host::F2) == sizeof(float2) &&
+                  sizeof(host::I4) == sizeof(int4) && sizeof(host::I4) == sizeof(M2LItem),
+              "host table layouts");
 
-static double factorial(int k)
+template <class D, class T>
+static int upload_as(fmm_plan *pl, D **dst, const std::vector<T> &src)
 {
-    double f = 1.0;
-    for (int i = 2; i <= k; ++i) f *= i;
-    return f;
-}
-
-static double binom(int a, int b)
-{
-    if (b < 0 || b > a) return 0.0;
-    double r = 1.0;
-    for (int i = 1; i <= b; ++i) r = r * (a - b + i) / i;
-    return std::floor(r + 0.5);
-}
-
-static cd ipow(cd z, int k)
-{
-    cd r = 1.0;
-    for (int i = 0; i < k; ++i) r *= z;
-    return r;
+    static_assert(sizeof(D) == sizeof(T), "layout");
+    FMM_HIP(pl, hipMalloc(dst, src.size() * sizeof(T)));
+    FMM_HIP(pl, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return FMM_OK;
 }
 
 template <class T>
 static int upload(fmm_plan *pl, T **dst, const std::vector<T> &src)
 {
-    FMM_HIP(pl, hipMalloc(dst, src.size() * sizeof(T)));
-    FMM_HIP(pl, hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
-    return FMM_OK;
+    return upload_as(pl, dst, src);
 }
 
 static int build_m2l_items(fmm_plan *pl);
 
 static int build_tables(fmm_plan *pl)
 {
-    const int p = pl->p;
-    // M2M
-    std::vector<double2> m2m((size_t)4 * p * p, double2{0.0, 0.0});
-    for (int qd = 0; qd < 4; ++qd) {
-        const cd c(0.5 * ((qd & 1) - 0.5), 0.5 * ((qd >> 1) - 0.5));
-        for (int n = 0; n < p; ++n)
-            for (int k = 0; k <= n; ++k) {
-                cd v;
-                if (n == 0) v = 1.0;
-                else if (k == 0) v = -ipow(c, n) / (double)n;
-                else v = std::ldexp(1.0, -k) * ipow(c, n - k) * binom(n - 1, k - 1);
-                m2m[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
-            }
-    }
-    // L2L: L~child_n = sum_{k>=n} C(k,n) c^(k-n) 2^-n L~parent_k
-    std::vector<double2> l2l((size_t)4 * p * p, double2{0.0, 0.0});
-    for (int qd = 0; qd < 4; ++qd) {
-        const cd c(0.5 * ((qd & 1) - 0.5), 0.5 * ((qd >> 1) - 0.5));
-        for (int n = 0; n < p; ++n)
-            for (int k = n; k < p; ++k) {
-                const cd v = binom(k, n) * ipow(c, k - n) * std::ldexp(1.0, -n);
-                l2l[((size_t)qd * p + n) * p + k] = double2{v.real(), v.imag()};
-            }
-    }
-    // M2L Hankel generators for source offsets (dx, dy) in [-R, R]^2, R =
-    // 2K + 1 (source cell = target cell + (dx, dy)); the expansion variable
-    // of Sec. 5.3 is z_{Lambda M} = target centre - source centre = -(dx + i dy)
-    // cell widths.  Offsets of the near disk are never used.
-    const int nh = 2 * p - 1, K = pl->K, R = 2 * K + 1, RD = 2 * R + 1;
-    std::vector<double2> hank((size_t)RD * RD * nh, double2{0.0, 0.0});
-    for (int dy = -R; dy <= R; ++dy)
-        for (int dx = -R; dx <= R; ++dx) {
-            if (pl->in_near(dx, dy)) continue;
-            const cd d(-(double)dx, -(double)dy);
-            const size_t o = (size_t)((dy + R) * RD + dx + R) * nh;
-            hank[o] = double2{-std::log(std::abs(d)), 0.0};
-            for (int m = 1; m < nh; ++m) {
-                const cd v = factorial(m - 1) / ipow(d, m);
-                hank[o + m] = double2{v.real(), v.imag()};
-            }
-        }
-    // interaction-list offsets per parity class: children of the parent's
-    // near set that are not in the target's own near set (Sec. 5.2; with the
-    // 3x3 near set of the list rule these are the 27 of the paper's Fig. 3,
-    // with a MAC theta the traversal's equivalent lists on the uniform tree)
-    std::vector<std::vector<int4>> cls(4);
-    for (int w = 0; w < 4; ++w) {
-        const int px = w & 1, py = w >> 1;
-        for (int dy = -2 * K - py; dy <= 2 * K + 1 - py; ++dy)
-            for (int dx = -2 * K - px; dx <= 2 * K + 1 - px; ++dx) {
-                if (pl->in_near(dx, dy)) continue;
-                // parent offset of the source
-                const int Dx = (dx + px) >> 1, Dy = (dy + py) >> 1;
-                if (!pl->in_near(Dx, Dy)) continue;
-                cls[w].push_back(int4{dx, dy, (dy + R) * RD + dx + R, 0});
-            }
-    }
-    for (int w = 1; w < 4; ++w)
-        if (cls[w].size() != cls[0].size()) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
-    pl->nlist = (int)cls[0].size();
-    if (K == 1 && pl->nlist != 27) return fail(pl, FMM_ERR_ARG, "internal: interaction list size");
-    std::vector<int4> offs;
-    for (int w = 0; w < 4; ++w) offs.insert(offs.end(), cls[w].begin(), cls[w].end());
-    // the generators again in list order, [class][list entry][2p - 1], so
-    // that M2L finds an entry's generators without first loading its offset
-    std::vector<double2> hankl(offs.size() * (size_t)nh);
-    for (size_t e = 0; e < offs.size(); ++e)
-        for (int m = 0; m < nh; ++m) hankl[e * nh + m] = hank[(size_t)offs[e].z * nh + m];
-    std::vector<double> an(p), bk(p);
-    for (int k = 0; k < p; ++k) {
-        an[k] = ((k & 1) ? -1.0 : 1.0) / factorial(k);
-        bk[k] = (k == 0) ? -1.0 : 1.0 / factorial(k - 1);
-    }
-    // leaf point pattern
-    std::vector<double2> p2m((size_t)p * 64), l2p((size_t)64 * p);
-    for (int j = 0; j < 64; ++j) {
-        const int a = j & 7, b = j >> 3;
-        const cd tau((a - 3.5) / 8.0, (b - 3.5) / 8.0);
-        for (int k = 0; k < p; ++k) {
-            const cd pk = ipow(tau, k);
-            const cd w = (k == 0) ? cd(1.0) : -pk / (double)k;
-            p2m[(size_t)k * 64 + j] = double2{w.real(), w.imag()};
-            l2p[(size_t)j * p + k] = double2{pk.real(), pk.imag()};
-        }
-    }
-    // near-field kernel table: lattice offsets within the (2K+1)^2 leaves
-    // around a leaf, |dx|, |dy| <= 8K + 7 (side 31 for K = 1)
-    const int KC = 8 * K + 7, KS = 2 * KC + 1;
-    std::vector<double> kt((size_t)KS * KS);
-    const double h = pl->h;
-    for (int dy = -KC; dy <= KC; ++dy)
-        for (int dx = -KC; dx <= KC; ++dx) {
-            const double v = (dx == 0 && dy == 0)
-                                 ? std::log(pl->self_eps * h)
-                                 : std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
-            kt[(size_t)(dy + KC) * KS + dx + KC] = v;
-        }
-    // ring node to grid node: |dx|, |dy| <= 8(K + 1) (side 17 for K = 1)
-    const int RS = 8 * K + 9;
-    std::vector<double> rt((size_t)RS * RS, 0.0);
-    for (int dy = 0; dy < RS; ++dy)
-        for (int dx = 0; dx < RS; ++dx)
-            if (dx || dy) rt[(size_t)dy * RS + dx] = std::log(h * std::sqrt((double)(dx * dx + dy * dy)));
-    // FP32 and split-FP16 tables (the split-FP16 leaf kernel exists for the 3x3 near set only)
-    std::vector<float> kt32(kt.begin(), kt.end());
-    const int prow = 16 * ((2 * p + 15) / 16);
-    std::vector<float> p2m32((size_t)prow * 64, 0.0f);
-    std::vector<_Float16> p2m16((size_t)2 * prow * 64, (_Float16)0.0f);
-    for (int k = 0; k < p; ++k)
-        for (int j = 0; j < 64; ++j) {
-            p2m32[(size_t)(2 * k) * 64 + j] = (float)p2m[(size_t)k * 64 + j].x;
-            p2m32[(size_t)(2 * k + 1) * 64 + j] = (float)p2m[(size_t)k * 64 + j].y;
-        }
-    // split x = hi + lo with hi = fp16(x), lo = fp16(x - hi)
-    auto split16 = [](double x, _Float16 &hi, _Float16 &lo) {
-        hi = (_Float16)x;
-        lo = (_Float16)(x - (double)hi);
-    };
-    // the same with BF16 halves (round to nearest even on the FP32 bits)
-    auto to_bf16 = [](double x) {
-        const float f = (float)x;
-        uint32_t b;
-        std::memcpy(&b, &f, 4);
-        b += 0x7fffu + ((b >> 16) & 1u);
-        const uint16_t hb = (uint16_t)(b >> 16);
-        __bf16 r;
-        std::memcpy(&r, &hb, 2);
-        return r;
-    };
-    auto bf16_val = [](__bf16 h) {
-        uint16_t hb;
-        std::memcpy(&hb, &h, 2);
-        const uint32_t b = (uint32_t)hb << 16;
-        float f;
-        std::memcpy(&f, &b, 4);
-        return (double)f;
-    };
-    auto splitb16 = [&](double x, __bf16 &hi, __bf16 &lo) {
-        hi = to_bf16(x);
-        lo = to_bf16(x - bf16_val(hi));
-    };
-    std::vector<__bf16> p2mb16((size_t)2 * prow * 64, to_bf16(0.0));
-    for (int r = 0; r < 2 * p; ++r)
-        for (int j = 0; j < 64; ++j) {
-            const double2 w = p2m[(size_t)(r / 2) * 64 + j];
-            split16(r & 1 ? w.y : w.x, p2m16[(size_t)r * 64 + j], p2m16[(size_t)(prow + r) * 64 + j]);
-            splitb16(r & 1 ? w.y : w.x, p2mb16[(size_t)r * 64 + j], p2mb16[(size_t)(prow + r) * 64 + j]);
-        }
-    // kernel table in 8 column-shifted copies: copy c, row r, entry j = T[r][j + c]
-    std::vector<_Float16> kt16((size_t)2 * 8 * 31 * 40, (_Float16)0.0f);
-    std::vector<__bf16> ktb16((size_t)2 * 8 * 31 * 40, to_bf16(0.0));
-    for (int c = 0; c < 8; ++c)
-        for (int r = 0; r < 31; ++r)
-            for (int j = 0; j + c <= 30 && j < 40; ++j) {
-                split16(kt[(size_t)r * 31 + j + c], kt16[((size_t)c * 31 + r) * 40 + j],
-                        kt16[((size_t)(8 + c) * 31 + r) * 40 + j]);
-                splitb16(kt[(size_t)r * 31 + j + c], ktb16[((size_t)c * 31 + r) * 40 + j],
-                         ktb16[((size_t)(8 + c) * 31 + r) * 40 + j]);
-            }
-    std::vector<float2> hank32(hank.size()), hankl32(hankl.size());
-    for (size_t i = 0; i < hank.size(); ++i) hank32[i] = float2{(float)hank[i].x, (float)hank[i].y};
-    for (size_t i = 0; i < hankl.size(); ++i) hankl32[i] = float2{(float)hankl[i].x, (float)hankl[i].y};
+    host::Tables t;
+    std::string err;
+    if (!host::build_tables(pl->p, pl->theta, pl->h, pl->self_eps, t, err)) return fail(pl, FMM_ERR_ARG, err);
+    pl->nlist = t.nlist;
     int st;
-    if ((st = upload(pl, &pl->tab.ktab32, kt32)) || (st = upload(pl, &pl->tab.p2m32, p2m32)) ||
-        (st = upload(pl, &pl->tab.ktab16, kt16)) || (st = upload(pl, &pl->tab.p2m16, p2m16)) ||
-        (st = upload(pl, &pl->tab.ktabb16, ktb16)) || (st = upload(pl, &pl->tab.p2mb16, p2mb16)) ||
-        (st = upload(pl, &pl->tab.hank32, hank32)) || (st = upload(pl, &pl->tab.hankl, hankl)) ||
-        (st = upload(pl, &pl->tab.hankl32, hankl32)) ||
-        (st = upload(pl, &pl->tab.rtab, rt)) || (st = upload(pl, &pl->tab.m2m, m2m)) || (st = upload(pl, &pl->tab.l2l, l2l)) ||
-        (st = upload(pl, &pl->tab.hank, hank)) ||
-        (st = upload(pl, &pl->tab.m2l_off, offs)) || (st = upload(pl, &pl->tab.m2l_a, an)) ||
-        (st = upload(pl, &pl->tab.m2l_b, bk)) || (st = upload(pl, &pl->tab.p2m, p2m)) ||
-        (st = upload(pl, &pl->tab.l2p, l2p)) || (st = upload(pl, &pl->tab.ktab, kt)))
+    if ((st = upload(pl, &pl->tab.ktab32, t.kt32)) || (st = upload(pl, &pl->tab.p2m32, t.p2m32)) ||
+        (st = upload(pl, &pl->tab.ktab16, t.kt16)) || (st = upload(pl, &pl->tab.p2m16, t.p2m16)) ||
+        (st = upload(pl, &pl->tab.ktabb16, t.ktb16)) || (st = upload(pl, &pl->tab.p2mb16, t.p2mb16)) ||
+        (st = upload_as(pl, &pl->tab.hank32, t.hank32)) || (st = upload_as(pl, &pl->tab.hankl, t.hankl)) ||
+        (st = upload_as(pl, &pl->tab.hankl32, t.hankl32)) || (st = upload(pl, &pl->tab.rtab, t.rt)) ||
+        (st = upload_as(pl, &pl->tab.m2m, t.m2m)) || (st = upload_as(pl, &pl->tab.l2l, t.l2l)) ||
+        (st = upload_as(pl, &pl->tab.hank, t.hank)) || (st = upload_as(pl, &pl->tab.m2l_off, t.offs)) ||
+        (st = upload(pl, &pl->tab.m2l_a, t.an)) || (st = upload(pl, &pl->tab.m2l_b, t.bk)) ||
+        (st = upload_as(pl, &pl->tab.p2m, t.p2m)) || (st = upload_as(pl, &pl->tab.l2p, t.l2p)) ||
+        (st = upload(pl, &pl->tab.ktab, t.kt)))
         return st;
     return FMM_OK;
 }
 
 static int build_levels_and_work(fmm_plan *pl)
 {
-    const int L = pl->L, p = pl->p;
-    int64_t off = 0;
+    host::Work w;
+    const bool ring_lists = pl->kind == FMM_GRID && pl->bem;
+    host::build_work(pl->L, pl->p, pl->K, pl->side, ring_lists, w);
+    static_assert(host::kMaxLevelsH == kMaxLevels, "level table size");
     for (int l = 0; l <= kMaxLevels; ++l) {
-        pl->lv.off[l] = 0;
-        pl->lv.logw[l] = 0.0;
+        pl->lv.off[l] = w.off[l];
+        pl->lv.logw[l] = w.logw[l];
     }
-    for (int l = 2; l <= L; ++l) {
-        pl->lv.off[l] = off;
-        off += ((int64_t)1 << (2 * l)) * p;
-        pl->lv.logw[l] = std::log(pl->side / (double)(1 << l));
-    }
-    pl->exp_elems = off;
-    std::vector<M2LItem> &tiles = pl->m2l_tiles;
-    tiles.clear();
-    std::vector<int4> ring;
-    for (int l = L; l >= 2; --l) {
-        const int nc = 1 << l, tw = std::min(16, nc), nt = nc / tw;
-        for (int ty = 0; ty < nt; ++ty)
-            for (int tx = 0; tx < nt; ++tx) {
-                M2LItem it;
-                it.level = l;
-                it.part = 0;
-                it.tx0 = tx * tw;
-                it.ty0 = ty * tw;
-                tiles.push_back(it);
-            }
-        // strips of cells whose lists can hold a boundary cell of level l (those
-        // within 2K + 1 cells of the boundary): (level, side | depth << 2,
-        // start, end), 64 lanes per item stepping by 2 from start
-        const int band = 2 * pl->K + 2;
-        if (nc <= 2 * band) {
-            for (int d = 0; d < nc; ++d)
-                for (int par = 0; par < 2; ++par) ring.push_back(int4{l, 0 | (d << 2), par, nc});
-        } else {
-            for (int side = 0; side < 4; ++side)
-                for (int d = 0; d < band; ++d)
-                    for (int par = 0; par < 2; ++par) {
-                        const int lo = (side & 1) ? band : 0, hi = (side & 1) ? nc - band : nc;
-                        for (int a0 = lo + par; a0 < hi; a0 += 128)
-                            ring.push_back(int4{l, side | (d << 2), a0, hi});
-                    }
-        }
-    }
+    pl->exp_elems = w.exp_elems;
+    pl->m2l_tiles.resize(w.tiles.size());
+    if (!w.tiles.empty()) std::memcpy(pl->m2l_tiles.data(), w.tiles.data(), w.tiles.size() * sizeof(M2LItem));
     int st;
     if ((st = build_m2l_items(pl)) != FMM_OK || (st = set_m2l_split(pl, default_m2l_split(pl))) != FMM_OK)
         return st;
-    if (pl->kind == FMM_GRID && pl->bem && !ring.empty()) {
-        pl->n_ring_cells = (int)ring.size();
-        if ((st = upload(pl, &pl->ring_cells, ring))) return st;
-        // boundary cells of every level: targets of the ring charges' P2M
-        std::vector<int4> bc;
-        for (int l = 2; l <= L; ++l) {
-            const int nc = 1 << l;
-            for (int iy = 0; iy < nc; ++iy)
-                for (int ix = 0; ix < nc; ++ix)
-                    if (ix == 0 || iy == 0 || ix == nc - 1 || iy == nc - 1) bc.push_back(int4{l, ix, iy, 0});
-        }
-        pl->n_ring_p2m = (int)bc.size();
-        if ((st = upload(pl, &pl->ring_p2m_cells, bc))) return st;
+    if (ring_lists && !w.ring.empty()) {
+        pl->n_ring_cells = (int)w.ring.size();
+        if ((st = upload_as(pl, &pl->ring_cells, w.ring))) return st;
+        pl->n_ring_p2m = (int)w.ring_p2m.size();
+        if ((st = upload_as(pl, &pl->ring_p2m_cells, w.ring_p2m))) return st;
     }
     return ensure_rhs(pl, 1);
 }
@@ -377,10 +158,7 @@ int ensure_rhs(fmm_plan *pl, int nr)
 
 int default_m2l_split(const fmm_plan *pl)
 {
-    const int tiles = (int)pl->m2l_tiles.size();
-    int split = 1;
-    while (split < 8 && (int64_t)2 * split * tiles < pl->ncu) split *= 2;
-    return split;
+    return host::default_m2l_split((int)pl->m2l_tiles.size(), pl->ncu);
 }
 
 int m2l_split_for(const fmm_plan *pl, int nr)
@@ -390,22 +168,15 @@ int m2l_split_for(const fmm_plan *pl, int nr)
     return split;
 }
 
-// the work items of every split, tile by tile, the shares of one tile next
-// to each other (they read the same sources, which then come from L2)
+// the work items of every split
 static int build_m2l_items(fmm_plan *pl)
 {
+    std::vector<host::I4> tiles(pl->m2l_tiles.size());
+    if (!tiles.empty()) std::memcpy(tiles.data(), pl->m2l_tiles.data(), tiles.size() * sizeof(host::I4));
     for (int e = 0; e < 4; ++e) {
-        const int split = 1 << e;
-        std::vector<M2LItem> items;
-        items.reserve(pl->m2l_tiles.size() * split);
-        for (const M2LItem &t : pl->m2l_tiles)
-            for (int part = 0; part < split; ++part) {
-                M2LItem it = t;
-                it.part = part;
-                items.push_back(it);
-            }
+        const std::vector<host::I4> items = host::m2l_items(tiles, 1 << e);
         if (items.empty()) continue;
-        const int st = upload(pl, &pl->m2l_items[e], items);
+        const int st = upload_as(pl, &pl->m2l_items[e], items);
         if (st != FMM_OK) return st;
     }
     return FMM_OK;

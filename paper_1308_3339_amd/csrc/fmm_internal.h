@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "fmmprec.h"
+#include "host_setup.h"
 
 namespace fmmprec {
 
@@ -43,14 +44,7 @@ constexpr int kMaxRhsChunk = 16;
 // level, radius r = w/sqrt2 each, are well separated when 2r < theta |d| w,
 // i.e. |d|^2 > 2/theta^2; K is the largest k with (k, 0) not separated.
 // theta = 0 selects the interaction lists of the list rule (K = 1).
-inline int near_radius(double theta)
-{
-    if (theta <= 0.0) return 1;
-    const double lim = 2.0 / (theta * theta);
-    int k = 1;
-    while ((double)((k + 1) * (k + 1)) <= lim) ++k;
-    return k;
-}
+inline int near_radius(double theta) { return host::near_radius(theta); }
 
 // The right-hand sides of one launch, selected by blockIdx.z: the grid
 // vectors of right-hand side r start r*sv doubles on, its expansions r*se
@@ -132,11 +126,7 @@ struct fmm_plan {
     int K = 1;
     int kx[fmmprec::kMaxK + 1] = {1, 1, 1, 1, 1};
     int nlist = 27;
-    bool in_near(int dx, int dy) const
-    {
-        if (theta <= 0.0) return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1;
-        return (double)(dx * dx + dy * dy) <= 2.0 / (theta * theta);
-    }
+    bool in_near(int dx, int dy) const { return fmmprec::host::in_near(theta, dx, dy); }
     void set_theta(double t)
     {
         theta = t;
