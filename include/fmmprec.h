@@ -105,6 +105,11 @@ typedef struct {
 
 /* FMM parameters.
  *   p        number of expansion coefficients, M_0..M_{p-1} (Sec. 5.3), 2..20.
+ *            Above 20 the downward pass's LDS (16 (4p^2 + 216p) bytes per
+ *            block, 176 KiB at p = 32) and M2L's source tile (16 p (16 + 4K)^2
+ *            bytes, above 160 KiB for p > 25 with the list rule) outgrow a
+ *            compute unit's 160 KiB; p = 20 already puts the list rule's
+ *            truncation error near 1e-11, three digits above FP64 rounding.
  *   leaf     points per leaf side squared; must be 64 (8 x 8 grid blocks).
  *   prec     fmm_precision (FMM_FP32 for GRID and POINTS plans, FMM_SPLIT_BF16
  *            and FMM_SPLIT_FP16 for GRID plans).
@@ -140,7 +145,14 @@ typedef struct {
 } fmm_params;
 
 /* Krylov parameters: tol > 0 (relative true residual ||b - Ax||/||b||),
- * restart in [1, 32], maxit >= 1 (total inner iterations). */
+ * restart in [1, 32], maxit >= 1 (total inner iterations).  The restart
+ * length is capped at 32 by the Arnoldi sweeps: each step orthogonalises in
+ * one pass over the basis that keeps 2j + 3 FP64 partial sums and j basis
+ * values per lane in registers (about 210 VGPRs at j = 31), and the group
+ * solver keeps each instance's rotated Hessenberg columns, (m + 1) x m
+ * doubles, in one device record.  The FMM-preconditioned iteration counts
+ * of Sec. 6 are 5-7 at every mesh size (Tables 1, 3 and 4; 7-8 here to
+ * 1e-8 up to 2048^2), far inside one cycle of 32; FMM_ERR_ARG otherwise. */
 typedef struct {
     double tol;
     int32_t restart;
@@ -200,7 +212,9 @@ int fmm_precond_stages(fmm_plan *plan, const double *r, double *z, double *phi_r
  * GRID plans only; nrhs grids; w must not alias v. */
 int fmm_stencil_apply(fmm_plan *plan, const double *v, double *w, int nrhs, void *stream);
 
-/* Solves A u = b with right-preconditioned FGMRES(restart) and P^{-1} of
+/* Solves A u = b (Sec. 2.1, eq. axb) with right-preconditioned
+ * FGMRES(restart) -- Sec. 3.1: the preconditioner only enters through its
+ * action, which may change from one iteration to the next -- and P^{-1} of
  * fmm_precond_apply (GRID plans only):
  *   b = f + (boundary values g at the neighbouring ring nodes) / h^2,
  *   f: n*n grid (device); g: 4n ring values (device) or NULL for zero data;
