@@ -544,6 +544,8 @@ def main():
                     help="counter-collection mode: one 512 MiB elementwise y = x*1 (the "
                          "calibration kernel of known size: 512 MiB read, 512 MiB written), "
                          "then 3 FMM applies, 3 preconditioner applies and one solve")
+    ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32", "split_fp16", "split_bf16"),
+                    help="with --probe: the arithmetic of the probed plan")
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="print markdown tables of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
@@ -576,7 +578,12 @@ def main():
     log("setup n=%d p=%d" % (n, p))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = fp.fmm_setup(n=n, p=p, bem=1)
+    precs = {"fp64": fp.FMM_FP64, "fp32": fp.FMM_FP32, "split_fp16": fp.FMM_SPLIT_FP16,
+             "split_bf16": fp.FMM_SPLIT_BF16}
+    if args.prec != "fp64" and not args.probe:
+        print("--prec applies to --probe only: the benchmark solve is FP64", file=sys.stderr)
+        sys.exit(2)
+    plan = fp.fmm_setup(n=n, p=p, bem=1, prec=precs[args.prec])
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log("setup %.3f s" % setup_s)

@@ -1015,7 +1015,14 @@ template <typename H> struct Split16;
 template <> struct Split16<_Float16> {
     typedef _Float16 v8 __attribute__((ext_vector_type(8)));
     static constexpr bool kLoLo = false;
-    __device__ static _Float16 cvt(double x) { return (_Float16)x; }
+    // FP64 -> FP32 -> FP16, each rounded to nearest.  gfx950 has no FP64 ->
+    // FP16 conversion, and the compiler turns a plain double-to-half cast
+    // (even through a float) into the correctly rounded software sequence,
+    // ~40 instructions per value and most of this kernel's VALU work.  A
+    // multiply by `one` (1.0f, not known at compile time) keeps the two
+    // steps apart: v_cvt_f32_f64 + v_fma_mixlo_f16.  The pair stays exact to
+    // lo's rounding, since lo = x - hi is formed in FP64 whatever hi's last bit.
+    __device__ static _Float16 cvt(double x, float one) { return (_Float16)((float)x * one); }
     __device__ static f4_t mfma(v8 a, v8 b, f4_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -1024,7 +1031,9 @@ template <> struct Split16<_Float16> {
 template <> struct Split16<__bf16> {
     typedef __bf16 v8 __attribute__((ext_vector_type(8)));
     static constexpr bool kLoLo = true;
-    __device__ static __bf16 cvt(double x) { return (__bf16)(float)x; }
+    // the same two steps as Split16<_Float16>::cvt (a plain cast is again
+    // folded into one FP64 -> BF16 rounding, done in software)
+    __device__ static __bf16 cvt(double x, float one) { return (__bf16)((float)x * one); }
     __device__ static f4_t mfma(v8 a, v8 b, f4_t c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -1072,16 +1081,18 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     const double tmax = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
     int ex = 0;
     if (tmax > 0.0) (void)frexp(tmax, &ex);          // tmax < 2^ex
+    ex = max(-100, min(100, ex));                     // (float) of both scales stays exact
     const double scale = ldexp(1.0, -ex), iscale = ldexp(1.0, ex);
+    const float one = (float)scale * (float)iscale;   // 1.0f, a run-time value (see Split16)
 #pragma unroll
     for (int i = 0; i < 25; ++i) {
         const int e = tid + 256 * i;
         const int yy = e / 80, xx = e - yy * 80;
         const int at = ((yy >> 3) * 10 + (xx >> 3)) * kQ16Leaf + (yy & 7) * 8 + (xx & 7);
         const double x = v[i] * scale;
-        const H hi = S::cvt(x);
+        const H hi = S::cvt(x, one);
         sqh[at] = hi;
-        sql[at] = S::cvt(x - (double)(float)hi);
+        sql[at] = S::cvt(x - (double)(float)hi, one);
     }
     __syncthreads();
     const int g = lane >> 4, m16 = lane & 15;
