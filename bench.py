@@ -546,6 +546,8 @@ def main():
                          "then 3 FMM applies, 3 preconditioner applies and one solve")
     ap.add_argument("--prec", default="fp64", choices=("fp64", "fp32", "split_fp16", "split_bf16"),
                     help="with --probe: the arithmetic of the probed plan")
+    ap.add_argument("--theta", type=float, default=0.0,
+                    help="with --probe: the MAC theta of the probed plan (0: list rule)")
     ap.add_argument("--trace-summary", metavar="CSV",
                     help="print markdown tables of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
@@ -580,10 +582,11 @@ def main():
     t0 = time.perf_counter()
     precs = {"fp64": fp.FMM_FP64, "fp32": fp.FMM_FP32, "split_fp16": fp.FMM_SPLIT_FP16,
              "split_bf16": fp.FMM_SPLIT_BF16}
-    if args.prec != "fp64" and not args.probe:
-        print("--prec applies to --probe only: the benchmark solve is FP64", file=sys.stderr)
+    if (args.prec != "fp64" or args.theta != 0.0) and not args.probe:
+        print("--prec and --theta apply to --probe only: the benchmark solve is the FP64 "
+              "list-rule plan", file=sys.stderr)
         sys.exit(2)
-    plan = fp.fmm_setup(n=n, p=p, bem=1, prec=precs[args.prec])
+    plan = fp.fmm_setup(n=n, p=p, bem=1, prec=precs[args.prec], theta=args.theta)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     log("setup %.3f s" % setup_s)

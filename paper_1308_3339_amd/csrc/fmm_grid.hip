@@ -872,8 +872,13 @@ __global__ __launch_bounds__(256) void k_leaf_mfma32(LeafArgs a, const float *__
 // there.  LDS: the (8+2K)^2-leaf q tile in FP32 at
 //   (pos/4) * TW*72 + row*72 + (pos%4)*16 + col,   col < TW = 8 + 2K <= 16,
 // so one B read (8 columns x 2 rows x 4 positions) covers the 64 banks once;
-// the kernel table T (side 16K + 15) with rows 80 floats apart (a half-wave's
-// 2 rows x 11 columns of A addresses on distinct banks).  Bounds: row and
+// the kernel table T (side KS = 16K + 15) with rows KS floats apart, so that
+// two blocks share a CU at K = 3 (80.4 KB).  An A read spans 2 rows x 11
+// columns; with the row pitch 63 = -1 (mod 64) at K = 3 the two rows share 10
+// banks, a 2-way conflict.  A conflict-free pitch (11..53 mod 64) needs at
+// least 75 floats per row, which leaves one block per CU; measured at K = 3
+// the conflicts cost 9.7e6 cycles per launch, LDS work in all 13% of the CU
+// cycles while the matrix cores are busy 69% of them.  Bounds: row and
 // column of a B read are ly + K + oy and lx + K + ox, both in [0, TW); a T
 // index dy + 8K + 7 with |dy| <= 8K + 7 stays in [0, 16K + 15).
 template <int P, int K>
