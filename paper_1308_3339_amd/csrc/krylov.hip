@@ -47,8 +47,12 @@ constexpr int kScal = 160;  // norms
 // slot j & 1, so that step j + 1 may run (and copy) while the host reads j's
 constexpr int kHostSlot = 256;
 // a step is issued ahead of the host's decision when the residual estimate is
-// above this multiple of the tolerance (one more step cannot reach it)
+// above this multiple of the tolerance (one more step cannot reach it) or,
+// once a step of the cycle has shown the rate, above kSpecSafety times the
+// largest of the last two per-step reductions (one more step at that rate
+// stays a factor kSpecSafety above the tolerance)
 constexpr double kSpecMargin = 1e3;
+constexpr double kSpecSafety = 4.0;
 
 // Instances of a group solve (many right-hand sides on one plan), selected by
 // blockIdx.y of the vector kernels and by blockIdx.x of the per-instance
@@ -639,7 +643,9 @@ class Fgmres {
     // with spec: step j_ + 1 now, if an estimate of est leaves it certainly needed
     int issue_ahead(double est)
     {
-        if (!spec_ || j_ + 1 >= m_ || iters_ + 2 > maxit_ || !(est > tol_ * kSpecMargin)) return FMM_OK;
+        const double rmax = std::max(red_[0], red_[1]);
+        const double margin = rmax > 1.0 ? std::min(kSpecMargin, kSpecSafety * rmax) : kSpecMargin;
+        if (!spec_ || j_ + 1 >= m_ || iters_ + 2 > maxit_ || !(est > tol_ * margin)) return FMM_OK;
         ahead_ = j_ + 1;
         return launch_step(j_ + 1);
     }
@@ -732,7 +738,12 @@ class Fgmres {
             gg_[c] = cs_[c] * gg_[c];
         }
         ++iters_;
+        const double prev = j == 0 ? beta_ / bnorm_ : est_;
         est_ = std::fabs(gg_[j + 1]) / bnorm_;
+        // the step's reduction of the estimate (the cycle's first step counts
+        // from the residual it restarted from)
+        red_[j & 1] = est_ > 0.0 ? prev / est_ : 0.0;
+        if (j == 0) red_[1] = 0.0;
         return FMM_OK;
     }
 
@@ -767,6 +778,7 @@ class Fgmres {
     Phase phase_ = INIT;
     int iters_ = 0, j_ = 0, status_ = FMM_NOT_CONVERGED;
     double bnorm_ = 0.0, beta_ = 0.0, g0_ = 0.0, rt_prev_ = 0.0, rt_last_ = 0.0, est_ = 1.0;
+    double red_[2] = {0.0, 0.0};   // reductions of the estimate by the last two steps
     gmres_result r_{};
 };
 
