@@ -63,7 +63,8 @@ static int build_tables(fmm_plan *pl)
         (st = upload_as(pl, &pl->tab.hank, t.hank)) || (st = upload_as(pl, &pl->tab.m2l_off, t.offs)) ||
         (st = upload(pl, &pl->tab.m2l_a, t.an)) || (st = upload(pl, &pl->tab.m2l_b, t.bk)) ||
         (st = upload_as(pl, &pl->tab.p2m, t.p2m)) || (st = upload_as(pl, &pl->tab.l2p, t.l2p)) ||
-        (st = upload(pl, &pl->tab.ktab, t.kt)))
+        (st = upload(pl, &pl->tab.ktab, t.kt)) || (st = upload(pl, &pl->tab.m2lt16, t.m2lt16)) ||
+        (st = upload(pl, &pl->tab.m2ltb16, t.m2ltb16)))
         return st;
     return FMM_OK;
 }
@@ -202,7 +203,7 @@ int set_m2l_split(fmm_plan *pl, int split)
 static void release(fmm_plan *pl)
 {
     void *ptrs[] = {pl->tab.ktab32, pl->tab.p2m32, pl->tab.ktab16, pl->tab.p2m16, pl->tab.ktabb16,
-                    pl->tab.p2mb16, pl->tab.hank32, pl->tab.hankl, pl->tab.hankl32, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
+                    pl->tab.p2mb16, pl->tab.hank32, pl->tab.hankl, pl->tab.hankl32, pl->tab.m2lt16, pl->tab.m2ltb16, pl->tab.m2m, pl->tab.l2l, pl->tab.hank, pl->tab.m2l_off, pl->tab.m2l_a, pl->tab.m2l_b,
                     pl->tab.p2m, pl->tab.l2p, pl->tab.ktab, pl->tab.rtab, pl->ws.M, pl->ws.Lt,
                     pl->ws.Lm, pl->ws.M2, pl->ws.Lt2, pl->ws.Lm2, pl->m2l_items[0], pl->m2l_items[1], pl->m2l_items[2], pl->m2l_items[3],
                     pl->ring_cells, pl->ring_p2m_cells, pl->X0, pl->X2, pl->X1, pl->Xh, pl->phi_ring, pl->ring_q,

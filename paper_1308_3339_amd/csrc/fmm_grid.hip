@@ -1186,6 +1186,253 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// M2L of the split 16-bit plans on the matrix cores (Sec. 5.3 item 3 as a
+// dense contraction).  Per list entry e of a parity class, the translation is
+// the real 2P x 2P matrix T_e of  L~_n = sum_k a_n H_{n+k} b_k M~_k  (rows
+// 2n + {Re, Im}, columns 2k + {Re, Im}; the level's log w term of H_0 is
+// added apart, in FP64), built and split into 16-bit pairs at setup, padded
+// to MP rows and KP columns.  For the 64 same-parity target cells of a class
+// (columns) the block computes
+//   D = sum_e T_e S_e,   S_e = the source multipoles at target + offset_e,
+// with the list entries concatenated along K, so that only the rows pad:
+// K step t takes groups 4t..4t+3 of KP/8 = G groups of 8 columns per entry,
+// lane group g = l/16 the group 4t + g (one entry and 8 columns of it).
+// v_mfma_f32_16x16x32_{f16,bf16}: A[l%16][8(l/16)+i], B[8(l/16)+i][l%16],
+// D[4(l/16)+i][l%16].  Operands are pairs x = hi + lo; the sources are
+// scaled per tile by a power of two (|M~| <= 1 on the staged tile) and split
+// here; hi*hi + hi*lo + lo*hi products (BF16 also lo*lo) accumulate in FP32.
+// Block layout as k_m2l: a 16x16 target tile and share item.part of nsplit
+// of the lists, 12 waves = 4 parity classes x 3 thirds of the share, the
+// thirds summed in LDS in a fixed order.  LDS: the tile's sources as [cell]
+// [KP] hi and lo halves, then M~_0 of every cell in FP64 (for the log w term).
+// ---------------------------------------------------------------------------
+// largest share of one class's list a k_m2l_mfma16 block takes (the list
+// rule's 27 entries at split 1)
+constexpr int kM2L16MaxShare = 32;
+
+// dynamic LDS of k_m2l_mfma16 for source tiles of side rw: the staged
+// hi/lo halves and M~_0, or the reduction of the thirds, whichever is larger
+template <int P>
+constexpr size_t m2l16_lds(int rw)
+{
+    constexpr int KP = 8 * ((2 * P + 7) / 8), MT = (2 * P + 15) / 16;
+    const size_t stage = (size_t)rw * rw * (KP * 2 * 2 + 16);
+    const size_t red = (size_t)4 * 64 * 16 * MT * sizeof(float);
+    return stage > red ? stage : red;
+}
+
+template <int P, typename H>
+__global__ __launch_bounds__(768) void k_m2l_mfma16(const M2LItem *__restrict__ items,
+                                                    const double2 *__restrict__ M,
+                                                    double2 *__restrict__ Lm, int64_t lm_part,
+                                                    int nsplit, LevelInfo lv,
+                                                    const H *__restrict__ T,
+                                                    const int4 *__restrict__ offs, int nlist,
+                                                    int halo, RhsSet rh)
+{
+    using S = Split16<H>;
+    typedef typename S::v8 h8;
+    typedef f4_t f4;
+    constexpr int KP = 8 * ((2 * P + 7) / 8), MP = 16 * ((2 * P + 15) / 16);
+    constexpr int MT = MP / 16, G = KP / 8;
+    if (!rhs_active(rh, blockIdx.z)) return;
+    M += blockIdx.z * rh.se;
+    Lm += blockIdx.z * rh.se;
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    __shared__ double smax[12];
+    __shared__ int sdel[4 * kM2L16MaxShare];   // source-cell offset in the tile of each entry of the share
+    const M2LItem it = items[blockIdx.x];
+    const int l = it.level, nc = 1 << l;
+    const int tw = nc < 16 ? nc : 16;
+    const int RW = tw + 2 * halo, RR = RW * RW;
+    const int64_t ncell = (int64_t)nc * nc;
+    H *sh = reinterpret_cast<H *>(sm_raw);                       // [RR][KP] hi
+    H *sl = sh + (size_t)RR * KP;                                // [RR][KP] lo
+    double2 *s0 = reinterpret_cast<double2 *>(sl + (size_t)RR * KP);   // [RR] M~_0
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2 *Ml = M + lv.off[l];
+    // the block's share of each class's list: entries [lo, lo + cnt)
+    const int per = (nlist + nsplit - 1) / nsplit;
+    const int lo = it.part * per, cnt = max(0, min(per, nlist - lo));
+    if (tid < 4 * cnt) {
+        const int w = tid / cnt, e = tid - w * cnt;
+        const int4 od = offs[w * nlist + lo + e];
+        sdel[w * kM2L16MaxShare + e] = od.y * RW + od.x;
+    }
+    // stage: thread r < RR holds the P coefficients of tile cell r
+    double2 v[P];
+    double mx = 0.0;
+    const bool has = tid < RR;
+    {
+        const int sy = has ? tid / RW : 0, sx = has ? tid - sy * RW : 0;
+        const int gx = it.tx0 - halo + sx, gy = it.ty0 - halo + sy;
+        const bool in = has && gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+        const int64_t gi = in ? (int64_t)gy * nc + gx : 0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            v[k] = in ? Ml[k * ncell + gi] : make_double2(0.0, 0.0);
+            mx = fmax(mx, fmax(fabs(v[k].x), fabs(v[k].y)));
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (lane == 0) smax[wave] = mx;
+    __syncthreads();
+    double tmax = 0.0;
+#pragma unroll
+    for (int w = 0; w < 12; ++w) tmax = fmax(tmax, smax[w]);
+    int ex = 0;
+    if (tmax > 0.0) (void)frexp(tmax, &ex);
+    ex = max(-100, min(100, ex));
+    const double scale = ldexp(1.0, -ex), iscale = ldexp(1.0, ex);
+    const float one = (float)scale * (float)iscale;   // 1.0f, a run-time value (see Split16)
+    if (has) {
+        // the cell's 2P values (Re, Im of each coefficient, zero padded to KP)
+        // as pairs, written 8 halves at a time
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            h8 vh, vl;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int kk = 8 * q + i;
+                const double x = kk < 2 * P ? ((kk & 1) ? v[kk >> 1].y : v[kk >> 1].x) * scale : 0.0;
+                const H hx = S::cvt(x, one);
+                vh[i] = hx;
+                vl[i] = S::cvt(x - (double)(float)hx, one);
+            }
+            *(h8 *)&sh[tid * KP + 8 * q] = vh;
+            *(h8 *)&sl[tid * KP + 8 * q] = vl;
+        }
+        s0[tid] = v[0];
+    }
+    __syncthreads();
+    const int cls = wave & 3, grp = wave >> 2;
+    const int px = cls & 1, py = cls >> 1;
+    const int col = lane & 15, g = lane >> 4;
+    // the four target cells of this lane (one per 16-column tile j) and the
+    // base of their source cells in the staged tile
+    int cbase[4];
+    bool act[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int c = 16 * j + col;
+        const int ltx = 2 * (c & 7) + px, lty = 2 * (c >> 3) + py;
+        act[j] = ltx < tw && lty < tw;
+        cbase[j] = (lty + halo) * RW + ltx + halo;
+    }
+    // this wave's entries: third grp of the block's share of the list
+    const int chunk = (cnt + 2) / 3;
+    const int e0 = lo + grp * chunk;
+    const int nown = max(0, min(chunk, cnt - grp * chunk));
+    const int ngroups = nown * G, nsteps = (ngroups + 3) / 4;
+    const int *dl = sdel + cls * kM2L16MaxShare;   // dl[e - lo], e in [lo, lo + cnt)
+    const size_t lo_half = (size_t)4 * nlist * MP * KP;   // the lo parts follow the hi parts
+    f4 acc[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[mt][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < nsteps; ++t) {
+        const int gi = 4 * t + g;
+        const bool valid = gi < ngroups;
+        const int e = e0 + (valid ? gi / G : 0), q = valid ? gi % G : 0;
+        const int sd = dl[e - lo];
+        h8 ah[MT], al[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const size_t ai = ((size_t)(cls * nlist + e) * MP + 16 * mt + col) * KP + 8 * q;
+            ah[mt] = *(const h8 *)&T[ai];
+            al[mt] = *(const h8 *)&T[lo_half + ai];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            h8 bh, bl;
+            if (valid && act[j]) {
+                const int si = (cbase[j] + sd) * KP + 8 * q;
+                bh = *(const h8 *)&sh[si];
+                bl = *(const h8 *)&sl[si];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bh[i] = S::cvt(0.0, one);
+                    bl[i] = S::cvt(0.0, one);
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                if constexpr (S::kLoLo) acc[mt][j] = S::mfma(al[mt], bl, acc[mt][j]);
+                acc[mt][j] = S::mfma(ah[mt], bl, acc[mt][j]);
+                acc[mt][j] = S::mfma(al[mt], bh, acc[mt][j]);
+                acc[mt][j] = S::mfma(ah[mt], bh, acc[mt][j]);
+            }
+        }
+    }
+    // the log w term of H_0 adds log w * sum_e M~_0(source) to L~_0 (D rows
+    // 0, 1: lanes of group 0), each wave over its own entries, summed in FP64
+    // and added to the FP32 accumulators at the tile's scale before the
+    // thirds are summed (and before that sum reuses the LDS)
+    if (g == 0) {
+        const double lws = lv.logw[l] * scale;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double cx = 0.0, cy = 0.0;
+#pragma unroll
+            for (int ee = 0; ee < (kM2L16MaxShare + 2) / 3; ++ee)
+                if (ee < nown && act[j]) {
+                    const double2 m0 = s0[cbase[j] + dl[e0 + ee - lo]];
+                    cx += m0.x;
+                    cy += m0.y;
+                }
+            acc[0][j][0] += (float)(lws * cx);
+            acc[0][j][1] += (float)(lws * cy);
+        }
+    }
+    // sum the three thirds: (third 0 + third 1) + third 2, through the
+    // source region of LDS, component-major ([16 MT][4 classes x 64 lanes]
+    // floats, so that a wave's 64 lanes write 64 consecutive words)
+    float *red = reinterpret_cast<float *>(sm_raw);
+    const int slot = cls * 64 + lane;
+    for (int gg = 1; gg < 3; ++gg) {
+        __syncthreads();
+        if (grp == gg) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) red[((mt * 4 + j) * 4 + i) * 256 + slot] = acc[mt][j][i];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[mt][j][i] += red[((mt * 4 + j) * 4 + i) * 256 + slot];
+        }
+    }
+    if (grp != 0) return;
+    // rows 16 mt + 4 g + i of D: coefficient n = row / 2, (Re, Im) = row & 1
+    double2 *out = Lm + it.part * lm_part + lv.off[l];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!act[j]) continue;
+        const int c = 16 * j + col;
+        const int tx = it.tx0 + 2 * (c & 7) + px, ty = it.ty0 + 2 * (c >> 3) + py;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; i += 2) {
+                const int row = 16 * mt + 4 * g + i, n = row >> 1;
+                if (n >= P) continue;
+                out[n * ncell + (int64_t)ty * nc + tx] =
+                    make_double2(iscale * (double)acc[mt][j][i], iscale * (double)acc[mt][j][i + 1]);
+            }
+    }
+}
+
 // Lattice coordinates (in units of h) of ring node t (counter-clockwise).
 __device__ __forceinline__ void ring_node(int t, int n, int &Ix, int &Iy)
 {
@@ -1703,9 +1950,22 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
     const M2LItem *items = pl->m2l_items[ns == 1 ? 0 : ns == 2 ? 1 : ns == 4 ? 2 : 3];
     if (nitems > 0) {
         StageTimer t(pl, timed ? FMM_STAGE_M2L : -1, s);
-        // reduced-precision grid plans translate in FP32; point clouds take only
-        // their near field in FP32 (Sec. 7.1) and keep M2L in FP64
-        if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
+        // split 16-bit grid plans translate on the matrix cores, FP32 grid plans
+        // in FP32; point clouds take only their near field in FP32 (Sec. 7.1)
+        // and keep M2L in FP64
+        const bool split16 = (pl->prec == FMM_SPLIT_FP16 || pl->prec == FMM_SPLIT_BF16) &&
+                             pl->kind == FMM_GRID && pl->K == 1 && pl->nlist <= kM2L16MaxShare;
+        if (split16) {
+            const size_t shm16 = m2l16_lds<P>(rw);
+            if (pl->prec == FMM_SPLIT_FP16)
+                hipLaunchKernelGGL((k_m2l_mfma16<P, _Float16>), dim3(nitems, 1, nr), dim3(768), shm16, s,
+                                   items, M, Lm, pl->lm_part, ns, pl->lv, pl->tab.m2lt16,
+                                   pl->tab.m2l_off, pl->nlist, 2 * pl->K, rh);
+            else
+                hipLaunchKernelGGL((k_m2l_mfma16<P, __bf16>), dim3(nitems, 1, nr), dim3(768), shm16, s,
+                                   items, M, Lm, pl->lm_part, ns, pl->lv, pl->tab.m2ltb16,
+                                   pl->tab.m2l_off, pl->nlist, 2 * pl->K, rh);
+        } else if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
             hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(768), shm / 2, s, items, M,
                                Lm, pl->lm_part, ns, pl->lv, pl->tab.hankl32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
@@ -1966,6 +2226,11 @@ static int m2l_attr_p(fmm_plan *pl)
                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm));
     FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l<P, float>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm / 2));
+    const int shm16 = (int)m2l16_lds<P>(rw);
+    FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l_mfma16<P, _Float16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, shm16));
+    FMM_HIP(pl, hipFuncSetAttribute((const void *)k_m2l_mfma16<P, __bf16>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, shm16));
     high[P] = shm;
     return FMM_OK;
 }

@@ -95,6 +95,8 @@ struct FmmTables {
     float2 *hank32;   // FP32 copy of hank (precision variant)
     double2 *hankl;   // [4 parity classes][nlist][2p-1]: hank of each list entry, in list order
     float2 *hankl32;  // FP32 copy of hankl
+    _Float16 *m2lt16; // matrix-core M2L operators of the list entries, FP16 hi then lo parts
+    __bf16 *m2ltb16;  // the same as BF16 pairs
 };
 
 struct Workspace {

@@ -240,6 +240,26 @@ bool build_tables(int p, double theta, double h, double self_eps, Tables &t, std
                 split16(v, t.kt16[((size_t)c * 31 + r) * 40 + j], t.kt16[((size_t)(8 + c) * 31 + r) * 40 + j]);
                 splitb16(v, t.ktb16[((size_t)c * 31 + r) * 40 + j], t.ktb16[((size_t)(8 + c) * 31 + r) * 40 + j]);
             }
+    // matrix-core M2L operators (see Tables::m2lt16)
+    t.m2l_mp = 16 * ((2 * p + 15) / 16);
+    t.m2l_kp = 8 * ((2 * p + 7) / 8);
+    const size_t nent = t.offs.size(), esz = (size_t)t.m2l_mp * t.m2l_kp;
+    t.m2lt16.assign(2 * nent * esz, (_Float16)0.0f);
+    t.m2ltb16.assign(2 * nent * esz, to_bf16(0.0));
+    for (size_t e = 0; e < nent; ++e)
+        for (int nn = 0; nn < p; ++nn)
+            for (int k = 0; k < p; ++k) {
+                const C2 hv = t.hankl[e * nh + nn + k];
+                const cd tv = t.an[nn] * cd(hv.x, hv.y) * t.bk[k];
+                // (Re L, Im L) += [[Re T, -Im T], [Im T, Re T]] (Re M, Im M)
+                const double v[2][2] = {{tv.real(), -tv.imag()}, {tv.imag(), tv.real()}};
+                for (int r = 0; r < 2; ++r)
+                    for (int c = 0; c < 2; ++c) {
+                        const size_t i = e * esz + (size_t)(2 * nn + r) * t.m2l_kp + 2 * k + c;
+                        split16(v[r][c], t.m2lt16[i], t.m2lt16[nent * esz + i]);
+                        splitb16(v[r][c], t.m2ltb16[i], t.m2ltb16[nent * esz + i]);
+                    }
+            }
     t.hank32.resize(t.hank.size());
     t.hankl32.resize(t.hankl.size());
     for (size_t i = 0; i < t.hank.size(); ++i) t.hank32[i] = F2{(float)t.hank[i].x, (float)t.hank[i].y};

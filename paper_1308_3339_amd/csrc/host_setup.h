@@ -50,6 +50,15 @@ struct Tables {
     std::vector<_Float16> kt16, p2m16;   // split FP16 halves
     std::vector<__bf16> ktb16, p2mb16;   // split BF16 halves
     std::vector<F2> hank32, hankl32;
+    // M2L operators of the list entries for the split 16-bit matrix-core
+    // M2L: entry e of class w as the real 2p x 2p matrix of
+    //   L~_n = sum_k a_n H_{n+k} b_k M~_k      (H_0 without the level's log w)
+    // rows 2n + {Re, Im}, columns 2k + {Re, Im} of M~_k, padded to m2l_mp
+    // rows and m2l_kp columns; [w][e][m2l_mp][m2l_kp] halves, the hi parts,
+    // then the lo parts (x = hi + lo)
+    int m2l_mp = 0, m2l_kp = 0;
+    std::vector<_Float16> m2lt16;
+    std::vector<__bf16> m2ltb16;
 };
 
 // Fills t; returns false with a message in err when the interaction lists
