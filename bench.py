@@ -725,7 +725,9 @@ def main():
         leaf_ms_v, leaf_n_v = prof.get("LEAF", (0.0, 0))
         avg = leaf_ms_v / max(leaf_n_v, 1)
         ach = flops / (avg * 1e-3) / 1e12
-        # M2L in FP32 on the vector ALU (k_m2l<P, float>): 8 p^2 flops per translation
+        # M2L: 8 p^2 algorithmic flops per translation; in FP32 on the vector
+        # ALU (k_m2l<P, float>) for FP32 plans, on the 16-bit matrix cores
+        # (k_m2l_mfma16, the same hi/lo products as the near field) for split plans
         m2l_ms_v, m2l_n_v = prof.get("M2L", (0.0, 0))
         m2l_avg = m2l_ms_v / max(m2l_n_v, 1)
         m2l_flops = 8.0 * p * p * m2l_translations((n // 8).bit_length() - 1)
@@ -740,14 +742,20 @@ def main():
                                   "achieved": round(ach, 3), "unit": "TFLOP/s",
                                   "mfma_flops_per_algorithmic_flop": mfma_per_flop,
                                   "peak": peak, "frac": round(ach * mfma_per_flop / peak, 4)},
-                "m2l_roofline": {"bound": "alu", "kernel": "k_m2l<P, float>",
-                                 "avg_call_ms": round(m2l_avg, 5), "achieved": round(m2l_ach, 3),
-                                 "unit": "TFLOP/s", "peak": PEAK_FP32_VALU_TFLOPS,
-                                 "frac": round(m2l_ach / PEAK_FP32_VALU_TFLOPS, 4),
-                                 # the library is built without packed FP32 instructions,
-                                 # which halves the vector FP32 rate it can issue
-                                 "peak_unpacked": PEAK_FP32_VALU_TFLOPS / 2,
-                                 "frac_unpacked": round(2 * m2l_ach / PEAK_FP32_VALU_TFLOPS, 4)}}
+                "m2l_roofline": (
+                    {"bound": "mfma", "kernel": "k_m2l_mfma16<P, %s>" % ("bf16" if "BF16" in label.upper() else "f16"),
+                     "avg_call_ms": round(m2l_avg, 5), "achieved": round(m2l_ach, 3),
+                     "unit": "TFLOP/s", "mfma_flops_per_algorithmic_flop": mfma_per_flop,
+                     "peak": peak, "frac": round(m2l_ach * mfma_per_flop / peak, 4)}
+                    if prec in (fp.FMM_SPLIT_FP16, fp.FMM_SPLIT_BF16) else
+                    {"bound": "alu", "kernel": "k_m2l<P, float>",
+                     "avg_call_ms": round(m2l_avg, 5), "achieved": round(m2l_ach, 3),
+                     "unit": "TFLOP/s", "peak": PEAK_FP32_VALU_TFLOPS,
+                     "frac": round(m2l_ach / PEAK_FP32_VALU_TFLOPS, 4),
+                     # the library is built without packed FP32 instructions,
+                     # which halves the vector FP32 rate it can issue
+                     "peak_unpacked": PEAK_FP32_VALU_TFLOPS / 2,
+                     "frac_unpacked": round(2 * m2l_ach / PEAK_FP32_VALU_TFLOPS, 4)})}
 
     def mac_block(p_t, theta, prec=fp.FMM_FP64):
         """MAC theta (Sec. 5.2): the 2048^2 solve with the dual tree
@@ -824,11 +832,13 @@ def main():
     variant = variant_block(fp.FMM_FP32, "P2P and P2M as FP32 MFMA contractions, M2L in FP32; "
                             "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 157.3, 1, "fp32")
     variant16 = variant_block(fp.FMM_SPLIT_FP16, "P2P and P2M as FP16 hi+lo MFMA products "
-                              "(hi*hi + hi*lo + lo*hi, FP32 accumulation), M2L in FP32; M2M, L2L, "
+                              "(hi*hi + hi*lo + lo*hi, FP32 accumulation), M2L as the same products of "
+                              "the list translations on the matrix cores; M2M, L2L, "
                               "L2P, boundary, stencil, Arnoldi FP64", 2500.0, 3, "split_fp16")
     variantb16 = variant_block(fp.FMM_SPLIT_BF16, "P2P and P2M as BF16 hi+lo MFMA products "
-                               "(hi*hi + hi*lo + lo*hi + lo*lo, FP32 accumulation), M2L in FP32; "
-                               "M2M, L2L, L2P, boundary, stencil, Arnoldi FP64", 2500.0, 4,
+                               "(hi*hi + hi*lo + lo*hi + lo*lo, FP32 accumulation), M2L as the same "
+                               "products on the matrix cores; M2M, L2L, L2P, boundary, stencil, "
+                               "Arnoldi FP64", 2500.0, 4,
                                "split_bf16")
     log("fp32 variant %.2f solves/s, split-fp16 %.2f, split-bf16 %.2f" % (
         variant["solves_per_s"], variant16["solves_per_s"], variantb16["solves_per_s"]))

@@ -68,10 +68,12 @@ typedef enum { FMM_GRID = 0, FMM_POINTS = 1 } fmm_kind;
  * polynomial fit of log2(x)/(x - 1), Kahan-compensated sums; pairs whose
  * FP32 r^2 is below the smallest normal float are left out like the self
  * pair); P2M, M2M, M2L, L2L and L2P stay FP64.
- * FMM_SPLIT_FP16 (GRID plans): as FMM_FP32, but the near field and P2M take
- * each operand as an FP16 pair x = hi + lo (charges scaled per tile by a
- * power of two) and sum hi*hi + hi*lo + lo*hi on the FP16 matrix cores with
- * FP32 accumulation (about 2^-22 relative per product).
+ * FMM_SPLIT_FP16 (GRID plans): as FMM_FP32, but the near field, P2M and the
+ * multipole-to-local translations take each operand as an FP16 pair
+ * x = hi + lo (charges and multipoles scaled per tile by a power of two, the
+ * translation operators split at setup) and sum hi*hi + hi*lo + lo*hi on the
+ * FP16 matrix cores with FP32 accumulation (about 2^-22 relative per
+ * product).
  * FMM_SPLIT_BF16 (GRID plans): the same with BF16 pairs on the BF16 matrix
  * cores, summing all four products hi*hi + hi*lo + lo*hi + lo*lo (about
  * 2^-16 relative per product, the pairs' representation error).
