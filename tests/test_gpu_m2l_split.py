@@ -149,3 +149,39 @@ def test_split_rejects_bad_values():
                 plan.set_m2l_split(bad)
             assert ei.value.code == fp.FMM_ERR_ARG
         assert plan.m2l_split in SPLITS
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["FMM_SPLIT_FP16", "FMM_SPLIT_BF16"])
+def test_matrix_core_m2l_every_split_and_stacked(name):
+    """The split 16-bit plans' M2L on the matrix cores: each split against the
+    FP64 oracle FMM (the stage bar of the split plans), the splits and a
+    stacked three-RHS call against the single calls to FP32 rounding."""
+    import paper_1308_3339_amd as fp
+    n, p = 256, 10
+    bar = 1e-5 if name == "FMM_SPLIT_FP16" else 5e-5
+    say("case matrix-core M2L %s n=%d" % (name, n))
+    Q = np.stack([inputs.random_charges(n * n, seed=3400 + k) for k in range(3)])
+    uo = o.grid_fmm(n, p, Q[0])
+    with fp.fmm_setup(n=n, p=p, bem=0, prec=getattr(fp, name)) as plan:
+        out = {}
+        for split in SPLITS:
+            plan.set_m2l_split(split)
+            u = empty(n * n)
+            plan.apply(dev(Q[0]), u)
+            out[split] = host(u)
+            err = relmax(out[split], uo)
+            say("  split %d: max rel err vs oracle %.3e" % (split, err))
+            assert err <= bar
+        for split in SPLITS[1:]:
+            assert relmax(out[split], out[1]) <= 2e-6
+        plan.set_m2l_split(4)
+        U = empty(3 * n * n)
+        plan.apply(dev(Q.reshape(-1)), U, nrhs=3)
+        Ug = host(U).reshape(3, -1)
+        for k in range(3):
+            u = empty(n * n)
+            plan.apply(dev(Q[k]), u)
+            d = relmax(Ug[k], host(u))
+            say("  stacked rhs %d vs single: %.3e" % (k, d))
+            assert d <= 2e-6
