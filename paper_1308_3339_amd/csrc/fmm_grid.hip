@@ -96,10 +96,11 @@ __device__ __forceinline__ void m2m_tile(const double2 *__restrict__ sA,
                                          const double2 *__restrict__ child,
                                          double2 *__restrict__ parent, int cw)
 {
-    const int pw = cw >> 1, np = pw * pw, nch = cw * cw;
+    // cw is a power of two: indices by shifts
+    const int pw = cw >> 1, np = pw * pw, nch = cw * cw, lpw = __builtin_ctz(pw);
     for (int t = threadIdx.x; t < np * P; t += blockDim.x) {
-        const int nn = t / np, pc = t - nn * np;
-        const int px = pc % pw, py = pc / pw;
+        const int nn = t >> (2 * lpw), pc = t & (np - 1);
+        const int px = pc & (pw - 1), py = pc >> lpw;
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
         for (int qd = 0; qd < 4; ++qd) {
@@ -118,11 +119,11 @@ template <int P>
 __device__ __forceinline__ void store_tile(const double2 *__restrict__ src, double2 *__restrict__ Ml,
                                            int nc, int x0, int y0, int tw)
 {
-    const int cnt = tw * tw;
+    const int cnt = tw * tw, ltw = __builtin_ctz(tw);   // tw is a power of two
     const int64_t ncell = (int64_t)nc * nc;
     for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
-        const int k = t / cnt, c = t - k * cnt;
-        Ml[k * ncell + (int64_t)(y0 + c / tw) * nc + x0 + c % tw] = src[t];
+        const int k = t >> (2 * ltw), c = t & (cnt - 1);
+        Ml[k * ncell + (int64_t)(y0 + (c >> ltw)) * nc + x0 + (c & (tw - 1))] = src[t];
     }
 }
 
@@ -193,18 +194,22 @@ __global__ __launch_bounds__(256) void k_m2m_up(double2 *__restrict__ M,
 // entries with the list rule, more with a MAC theta).  Splitting the lists
 // gives small trees enough blocks: a 1024^2 grid has 87 tiles for 256
 // compute units.  Sources (the tile plus a halo of 2K cells, 20x20 for
-// K = 1) are staged once in LDS, split by parity, each parity sub-grid
-// column-major: a 16-byte read of 8 columns x 2 rows of a wave's cells then
-// puts its 16 lanes on 16 distinct 16-byte bank groups (column stride
-// RH = 10, even, and rows one apart); the three thirds are summed in LDS in
-// a fixed order.  R is the arithmetic type of the translation (double, or
+// K = 1) are staged once in LDS, a thread per source cell with its P
+// coefficients (64 KB at p = 10, so two blocks share a compute unit), split
+// by parity, each parity sub-grid column-major: a 16-byte read of 8 columns
+// x 2 rows of a wave's cells then puts its 16 lanes on 16 distinct 16-byte
+// bank groups (column stride RH = 10, even, and rows one apart); the three
+// thirds are summed in LDS in a fixed order.  R is the arithmetic type of the translation (double, or
 // float for the FP32 variant; the level-scaled expansions and generators
 // stay far inside FP32 range for p <= 20), inputs and outputs are FP64.
 // hank holds the generators in list order ([class][entry][2P-1]), so the
 // address of an entry's generators does not wait for its offset to load.
 // ---------------------------------------------------------------------------
+constexpr int kM2LGroups = 3;   // list groups per parity class in a k_m2l block
+constexpr int kM2LThreads = 256 * kM2LGroups;
+
 template <int P, typename R>
-__global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
+__global__ __launch_bounds__(kM2LThreads) void k_m2l(const M2LItem *__restrict__ items,
                                              const double2 *__restrict__ M,
                                              double2 *__restrict__ Lm, int64_t lm_part,
                                              int nsplit, LevelInfo lv,
@@ -226,31 +231,24 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
     const int RW = tw + 2 * halo, RH = RW >> 1, SUB = RH * RH, RR = RW * RW;
     const int64_t ncell = (int64_t)nc * nc;
     const double2 *Ml = M + lv.off[l];
-    for (int e0 = threadIdx.x; e0 < P * RR; e0 += 768 * 6) {
-        double2 v[6];
+    // stage: a thread takes one source cell and its P coefficients (one
+    // division per cell, P loads in flight)
+    for (int r = threadIdx.x; r < RR; r += kM2LThreads) {
+        const int sy = r / RW, sx = r - sy * RW;
+        const int gx = it.tx0 - halo + sx, gy = it.ty0 - halo + sy;
+        const bool in = gx >= 0 && gx < nc && gy >= 0 && gy < nc;
+        const int64_t gi = in ? (int64_t)gy * nc + gx : 0;
+        double2 v[P];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            const int e = e0 + 768 * i;
-            v[i] = make_double2(0.0, 0.0);
-            if (e < P * RR) {
-                const int k = e / RR, r = e - k * RR;
-                const int sy = r / RW, sx = r - sy * RW;
-                const int gx = it.tx0 - halo + sx, gy = it.ty0 - halo + sy;
-                if (gx >= 0 && gx < nc && gy >= 0 && gy < nc) v[i] = Ml[k * ncell + (int64_t)gy * nc + gx];
-            }
-        }
+        for (int k = 0; k < P; ++k) v[k] = in ? Ml[k * ncell + gi] : make_double2(0.0, 0.0);
+        const int si = ((sy & 1) * 2 + (sx & 1)) * SUB + (sx >> 1) * RH + (sy >> 1);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            const int e = e0 + 768 * i;
-            if (e < P * RR) {
-                const int k = e / RR, r = e - k * RR;
-                const int sy = r / RW, sx = r - sy * RW;
-                const double bk = b_k[k];
-                C c;
-                c.x = (R)(v[i].x * bk);
-                c.y = (R)(v[i].y * bk);
-                sm[k * RR + ((sy & 1) * 2 + (sx & 1)) * SUB + (sx >> 1) * RH + (sy >> 1)] = c;
-            }
+        for (int k = 0; k < P; ++k) {
+            const double bk = b_k[k];
+            C c;
+            c.x = (R)(v[k].x * bk);
+            c.y = (R)(v[k].y * bk);
+            sm[k * RR + si] = c;
         }
     }
     __syncthreads();
@@ -264,10 +262,10 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k].x = acc[k].y = (R)0;
     const R logw = (R)lv.logw[l];
-    // this block's share of the list: entries [lo, lo + cnt), in thirds
+    // this block's share of the list: entries [lo, lo + cnt), in groups
     const int per = (nlist + nsplit - 1) / nsplit;
     const int lo = it.part * per, cnt = max(0, min(per, nlist - lo));
-    const int chunk = (cnt + 2) / 3;
+    const int chunk = (cnt + kM2LGroups - 1) / kM2LGroups;
     const int4 *ol = offs + cls * nlist + lo + grp * chunk;
     const C *Hl = hank + (size_t)(cls * nlist + lo + grp * chunk) * (2 * P - 1);
     const int nown = max(0, min(chunk, cnt - grp * chunk));
@@ -291,9 +289,9 @@ __global__ __launch_bounds__(768) void k_m2l(const M2LItem *__restrict__ items,
             }
         }
     }
-    // sum the three list thirds: (third 0 + third 1) + third 2
+    // sum the groups in order: ((group 0 + group 1) + group 2) + ...
     const int slot = cls * 64 + lane;
-    for (int g = 1; g < 3; ++g) {
+    for (int g = 1; g < kM2LGroups; ++g) {
         __syncthreads();
         if (grp == g && active) {
 #pragma unroll
@@ -433,8 +431,8 @@ __device__ __forceinline__ double2 *down_levels(const double2 *__restrict__ Lm, 
         double2 *next = (st & 1) ? buf1 : buf0;
         const int pcnt = pw * pw;
         for (int t = threadIdx.x; t < P * cnt; t += blockDim.x) {
-            const int nn = t / cnt, c = t - nn * cnt;
-            const int cx = c % tw, cy = c / tw;
+            const int nn = t >> (2 * st), c = t & (cnt - 1);
+            const int cx = c & (tw - 1), cy = c >> st;
             const int pc = (cy >> 1) * pw + (cx >> 1), qd = (cy & 1) * 2 + (cx & 1);
             double2 acc = sm2l[nn * 84 + base + c];
             const double2 *Br = sB + (qd * P + nn) * P;
@@ -1045,12 +1043,19 @@ template <> struct Split16<__bf16> {
     }
 };
 
+// One block per CU-slot loops over the 8 x 8-leaf tiles t = blockIdx.x,
+// blockIdx.x + gridDim.x, ... (ntx tiles per row, ntiles in all): the kernel
+// table is staged once per block, and the next tile's charges are loaded
+// into registers while the current tile's products run.  A thread holds row
+// segments sg = tid + 256 i (i < 4, sg < 800) of the 80 x 80 q tile, 8
+// consecutive nodes of one leaf row each, and writes each segment's halves
+// as one 16-byte store.
 template <int P, typename H>
 __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__restrict__ kt16,
-                                                     const H *__restrict__ w16)
+                                                     const H *__restrict__ w16, int ntx, int ntiles)
 {
     const LeafPtrs pp = rhs_ptrs(a);
-    if (!pp.on) return;
+    if (!pp.on || (int)blockIdx.x >= ntiles) return;
     using S = Split16<H>;
     typedef typename S::v8 h8;
     typedef f4_t f4;
@@ -1061,18 +1066,6 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
-    const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
-    const int X0 = (TX0 - 1) * 8, Y0 = (TY0 - 1) * 8;
-    double v[25];
-    double mx = 0.0;
-#pragma unroll
-    for (int i = 0; i < 25; ++i) {
-        const int e = tid + 256 * i;
-        const int yy = e / 80, xx = e - yy * 80;
-        const int gx = X0 + xx, gy = Y0 + yy;
-        v[i] = (gx >= 0 && gx < n && gy >= 0 && gy < n) ? pp.q[(size_t)gy * n + gx] : 0.0;
-        mx = fmax(mx, fabs(v[i]));
-    }
     // kernel table: 2 x 8 copies of 31 rows x 40 halves, copied in 16-byte units
     for (int e = tid; e < 2 * 8 * 31 * 5; e += 256) {
         const int part = e / (8 * 31 * 5), rem = e - part * (8 * 31 * 5);
@@ -1080,109 +1073,144 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
         *(h8 *)&st[part][c * kT16Pitch + r * kT16Row + 8 * q8] =
             *(const h8 *)&kt16[((size_t)(part * 8 + c) * 31 + r) * kT16Row + 8 * q8];
     }
-    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-    if (lane == 0) smax[wave] = mx;
-    __syncthreads();
-    const double tmax = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
-    int ex = 0;
-    if (tmax > 0.0) (void)frexp(tmax, &ex);          // tmax < 2^ex
-    ex = max(-100, min(100, ex));                     // (float) of both scales stays exact
-    const double scale = ldexp(1.0, -ex), iscale = ldexp(1.0, ex);
-    const float one = (float)scale * (float)iscale;   // 1.0f, a run-time value (see Split16)
+    double v[4][8];
+    auto load = [&](int t) {
+        const int X0 = ((t % ntx) * 8 - 1) * 8, Y0 = ((t / ntx) * 8 - 1) * 8;
 #pragma unroll
-    for (int i = 0; i < 25; ++i) {
-        const int e = tid + 256 * i;
-        const int yy = e / 80, xx = e - yy * 80;
-        const int at = ((yy >> 3) * 10 + (xx >> 3)) * kQ16Leaf + (yy & 7) * 8 + (xx & 7);
-        const double x = v[i] * scale;
-        const H hi = S::cvt(x, one);
-        sqh[at] = hi;
-        sql[at] = S::cvt(x - (double)(float)hi, one);
-    }
-    __syncthreads();
-    const int g = lane >> 4, m16 = lane & 15;
-    const int nloc = 16 * wave + m16;
-    const int lx = nloc & 7, ly = nloc >> 3;
-    // A: target t = 16 mt + m16 (tx = lane & 7, ty = 2 mt + ((lane >> 3) & 1)),
-    //    source rows sy = 4 ks + g, columns from 8 ox - tx + 15 in copy 7 - tx
-    const int tx = lane & 7, tyb = (lane >> 3) & 1;
-    const int abase = (7 - tx) * kT16Pitch + (15 - tyb + g) * kT16Row + 8;
-    const int bbase = ((ly + 1) * 10 + lx + 1) * kQ16Leaf + 8 * g;
-    double acc[4][4];
+        for (int i = 0; i < 4; ++i) {
+            const int sg = tid + 256 * i, yy = sg / 10, gy = Y0 + yy;
+            const int gx0 = X0 + 8 * (sg - yy * 10);
+            const bool rowin = sg < 800 && gy >= 0 && gy < n;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
-#pragma unroll 1
-    for (int o = 0; o < 9; ++o) {
-        const int oy = o / 3 - 1, ox = o % 3 - 1;
-        f4 c[4];
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-        const int boff = bbase + (oy * 10 + ox) * kQ16Leaf;
-        const int aoff = abase + 8 * oy * kT16Row + 8 * ox;
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const h8 bh = *(const h8 *)&sqh[boff + 32 * ks];
-            const h8 bl = *(const h8 *)&sql[boff + 32 * ks];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int ai = aoff + (4 * ks - 2 * mt) * kT16Row;
-                const h8 ah = *(const h8 *)&st[0][ai];
-                const h8 al = *(const h8 *)&st[1][ai];
-                if constexpr (S::kLoLo) c[mt] = S::mfma(al, bl, c[mt]);
-                c[mt] = S::mfma(ah, bl, c[mt]);
-                c[mt] = S::mfma(al, bh, c[mt]);
-                c[mt] = S::mfma(ah, bh, c[mt]);
+            for (int j = 0; j < 8; ++j) {
+                const int gx = gx0 + j;
+                v[i][j] = (rowin && gx >= 0 && gx < n) ? pp.q[(size_t)gy * n + gx] : 0.0;
             }
         }
-#pragma unroll
+    };
+    load(blockIdx.x);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int TX0 = (t % ntx) * 8, TY0 = (t / ntx) * 8;
+        double mx = 0.0;
+    #pragma unroll
+        for (int i = 0; i < 4; ++i)
+    #pragma unroll
+            for (int j = 0; j < 8; ++j) mx = fmax(mx, fabs(v[i][j]));
+        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+        if (lane == 0) smax[wave] = mx;
+        // (the previous tile's reads of the q tile and of smax are done)
+        __syncthreads();
+        const double tmax = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+        int ex = 0;
+        if (tmax > 0.0) (void)frexp(tmax, &ex);          // tmax < 2^ex
+        ex = max(-100, min(100, ex));                     // (float) of both scales stays exact
+        const double scale = ldexp(1.0, -ex), iscale = ldexp(1.0, ex);
+        const float one = (float)scale * (float)iscale;   // 1.0f, a run-time value (see Split16)
+    #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int sg = tid + 256 * i;
+            if (sg < 800) {
+                const int yy = sg / 10, jx = sg - yy * 10;
+                const int at = ((yy >> 3) * 10 + jx) * kQ16Leaf + (yy & 7) * 8;
+                h8 vh, vl;
+    #pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const double x = v[i][j] * scale;
+                    const H hi = S::cvt(x, one);
+                    vh[j] = hi;
+                    vl[j] = S::cvt(x - (double)(float)hi, one);
+                }
+                *(h8 *)&sqh[at] = vh;
+                *(h8 *)&sql[at] = vl;
+            }
+        }
+        __syncthreads();
+        if (t + (int)gridDim.x < ntiles) load(t + gridDim.x);
+        const int g = lane >> 4, m16 = lane & 15;
+        const int nloc = 16 * wave + m16;
+        const int lx = nloc & 7, ly = nloc >> 3;
+        // A: target t = 16 mt + m16 (tx = lane & 7, ty = 2 mt + ((lane >> 3) & 1)),
+        //    source rows sy = 4 ks + g, columns from 8 ox - tx + 15 in copy 7 - tx
+        const int tx = lane & 7, tyb = (lane >> 3) & 1;
+        const int abase = (7 - tx) * kT16Pitch + (15 - tyb + g) * kT16Row + 8;
+        const int bbase = ((ly + 1) * 10 + lx + 1) * kQ16Leaf + 8 * g;
+        double acc[4][4];
+    #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
-    }
-    f4 pm[MTP];
-#pragma unroll
-    for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (pp.M) {
-#pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const h8 bh = *(const h8 *)&sqh[bbase + 32 * ks];
-            const h8 bl = *(const h8 *)&sql[bbase + 32 * ks];
-#pragma unroll
-            for (int mt = 0; mt < MTP; ++mt) {
-                const size_t wi = (size_t)(16 * mt + m16) * 64 + 32 * ks + 8 * g;
-                const h8 wh = *(const h8 *)&w16[wi];
-                const h8 wl = *(const h8 *)&w16[(size_t)16 * MTP * 64 + wi];
-                if constexpr (S::kLoLo) pm[mt] = S::mfma(wl, bl, pm[mt]);
-                pm[mt] = S::mfma(wh, bl, pm[mt]);
-                pm[mt] = S::mfma(wl, bh, pm[mt]);
-                pm[mt] = S::mfma(wh, bh, pm[mt]);
+    #pragma unroll
+            for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
+    #pragma unroll 1
+        for (int o = 0; o < 9; ++o) {
+            const int oy = o / 3 - 1, ox = o % 3 - 1;
+            f4 c[4];
+    #pragma unroll
+            for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+            const int boff = bbase + (oy * 10 + ox) * kQ16Leaf;
+            const int aoff = abase + 8 * oy * kT16Row + 8 * ox;
+    #pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const h8 bh = *(const h8 *)&sqh[boff + 32 * ks];
+                const h8 bl = *(const h8 *)&sql[boff + 32 * ks];
+    #pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const int ai = aoff + (4 * ks - 2 * mt) * kT16Row;
+                    const h8 ah = *(const h8 *)&st[0][ai];
+                    const h8 al = *(const h8 *)&st[1][ai];
+                    if constexpr (S::kLoLo) c[mt] = S::mfma(al, bl, c[mt]);
+                    c[mt] = S::mfma(ah, bl, c[mt]);
+                    c[mt] = S::mfma(al, bh, c[mt]);
+                    c[mt] = S::mfma(ah, bh, c[mt]);
+                }
+            }
+    #pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+        }
+        f4 pm[MTP];
+    #pragma unroll
+        for (int mt = 0; mt < MTP; ++mt) pm[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (pp.M) {
+    #pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const h8 bh = *(const h8 *)&sqh[bbase + 32 * ks];
+                const h8 bl = *(const h8 *)&sql[bbase + 32 * ks];
+    #pragma unroll
+                for (int mt = 0; mt < MTP; ++mt) {
+                    const size_t wi = (size_t)(16 * mt + m16) * 64 + 32 * ks + 8 * g;
+                    const h8 wh = *(const h8 *)&w16[wi];
+                    const h8 wl = *(const h8 *)&w16[(size_t)16 * MTP * 64 + wi];
+                    if constexpr (S::kLoLo) pm[mt] = S::mfma(wl, bl, pm[mt]);
+                    pm[mt] = S::mfma(wh, bl, pm[mt]);
+                    pm[mt] = S::mfma(wl, bh, pm[mt]);
+                    pm[mt] = S::mfma(wh, bh, pm[mt]);
+                }
             }
         }
-    }
-    const int gLx = TX0 + lx, gLy = TY0 + ly;
-    if (gLx >= nl || gLy >= nl) return;
-    const double qs = -a.qscale * iscale * kInv2Pi;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        double *ur = pp.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
-    }
-    if (pp.M) {
-        const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
-        double2 *Ml = pp.M + a.lv.off[a.L];
-        const double ms = a.qscale * iscale;
-#pragma unroll
-        for (int mt = 0; mt < MTP; ++mt)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int k = 8 * mt + 2 * g + j;
-                if (k < P)
-                    Ml[k * ncell + cell] = make_double2(ms * (double)pm[mt][2 * j],
-                                                        ms * (double)pm[mt][2 * j + 1]);
+        const int gLx = TX0 + lx, gLy = TY0 + ly;
+        if (gLx < nl && gLy < nl) {
+            const double qs = -a.qscale * iscale * kInv2Pi;
+    #pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                double *ur = pp.u + (size_t)(gLy * 8 + 2 * mt + (g >> 1)) * n + gLx * 8 + 4 * (g & 1);
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) ur[i] = qs * acc[mt][i];
             }
+            if (pp.M) {
+                const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
+                double2 *Ml = pp.M + a.lv.off[a.L];
+                const double ms = a.qscale * iscale;
+    #pragma unroll
+                for (int mt = 0; mt < MTP; ++mt)
+    #pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int k = 8 * mt + 2 * g + j;
+                        if (k < P)
+                            Ml[k * ncell + cell] = make_double2(ms * (double)pm[mt][2 * j],
+                                                                ms * (double)pm[mt][2 * j + 1]);
+                    }
+            }
+        }
     }
 }
 
@@ -1966,11 +1994,11 @@ static int run_m2l_l2l(fmm_plan *pl, const double2 *M, double2 *Lm, double2 *Lt,
                                    items, M, Lm, pl->lm_part, ns, pl->lv, pl->tab.m2ltb16,
                                    pl->tab.m2l_off, pl->nlist, 2 * pl->K, rh);
         } else if (pl->prec != FMM_FP64 && pl->kind == FMM_GRID)
-            hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(768), shm / 2, s, items, M,
+            hipLaunchKernelGGL((k_m2l<P, float>), dim3(nitems, 1, nr), dim3(kM2LThreads), shm / 2, s, items, M,
                                Lm, pl->lm_part, ns, pl->lv, pl->tab.hankl32, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
         else
-            hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems, 1, nr), dim3(768), shm, s, items, M,
+            hipLaunchKernelGGL((k_m2l<P, double>), dim3(nitems, 1, nr), dim3(kM2LThreads), shm, s, items, M,
                                Lm, pl->lm_part, ns, pl->lv, pl->tab.hankl, pl->tab.m2l_off, pl->tab.m2l_a,
                                pl->tab.m2l_b, pl->nlist, 2 * pl->K, rh);
     }
@@ -2043,12 +2071,16 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8, nr);
+        // split 16-bit plans: two blocks per compute unit over all right-hand
+        // sides, each looping over tiles
+        const int ntx = (nl + 7) / 8, ntiles = ntx * ntx;
+        const dim3 g16(std::min(ntiles, std::max(1, (2 * pl->ncu + nr - 1) / nr)), 1, nr);
         if (pl->prec == FMM_SPLIT_FP16)
-            hipLaunchKernelGGL((k_leaf_mfma16<P, _Float16>), gl, dim3(256), 0, s, a, pl->tab.ktab16,
-                               pl->tab.p2m16);
+            hipLaunchKernelGGL((k_leaf_mfma16<P, _Float16>), g16, dim3(256), 0, s, a, pl->tab.ktab16,
+                               pl->tab.p2m16, ntx, ntiles);
         else if (pl->prec == FMM_SPLIT_BF16)
-            hipLaunchKernelGGL((k_leaf_mfma16<P, __bf16>), gl, dim3(256), 0, s, a, pl->tab.ktabb16,
-                               pl->tab.p2mb16);
+            hipLaunchKernelGGL((k_leaf_mfma16<P, __bf16>), g16, dim3(256), 0, s, a, pl->tab.ktabb16,
+                               pl->tab.p2mb16, ntx, ntiles);
         else if (fp32 && pl->K > 1)
             launch_leaf_wide_mfma32<P>(pl, gl, a, s);
         else if (fp32)
