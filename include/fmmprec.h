@@ -288,8 +288,9 @@ int fmm_tune(fmm_plan *plan, void *stream, int32_t *vec_blocks);
  * right-hand sides already multiply the blocks; its results then agree with
  * single calls to rounding rather than bit for bit.
  *   fmm_tune_m2l: times the M2L and downward launches of the plan for each S
- *     on `stream`, keeps the fastest, writes it to *split (HOST, may be
- *     NULL); synchronises `stream`.
+ *     on `stream` (the fastest of three calls, in three rounds over the four
+ *     values), keeps the fastest S, writes it to *split (HOST, may be NULL);
+ *     synchronises `stream`.
  *   fmm_set_m2l_split: sets S (FMM_ERR_ARG otherwise); synchronises the
  *     device (the buffer of M2L sums may grow).
  *   fmm_get_m2l_split: the plan's current S into *split (HOST).

@@ -2184,27 +2184,33 @@ static int tune_m2l_split_p(fmm_plan *pl, hipStream_t s, int *chosen)
     hipEvent_t e0, e1;
     FMM_HIP(pl, hipEventCreate(&e0));
     FMM_HIP(pl, hipEventCreate(&e1));
-    float best_ms = 1e30f;
+    // the fastest of three timed calls per split, over three rounds that
+    // visit the splits in turn (so that a slow phase of the device does not
+    // decide); ties go to the smaller split
+    const int splits[4] = {1, 2, 4, 8};
+    float split_ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+    for (int round = 0; round < 3 && st == FMM_OK; ++round)
+        for (int i = 0; i < 4; ++i) {
+            FMM_HIP(pl, hipStreamSynchronize(s));
+            st = set_m2l_split(pl, splits[i]);
+            if (st != FMM_OK) break;
+            for (int rep = 0; rep < 4; ++rep) {
+                FMM_HIP(pl, hipEventRecord(e0, s));
+                run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, rh, 1, s, false);
+                FMM_HIP(pl, hipEventRecord(e1, s));
+                FMM_HIP(pl, hipEventSynchronize(e1));
+                float t = 0.0f;
+                FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
+                if (rep > 0) split_ms[i] = std::min(split_ms[i], t);
+            }
+        }
     int best = pl->m2l_split;
-    for (int split : {1, 2, 4, 8}) {
-        FMM_HIP(pl, hipStreamSynchronize(s));
-        st = set_m2l_split(pl, split);
-        if (st != FMM_OK) break;
-        float ms = 0.0f;
-        for (int rep = 0; rep < 4; ++rep) {
-            FMM_HIP(pl, hipEventRecord(e0, s));
-            run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, rh, 1, s, false);
-            FMM_HIP(pl, hipEventRecord(e1, s));
-            FMM_HIP(pl, hipEventSynchronize(e1));
-            float t = 0.0f;
-            FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
-            if (rep > 0) ms += t;
+    float best_ms = 1e30f;
+    for (int i = 0; i < 4; ++i)
+        if (split_ms[i] < best_ms) {
+            best_ms = split_ms[i];
+            best = splits[i];
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = split;
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != FMM_OK) return st;
