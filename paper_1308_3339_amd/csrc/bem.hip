@@ -69,65 +69,165 @@ __global__ __launch_bounds__(256) void k_bem_build(double *__restrict__ S0,
     S1[e] = make_double2(C[0] - C[2], C[1] - C[3]);
 }
 
-// Gauss-Jordan inversion without pivoting, one elimination step per pair of
-// launches (row kernel, then update into the other buffer).
-__global__ void k_gj_row_real(const double *__restrict__ A, double *__restrict__ rk, int n, int k)
-{
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double piv = A[(size_t)k * n + k];
-    rk[j] = (j == k) ? 1.0 / piv : A[(size_t)k * n + j] / piv;
-}
+// Blocked Gauss-Jordan inversion in place, without pivoting (the blocks are
+// Hermitian positive definite), in panels of kGjB columns.  With K the
+// panel's index range, D = A[K,K], C = A[:,K] and R = D^-1 A[K,:]:
+//   A[K,K] <- D^-1,  A[K,j] <- R[:,j],  A[i,K] <- -C[i,:] D^-1,
+//   A[i,j] <- A[i,j] - C[i,:] R[:,j]          (i, j outside K),
+// i.e. kGjB unblocked elimination steps at once.  R[:,K] holds D^-1, so the
+// rows i outside K take A[i,j] <- [j outside K] A[i,j] - C[i,:] R[:,j] for
+// every column.  Three launches per panel: D^-1 by one block in LDS, then R
+// and a copy of C, then the rank-kGjB update (64 x 64 output tiles).
+constexpr int kGjB = 32;
 
-__global__ __launch_bounds__(256) void k_gj_upd_real(const double *__restrict__ A,
-                                                     double *__restrict__ B,
-                                                     const double *__restrict__ rk, int n, int k)
-{
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= n || j >= n) return;
-    const size_t e = (size_t)i * n + j;
-    double v;
-    if (i == k) v = rk[j];
-    else if (j == k) v = -A[(size_t)i * n + k] * rk[k];
-    else v = fma(-A[(size_t)i * n + k], rk[j], A[e]);
-    B[e] = v;
-}
+// complex entries as a clang vector of (re, im), the layout of double2
+typedef double gj_c __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ double2 cdiv(double2 a, double2 b)
+__device__ __forceinline__ double gj_mul(double a, double b) { return a * b; }
+__device__ __forceinline__ gj_c gj_mul(gj_c a, gj_c b)
 {
-    const double d = b.x * b.x + b.y * b.y;
-    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+    return gj_c{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
-
-__global__ void k_gj_row_cplx(const double2 *__restrict__ A, double2 *__restrict__ rk, int n, int k)
+__device__ __forceinline__ double gj_fms(double acc, double a, double b) { return fma(-a, b, acc); }
+__device__ __forceinline__ gj_c gj_fms(gj_c acc, gj_c a, gj_c b)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const double2 piv = A[(size_t)k * n + k];
-    rk[j] = (j == k) ? cdiv(make_double2(1.0, 0.0), piv) : cdiv(A[(size_t)k * n + j], piv);
+    return gj_c{fma(-a.x, b.x, fma(a.y, b.y, acc.x)), fma(-a.x, b.y, fma(-a.y, b.x, acc.y))};
 }
-
-__global__ __launch_bounds__(256) void k_gj_upd_cplx(const double2 *__restrict__ A,
-                                                     double2 *__restrict__ B,
-                                                     const double2 *__restrict__ rk, int n, int k)
+__device__ __forceinline__ double gj_inv(double a) { return 1.0 / a; }
+__device__ __forceinline__ gj_c gj_inv(gj_c a)
 {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= n || j >= n) return;
-    const size_t e = (size_t)i * n + j;
-    const double2 aik = A[(size_t)i * n + k];
-    double2 v;
-    if (i == k) {
-        v = rk[j];
-    } else if (j == k) {
-        const double2 r = rk[k];
-        v = make_double2(-(aik.x * r.x - aik.y * r.y), -(aik.x * r.y + aik.y * r.x));
-    } else {
-        const double2 r = rk[j], a = A[e];
-        v = make_double2(a.x - (aik.x * r.x - aik.y * r.y), a.y - (aik.x * r.y + aik.y * r.x));
+    const double d = a.x * a.x + a.y * a.y;
+    return gj_c{a.x / d, -a.y / d};
+}
+template <typename T> __device__ __forceinline__ T gj_zero();
+template <> __device__ __forceinline__ double gj_zero<double>() { return 0.0; }
+template <> __device__ __forceinline__ gj_c gj_zero<gj_c>() { return gj_c{0.0, 0.0}; }
+__device__ __forceinline__ double gj_neg(double a) { return -a; }
+__device__ __forceinline__ gj_c gj_neg(gj_c a) { return -a; }
+
+// D^-1 of the diagonal block at k0 (b = min(kGjB, n) rows) into Dinv [b][b],
+// by b unpivoted elimination steps in LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_diag(const T *__restrict__ A, T *__restrict__ Dinv, int n,
+                                                 int k0, int b)
+{
+    __shared__ T D[kGjB][kGjB + 1];
+    for (int e = threadIdx.x; e < b * b; e += 256) D[e / b][e % b] = A[(size_t)(k0 + e / b) * n + k0 + e % b];
+    __syncthreads();
+    constexpr int NQ = kGjB * kGjB / 256;   // elements per thread at b = kGjB
+    for (int k = 0; k < b; ++k) {
+        const T ip = gj_inv(D[k][k]);
+        T v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            if (e >= b * b) continue;
+            const int r = e / b, c = e % b;
+            if (r == k) v[q] = c == k ? ip : gj_mul(D[k][c], ip);
+            else if (c == k) v[q] = gj_neg(gj_mul(D[r][k], ip));
+            else v[q] = gj_fms(D[r][c], gj_mul(D[r][k], ip), D[k][c]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            if (e < b * b) D[e / b][e % b] = v[q];
+        }
+        __syncthreads();
     }
-    B[e] = v;
+    for (int e = threadIdx.x; e < b * b; e += 256) Dinv[e] = D[e / b][e % b];
+}
+
+// R [b][n] = D^-1 A[K,:] (D^-1 itself in the panel's columns), and the
+// column panel C [n][b] = A[:,K]
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_panel(const T *__restrict__ A, const T *__restrict__ Dinv,
+                                                  T *__restrict__ R, T *__restrict__ C, int n, int k0,
+                                                  int b)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    for (int s = 0; s < b; ++s) C[(size_t)j * b + s] = A[(size_t)j * n + k0 + s];
+    if (j >= k0 && j < k0 + b) {
+        for (int r = 0; r < b; ++r) R[(size_t)r * n + j] = Dinv[r * b + j - k0];
+        return;
+    }
+    // (loops to the compile-time kGjB, so that col stays in registers)
+    T col[kGjB];
+#pragma unroll
+    for (int s = 0; s < kGjB; ++s) col[s] = s < b ? A[(size_t)(k0 + s) * n + j] : gj_zero<T>();
+    for (int r = 0; r < b; ++r) {
+        T acc = gj_zero<T>();
+#pragma unroll
+        for (int s = 0; s < kGjB; ++s)
+            if (s < b) acc = gj_fms(acc, gj_neg(Dinv[r * b + s]), col[s]);
+        R[(size_t)r * n + j] = acc;
+    }
+}
+
+// rows per thread of the update tile: 4 (real), 2 (complex)
+template <typename T> constexpr int gj_rows() { return sizeof(T) == sizeof(double) ? 4 : 2; }
+
+// A <- the panel's elimination, (16 TI) x 64 output tiles (a thread TI x 4
+// of them), C and R tiles in LDS
+template <typename T>
+__global__ __launch_bounds__(256) void k_gj_update(T *__restrict__ A, const T *__restrict__ R,
+                                                   const T *__restrict__ C, int n, int k0, int b)
+{
+    constexpr int TI = gj_rows<T>(), TR = 16 * TI;
+    __shared__ T sc[TR][kGjB + 1], sr[kGjB][64];
+    const int i0 = blockIdx.y * TR, j0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int e = threadIdx.x; e < TR * b; e += 256) {
+        const int r = e / b, s = e % b;
+        sc[r][s] = i0 + r < n ? C[(size_t)(i0 + r) * b + s] : gj_zero<T>();
+    }
+    for (int e = threadIdx.x; e < 64 * b; e += 256) {
+        const int s2 = e / 64, c = e % 64;
+        sr[s2][c] = j0 + c < n ? R[(size_t)s2 * n + j0 + c] : gj_zero<T>();
+    }
+    __syncthreads();
+    T acc[TI][4];
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int i = i0 + TI * ty + ii, j = j0 + 4 * tx + jj;
+            const bool inK = j >= k0 && j < k0 + b;
+            acc[ii][jj] = (i < n && j < n && !inK) ? A[(size_t)i * n + j] : gj_zero<T>();
+        }
+    for (int s = 0; s < b; ++s) {
+        T cv[TI], rv[4];
+#pragma unroll
+        for (int q = 0; q < TI; ++q) cv[q] = sc[TI * ty + q][s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rv[q] = sr[s][4 * tx + q];
+#pragma unroll
+        for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = gj_fms(acc[ii][jj], cv[ii], rv[jj]);
+    }
+#pragma unroll
+    for (int ii = 0; ii < TI; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+            const int i = i0 + TI * ty + ii, j = j0 + 4 * tx + jj;
+            if (i >= n || j >= n) continue;
+            // the panel's own rows take R
+            A[(size_t)i * n + j] = (i >= k0 && i < k0 + b) ? sr[i - k0][4 * tx + jj] : acc[ii][jj];
+        }
+}
+
+template <typename T>
+static void gj_invert(T *A, T *Dinv, T *R, T *C, int n, hipStream_t s)
+{
+    const int b = n < kGjB ? n : kGjB, tr = 16 * gj_rows<T>();
+    const dim3 gu((n + 63) / 64, (n + tr - 1) / tr), gp((n + 255) / 256);
+    for (int k0 = 0; k0 < n; k0 += b) {
+        hipLaunchKernelGGL(k_gj_diag<T>, dim3(1), dim3(256), 0, s, A, Dinv, n, k0, b);
+        hipLaunchKernelGGL(k_gj_panel<T>, gp, dim3(256), 0, s, A, Dinv, R, C, n, k0, b);
+        hipLaunchKernelGGL(k_gj_update<T>, gu, dim3(256), 0, s, A, R, C, n, k0, b);
+    }
 }
 
 // Halves of the folded inverses, each (n/2) x (n/2) row-major, in one
@@ -255,45 +355,33 @@ int bem_setup(fmm_plan *pl, hipStream_t s)
 {
     const int n = (int)pl->n;
     const size_t nn = (size_t)n * n;
-    double2 *tmp = nullptr, *rk = nullptr;
+    double2 *dinv = nullptr, *R = nullptr, *C = nullptr;
+    const int b = n < kGjB ? n : kGjB;
     FMM_HIP(pl, hipMalloc(&pl->X0, nn * sizeof(double)));
     FMM_HIP(pl, hipMalloc(&pl->X2, nn * sizeof(double)));
     FMM_HIP(pl, hipMalloc(&pl->X1, nn * sizeof(double2)));
-    FMM_HIP(pl, hipMalloc(&tmp, nn * sizeof(double2)));
-    FMM_HIP(pl, hipMalloc(&rk, (size_t)n * sizeof(double2)));
-    const dim3 g2((n + 63) / 64, (n + 3) / 4), g1((n + 255) / 256);
+    FMM_HIP(pl, hipMalloc(&dinv, (size_t)b * b * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&R, (size_t)b * n * sizeof(double2)));
+    FMM_HIP(pl, hipMalloc(&C, (size_t)b * n * sizeof(double2)));
+    const dim3 g2((n + 63) / 64, (n + 3) / 4);
     hipLaunchKernelGGL(k_bem_build, g2, dim3(256), 0, s, pl->X0, pl->X2, pl->X1, n);
-    // real blocks
-    for (int b = 0; b < 2; ++b) {
-        double *A = (b == 0) ? pl->X0 : pl->X2;
-        double *B = reinterpret_cast<double *>(tmp);
-        for (int k = 0; k < n; ++k) {
-            hipLaunchKernelGGL(k_gj_row_real, g1, dim3(256), 0, s, A, reinterpret_cast<double *>(rk), n, k);
-            hipLaunchKernelGGL(k_gj_upd_real, g2, dim3(256), 0, s, A, B,
-                               reinterpret_cast<const double *>(rk), n, k);
-            double *t = A; A = B; B = t;
-        }
-        double *dst = (b == 0) ? pl->X0 : pl->X2;
-        if (A != dst) FMM_HIP(pl, hipMemcpyAsync(dst, A, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-    }
-    {
-        double2 *A = pl->X1, *B = tmp;
-        for (int k = 0; k < n; ++k) {
-            hipLaunchKernelGGL(k_gj_row_cplx, g1, dim3(256), 0, s, A, rk, n, k);
-            hipLaunchKernelGGL(k_gj_upd_cplx, g2, dim3(256), 0, s, A, B, rk, n, k);
-            double2 *t = A; A = B; B = t;
-        }
-        if (A != pl->X1)
-            FMM_HIP(pl, hipMemcpyAsync(pl->X1, A, nn * sizeof(double2), hipMemcpyDeviceToDevice, s));
-    }
+    // the real blocks, then the complex one
+    gj_invert<double>(pl->X0, reinterpret_cast<double *>(dinv), reinterpret_cast<double *>(R),
+                      reinterpret_cast<double *>(C), n, s);
+    gj_invert<double>(pl->X2, reinterpret_cast<double *>(dinv), reinterpret_cast<double *>(R),
+                      reinterpret_cast<double *>(C), n, s);
+    static_assert(sizeof(gj_c) == sizeof(double2), "complex layout");
+    gj_invert<gj_c>(reinterpret_cast<gj_c *>(pl->X1), reinterpret_cast<gj_c *>(dinv),
+                    reinterpret_cast<gj_c *>(R), reinterpret_cast<gj_c *>(C), n, s);
     // fold into the even/odd halves and keep only those
     FMM_HIP(pl, hipMalloc(&pl->Xh, (size_t)kHalves * (nn / 4) * sizeof(double)));
     hipLaunchKernelGGL(k_bem_fold, dim3((n / 2 + 63) / 64, (n / 2 + 3) / 4), dim3(256), 0, s,
                        pl->X0, pl->X2, pl->X1, pl->Xh, n);
     FMM_HIP(pl, hipGetLastError());
     FMM_HIP(pl, hipStreamSynchronize(s));
-    FMM_HIP(pl, hipFree(tmp));
-    FMM_HIP(pl, hipFree(rk));
+    FMM_HIP(pl, hipFree(dinv));
+    FMM_HIP(pl, hipFree(R));
+    FMM_HIP(pl, hipFree(C));
     FMM_HIP(pl, hipFree(pl->X0));
     FMM_HIP(pl, hipFree(pl->X2));
     FMM_HIP(pl, hipFree(pl->X1));
