@@ -188,7 +188,13 @@ __global__ __launch_bounds__(256) void k_p2m_points(const double *__restrict__ p
 // 1e-12 of the oracle's libm sums).
 constexpr double kLn2Hi = 0.69314718055994530942;            // nearest double to ln 2
 constexpr double kLn2Lo = 2.3190468138462995584e-17;         // ln 2 - kLn2Hi
-__device__ __forceinline__ double log_pos(double x)
+// 1/19, 1/17, ..., 1/3, the series coefficients, as data: the kernel loads
+// them into scalar registers once (as literals the compiler holds them in
+// vector registers and copies one before each multiply-add of the series)
+__device__ double kSeriesInv[9] = {1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+                                   1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0};
+
+__device__ __forceinline__ double log_pos(double x, const double (&cs)[9])
 {
     int e;
     double m = frexp(x, &e);                 // x = m 2^e, m in [1/2, 1)
@@ -203,15 +209,9 @@ __device__ __forceinline__ double log_pos(double x)
     double sv = a * y;
     sv = fma(fma(-sv, d, a), y, sv);
     const double z = sv * sv;
-    double p = 1.0 / 19.0;
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    double p = cs[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) p = fma(p, z, cs[i]);
     const double s2 = 2.0 * sv;
     const double lm = fma(s2 * z, p, s2);
     const double de = (double)e;
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
                                                      int kxp)
 {
     __shared__ double sx[kChunk], sy[kChunk], sqv[kChunk];
-    __shared__ double red[3][64];
+    __shared__ double red[4][64];
     __shared__ int seg_s[kMaxNearLeaves], seg_p[kMaxNearLeaves + 1];
     const int nl = 1 << L;
     const int m = leaf_of_block(blockIdx.x, nl * nl);
@@ -250,41 +250,60 @@ __global__ __launch_bounds__(256) void k_leaf_points(const double *__restrict__ 
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
     const int nc = near_segments(start, lx, ly, nl, K, kxp, seg_s, seg_p);
     const int ns = seg_p[nc];
-    // targets in slices of 64; sources of the near leaves (the 3x3 block with
-    // the list rule, the disk of radius K with a MAC theta) in chunks through LDS
+    // sources of the near leaves (the 3x3 block with the list rule, the disk
+    // of radius K with a MAC theta) in chunks through LDS, staged once for all
+    // target slices when they fit one chunk
+    auto stage = [&](int cb, int cnt) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            const int j = near_source(seg_s, seg_p, nc, cb + e);
+            sx[e] = px[j];
+            sy[e] = py[j];
+            sqv[e] = qs[j];
+        }
+        __syncthreads();
+    };
+    const bool once = ns <= kChunk;
+    if (once && t1 > t0) stage(0, ns);
+    double cs[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cs[i] = kSeriesInv[i];
+    // targets in slices of up to 64: a slice of r targets gives each target
+    // g = 64 / r lanes (lane = tl g + sub), and lane sub of wave wv takes the
+    // sources e = wv + 4 sub (mod 4 g), so that a short last slice keeps the
+    // lanes busy; a full slice is one target per lane, the sources in quarters
     for (int tb = t0; tb < t1; tb += 64) {
-        const int t = tb + lane;
-        const bool tv = t < t1;
-        const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
+        const int r = min(64, t1 - tb), g = 64 / r;
+        const int tl = lane / g, sub = lane - tl * g;
+        const bool tv = tl < r;
+        const double tx = tv ? px[tb + tl] : 0.0, ty = tv ? py[tb + tl] : 0.0;
         double acc = 0.0;
         for (int cb = 0; cb < ns; cb += kChunk) {
             const int cnt = min(kChunk, ns - cb);
-            __syncthreads();
-            for (int e = threadIdx.x; e < cnt; e += 256) {
-                const int j = near_source(seg_s, seg_p, nc, cb + e);
-                sx[e] = px[j];
-                sy[e] = py[j];
-                sqv[e] = qs[j];
-            }
-            __syncthreads();
+            if (!once) stage(cb, cnt);
             if (tv) {
-                for (int e = wv; e < cnt; e += 4) {
+                for (int e = wv + 4 * sub; e < cnt; e += 4 * g) {
                     const double dx = tx - sx[e], dy = ty - sy[e];
                     const double r2 = dx * dx + dy * dy;
-                    if (r2 > 0.0) acc = fma(sqv[e], log_pos(r2), acc);
+                    if (r2 > 0.0) acc = fma(sqv[e], log_pos(r2, cs), acc);
                 }
             }
         }
-        // sum the four source quarters: ((w0 + w1) + w2) + w3; the pairs summed
+        // per target, the partial sums in a fixed order: waves outer, sub-lanes
+        // inner (a full slice: ((w0 + w1) + w2) + w3); the pairs summed
         // q log r^2, so half of it is the sum of q log r
         __syncthreads();
-        if (wv > 0) red[wv - 1][lane] = acc;
+        red[wv][lane] = acc;
         __syncthreads();
-        if (wv == 0 && tv) {
-            acc = 0.5 * (((acc + red[0][lane]) + red[1][lane]) + red[2][lane]);
+        if (wv == 0 && lane < r) {
+            const int t = tb + lane;
+            double sum = 0.0;
+            for (int w = 0; w < 4; ++w)
+                for (int sb = 0; sb < g; ++sb) sum += red[w][lane * g + sb];
+            acc = 0.5 * sum;
             double farv = 0.0;
             if (far) {
-                const double2 tau = make_double2((tx - cx) * iw, (ty - cy) * iw);
+                const double2 tau = make_double2((px[t] - cx) * iw, (py[t] - cy) * iw);
                 double2 pk = make_double2(1.0, 0.0);
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
@@ -335,7 +354,7 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
                                                          int kxp)
 {
     __shared__ float sx[kChunk], sy[kChunk], sqv[kChunk];
-    __shared__ double red[3][64];
+    __shared__ double red[4][64];
     __shared__ int seg_s[kMaxNearLeaves], seg_p[kMaxNearLeaves + 1];
     const int nl = 1 << L;
     const int m = leaf_of_block(blockIdx.x, nl * nl);
@@ -353,24 +372,31 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
     const double cx = x0 + (lx + 0.5) * w, cy = y0 + (ly + 0.5) * w, iw = 1.0 / w;
     const int nc = near_segments(start, lx, ly, nl, K, kxp, seg_s, seg_p);
     const int ns = seg_p[nc];
+    // sources staged and targets sliced as in k_leaf_points
+    auto stage = [&](int cb, int cnt) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            const int j = near_source(seg_s, seg_p, nc, cb + e);
+            sx[e] = (float)(px[j] - cx);
+            sy[e] = (float)(py[j] - cy);
+            sqv[e] = (float)qs[j];
+        }
+        __syncthreads();
+    };
+    const bool once = ns <= kChunk;
+    if (once && t1 > t0) stage(0, ns);
     for (int tb = t0; tb < t1; tb += 64) {
-        const int t = tb + lane;
-        const bool tv = t < t1;
-        const double tx = tv ? px[t] : 0.0, ty = tv ? py[t] : 0.0;
+        const int r = min(64, t1 - tb), g = 64 / r;
+        const int tl = lane / g, sub = lane - tl * g;
+        const bool tv = tl < r;
+        const double tx = tv ? px[tb + tl] : 0.0, ty = tv ? py[tb + tl] : 0.0;
         const float txf = (float)(tx - cx), tyf = (float)(ty - cy);
         float ks = 0.0f, kc = 0.0f;   // Kahan sum of q log2(r^2) and its compensation
         for (int cb = 0; cb < ns; cb += kChunk) {
             const int cnt = min(kChunk, ns - cb);
-            __syncthreads();
-            for (int e = threadIdx.x; e < cnt; e += 256) {
-                const int j = near_source(seg_s, seg_p, nc, cb + e);
-                sx[e] = (float)(px[j] - cx);
-                sy[e] = (float)(py[j] - cy);
-                sqv[e] = (float)qs[j];
-            }
-            __syncthreads();
+            if (!once) stage(cb, cnt);
             if (tv) {
-                for (int e = wv; e < cnt; e += 4) {
+                for (int e = wv + 4 * sub; e < cnt; e += 4 * g) {
                     const float dx = txf - sx[e], dy = tyf - sy[e];
                     const float r2 = fmaf(dx, dx, dy * dy);
                     if (r2 >= FLT_MIN) {
@@ -382,15 +408,17 @@ __global__ __launch_bounds__(256) void k_leaf_points_f32(const double *__restric
                 }
             }
         }
-        double acc = ((double)ks - (double)kc) * (0.5 * kLn2);
         __syncthreads();
-        if (wv > 0) red[wv - 1][lane] = acc;
+        red[wv][lane] = ((double)ks - (double)kc) * (0.5 * kLn2);
         __syncthreads();
-        if (wv == 0 && tv) {
-            acc = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+        if (wv == 0 && lane < r) {
+            const int t = tb + lane;
+            double acc = 0.0;
+            for (int w = 0; w < 4; ++w)
+                for (int sb = 0; sb < g; ++sb) acc += red[w][lane * g + sb];
             double farv = 0.0;
             if (far) {
-                const double2 tau = make_double2((tx - cx) * iw, (ty - cy) * iw);
+                const double2 tau = make_double2((px[t] - cx) * iw, (py[t] - cy) * iw);
                 double2 pk = make_double2(1.0, 0.0);
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
