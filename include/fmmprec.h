@@ -269,9 +269,10 @@ int precond_gmres_solve_multi(fmm_plan *plan, int32_t nrhs, const double *f, dou
                               void *stream);
 
 /* Autotuner: times the Krylov sweeps of this plan's grid with candidate
- * block counts (64 .. 4096) and keeps the fastest for later solves; the
- * choice is returned in *vec_blocks (HOST, may be NULL).  Synchronises
- * `stream`.  GRID plans only. */
+ * block counts (64 .. 4096; the fastest of three calls each, in three rounds
+ * over the candidates) and keeps the fastest for later solves; the choice is
+ * returned in *vec_blocks (HOST, may be NULL).  Synchronises `stream`.  GRID
+ * plans only. */
 int fmm_tune(fmm_plan *plan, void *stream, int32_t *vec_blocks);
 
 /* M2L tile shape (Sec. 5.3 item 3, the translations of every level in one

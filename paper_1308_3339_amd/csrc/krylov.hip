@@ -1575,8 +1575,10 @@ int gmres_solve_batch(fmm_plan *const *plans, int count, const double *const *f,
 }
 
 // Tunes the block count of the Krylov vector kernels for this plan's grid:
-// times sweep A and B of an Arnoldi step (j = 4) for each candidate and
-// keeps the fastest (small grids want more blocks than elements / 1024).
+// times sweep A and B of an Arnoldi step (j = 4) for each candidate (the
+// fastest of three calls, over three rounds that visit the candidates in
+// turn) and keeps the fastest (small grids want more blocks than
+// elements / 1024).
 int tune_vector_blocks(fmm_plan *pl, hipStream_t s, int *chosen)
 {
     int st = ensure_krylov(pl, 8);
@@ -1591,29 +1593,34 @@ int tune_vector_blocks(fmm_plan *pl, hipStream_t s, int *chosen)
     // a finite basis to sweep over (values do not affect the timing)
     hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->V, pl->V, nullptr, 0.0, pl->ldb * 6);
     hipLaunchKernelGGL(k_scale, dim3(256), dim3(256), 0, s, pl->Z, pl->Z, nullptr, 0.0, N);
+    constexpr int NC = sizeof(cands) / sizeof(cands[0]);
+    float cand_ms[NC];
+    for (int i = 0; i < NC; ++i) cand_ms[i] = 1e30f;
+    for (int round = 0; round < 3; ++round)
+        for (int i = 0; i < NC; ++i) {
+            const int c = cands[i];
+            if ((int64_t)c * 256 > 4 * N && c > 64) continue;   // under 4 elements per thread
+            const int nb = c > kRedBlocks ? kRedBlocks : c;
+            for (int rep = 0; rep < 4; ++rep) {
+                FMM_HIP(pl, hipEventRecord(e0, s));
+                launch_arnoldi_dots<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->partial, n, ln, ih2,
+                                           Faces{nullptr, nullptr});
+                launch_arnoldi_update<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->dscal + kCoef, n,
+                                             ln, ih2, Faces{nullptr, nullptr});
+                FMM_HIP(pl, hipEventRecord(e1, s));
+                FMM_HIP(pl, hipEventSynchronize(e1));
+                float t = 0.0f;
+                FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
+                if (rep > 0) cand_ms[i] = std::min(cand_ms[i], t);
+            }
+        }
     float best_ms = 1e30f;
     int best = red_blocks(nullptr, N);
-    for (int c : cands) {
-        if ((int64_t)c * 256 > 4 * N && c > 64) continue;   // under 4 elements per thread
-        const int nb = c > kRedBlocks ? kRedBlocks : c;
-        float ms = 0.0f;
-        for (int rep = 0; rep < 3; ++rep) {
-            FMM_HIP(pl, hipEventRecord(e0, s));
-            launch_arnoldi_dots<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->partial, n, ln, ih2,
-                                       Faces{nullptr, nullptr});
-            launch_arnoldi_update<false>(4, dim3(nb), s, pl->Z, pl->V, pl->ldb, pl->dscal + kCoef, n, ln,
-                                         ih2, Faces{nullptr, nullptr});
-            FMM_HIP(pl, hipEventRecord(e1, s));
-            FMM_HIP(pl, hipEventSynchronize(e1));
-            float t = 0.0f;
-            FMM_HIP(pl, hipEventElapsedTime(&t, e0, e1));
-            if (rep > 0) ms += t;
+    for (int i = 0; i < NC; ++i)
+        if (cand_ms[i] < best_ms) {
+            best_ms = cand_ms[i];
+            best = cands[i] > kRedBlocks ? kRedBlocks : cands[i];
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = nb;
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (pl->vec_blocks != best) drop_step_graphs(pl);
