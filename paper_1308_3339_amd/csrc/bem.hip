@@ -138,31 +138,29 @@ __global__ __launch_bounds__(256) void k_gj_diag(const T *__restrict__ A, T *__r
     for (int e = threadIdx.x; e < b * b; e += 256) Dinv[e] = D[e / b][e % b];
 }
 
-// R [b][n] = D^-1 A[K,:] (D^-1 itself in the panel's columns), and the
-// column panel C [n][b] = A[:,K]
+// R [b][n] = D^-1 A[K,:] (D^-1 itself in the panel's columns), a thread
+// per (r, j): r = 4 blockIdx.y + wave, j = 64 blockIdx.x + lane; the blocks
+// of blockIdx.y = 0 also copy the column panel C [n][b] = A[:,K]
 template <typename T>
 __global__ __launch_bounds__(256) void k_gj_panel(const T *__restrict__ A, const T *__restrict__ Dinv,
                                                   T *__restrict__ R, T *__restrict__ C, int n, int k0,
                                                   int b)
 {
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (j >= n) return;
-    for (int s = 0; s < b; ++s) C[(size_t)j * b + s] = A[(size_t)j * n + k0 + s];
-    if (j >= k0 && j < k0 + b) {
-        for (int r = 0; r < b; ++r) R[(size_t)r * n + j] = Dinv[r * b + j - k0];
-        return;
+    if (r < b) {
+        T v;
+        if (j >= k0 && j < k0 + b) {
+            v = Dinv[r * b + j - k0];
+        } else {
+            v = gj_zero<T>();
+            for (int s = 0; s < b; ++s) v = gj_fms(v, gj_neg(Dinv[r * b + s]), A[(size_t)(k0 + s) * n + j]);
+        }
+        R[(size_t)r * n + j] = v;
     }
-    // (loops to the compile-time kGjB, so that col stays in registers)
-    T col[kGjB];
-#pragma unroll
-    for (int s = 0; s < kGjB; ++s) col[s] = s < b ? A[(size_t)(k0 + s) * n + j] : gj_zero<T>();
-    for (int r = 0; r < b; ++r) {
-        T acc = gj_zero<T>();
-#pragma unroll
-        for (int s = 0; s < kGjB; ++s)
-            if (s < b) acc = gj_fms(acc, gj_neg(Dinv[r * b + s]), col[s]);
-        R[(size_t)r * n + j] = acc;
-    }
+    if (blockIdx.y == 0 && (threadIdx.x >> 6) == 0)
+        for (int s = 0; s < b; ++s) C[(size_t)j * b + s] = A[(size_t)j * n + k0 + s];
 }
 
 // rows per thread of the update tile: 4 (real), 2 (complex)
@@ -222,7 +220,7 @@ template <typename T>
 static void gj_invert(T *A, T *Dinv, T *R, T *C, int n, hipStream_t s)
 {
     const int b = n < kGjB ? n : kGjB, tr = 16 * gj_rows<T>();
-    const dim3 gu((n + 63) / 64, (n + tr - 1) / tr), gp((n + 255) / 256);
+    const dim3 gu((n + 63) / 64, (n + tr - 1) / tr), gp((n + 63) / 64, (b + 3) / 4);
     for (int k0 = 0; k0 < n; k0 += b) {
         hipLaunchKernelGGL(k_gj_diag<T>, dim3(1), dim3(256), 0, s, A, Dinv, n, k0, b);
         hipLaunchKernelGGL(k_gj_panel<T>, gp, dim3(256), 0, s, A, Dinv, R, C, n, k0, b);
