@@ -102,6 +102,39 @@ def test_points_clustered_and_on_the_boundary():
     assert np.abs(ug2 - uo2).max() <= 1e-12 * np.abs(uo2).max()
 
 
+@pytest.mark.parametrize("prec", ["FMM_FP64", "FMM_FP32"])
+def test_points_leaf_populations_around_the_target_slices(prec):
+    """Leaves holding 1, 63, 64, 65, 100, 127, 128, 129, 190 and 257 points:
+    the leaf kernels take targets in slices of 64 and give the r targets of a
+    short slice 64 / r lanes each (sources split among them), so each count
+    exercises a different lane split; against the oracle FMM (FP64 plans at
+    1e-12, FP32 plans at their 1e-5 bar)."""
+    fp = _fp()
+    import torch
+    say("case points leaf populations %s" % prec)
+    rng = np.random.default_rng(41)
+    L = 3                                   # 8 x 8 leaves of width 1/8
+    counts = [1, 63, 64, 65, 100, 127, 128, 129, 190, 257]
+    xs, ys = [], []
+    leaves = [(0, 0), (2, 1), (4, 2), (6, 3), (1, 4), (3, 5), (5, 6), (7, 7), (0, 6), (7, 0)]
+    for (lx, ly), c in zip(leaves, counts):
+        xs.append((lx + rng.uniform(0.05, 0.95, c)) / 8)
+        ys.append((ly + rng.uniform(0.05, 0.95, c)) / 8)
+    x, y = np.concatenate(xs), np.concatenate(ys)
+    N = len(x)
+    assert levels(N) == L
+    q = rng.uniform(-1, 1, N)
+    with fp.fmm_setup(kind=fp.FMM_POINTS, n=N, p=10, x=dev(x), y=dev(y),
+                      prec=getattr(fp, prec)) as plan:
+        u = torch.empty(N, dtype=torch.float64, device="cuda")
+        plan.apply(dev(q), u)
+        ug = host(u)
+    uo = o.fmm(L, 0.0, 0.0, 1.0, 10, x, y, q, x, y, 0.0)
+    err = np.abs(ug - uo).max() / np.abs(uo).max()
+    say("  N=%d max rel err vs oracle FMM %.3e" % (N, err))
+    assert err <= (1e-12 if prec == "FMM_FP64" else 1e-5)
+
+
 def test_points_multi_rhs_and_determinism():
     say("case points nrhs=2")
     N = 5000
