@@ -1234,6 +1234,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
 // of the lists, 12 waves = 4 parity classes x 3 thirds of the share, the
 // thirds summed in LDS in a fixed order.  LDS: the tile's sources as [cell]
 // [KP] hi and lo halves, then M~_0 of every cell in FP64 (for the log w term).
+// Six waves per SIMD (at most 80 VGPRs) let two 12-wave blocks share a CU.
 // ---------------------------------------------------------------------------
 // largest share of one class's list a k_m2l_mfma16 block takes (the list
 // rule's 27 entries at split 1)
@@ -1251,7 +1252,7 @@ constexpr size_t m2l16_lds(int rw)
 }
 
 template <int P, typename H>
-__global__ __launch_bounds__(768) void k_m2l_mfma16(const M2LItem *__restrict__ items,
+__global__ __launch_bounds__(768, P <= 12 ? 6 : 1) void k_m2l_mfma16(const M2LItem *__restrict__ items,
                                                     const double2 *__restrict__ M,
                                                     double2 *__restrict__ Lm, int64_t lm_part,
                                                     int nsplit, LevelInfo lv,
