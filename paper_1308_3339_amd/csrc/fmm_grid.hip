@@ -896,7 +896,15 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
     const int n = a.n, nl = a.nl;
     const int TX0 = blockIdx.x * 8, TY0 = blockIdx.y * 8;
     const int X0 = (TX0 - K) * 8, Y0 = (TY0 - K) * 8;
-    constexpr int PW = 8 * TW, NE = PW * PW, NB = 8;
+    constexpr int PW = 8 * TW, NE = PW * PW, NB = 8, NT = (KS * KS + 255) / 256;
+    // the kernel table's loads are all issued before the charge tile's, and
+    // stored once those are in
+    float w[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int e = tid + 256 * i;
+        w[i] = e < KS * KS ? kt32[e] : 0.0f;
+    }
 #pragma unroll 1
     for (int base = 0; base < NE; base += 256 * NB) {
         float v[NB];
@@ -915,7 +923,11 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
             if (e < NE) sq[(pos >> 2) * PS + (yy >> 3) * 72 + (pos & 3) * 16 + (xx >> 3)] = v[i];
         }
     }
-    for (int e = tid; e < KS * KS; e += 256) st[(e / KS) * TS + e % KS] = kt32[e];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int e = tid + 256 * i;
+        if (e < KS * KS) st[(e / KS) * TS + e % KS] = w[i];
+    }
     __syncthreads();
     const int g = lane >> 4, m16 = lane & 15;
     const int lx = m16 & 7, ly = 2 * wave + (m16 >> 3);   // leaf of this lane's B column
@@ -1066,12 +1078,16 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
-    // kernel table: 2 x 8 copies of 31 rows x 40 halves, copied in 16-byte units
-    for (int e = tid; e < 2 * 8 * 31 * 5; e += 256) {
-        const int part = e / (8 * 31 * 5), rem = e - part * (8 * 31 * 5);
-        const int c = rem / (31 * 5), r = (rem / 5) % 31, q8 = rem % 5;
-        *(h8 *)&st[part][c * kT16Pitch + r * kT16Row + 8 * q8] =
-            *(const h8 *)&kt16[((size_t)(part * 8 + c) * 31 + r) * kT16Row + 8 * q8];
+    // kernel table: 2 x 8 copies of 31 rows x 40 halves, contiguous in global
+    // memory and copied in 16-byte units (unit e = halves 8e..8e+7, copy
+    // e / 155), each copy padded to kT16Pitch halves in LDS.  A thread issues
+    // all its table loads and the first tile's charge loads before it waits.
+    constexpr int kTabUnits = 2 * 8 * kT16Copy / 8, kTabIt = (kTabUnits + 255) / 256;
+    h8 tb[kTabIt];
+#pragma unroll
+    for (int i = 0; i < kTabIt; ++i) {
+        const int e = tid + 256 * i;
+        if (e < kTabUnits) tb[i] = *(const h8 *)&kt16[8 * e];
     }
     double v[4][8];
     auto load = [&](int t) {
@@ -1089,6 +1105,12 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
         }
     };
     load(blockIdx.x);
+    H *const stp = &st[0][0];
+#pragma unroll
+    for (int i = 0; i < kTabIt; ++i) {
+        const int e = tid + 256 * i;
+        if (e < kTabUnits) *(h8 *)&stp[8 * e + (kT16Pitch - kT16Copy) * (e / (kT16Copy / 8))] = tb[i];
+    }
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int TX0 = (t % ntx) * 8, TY0 = (t / ntx) * 8;
         double mx = 0.0;
