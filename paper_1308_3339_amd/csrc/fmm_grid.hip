@@ -1019,10 +1019,13 @@ __global__ __launch_bounds__(256) void k_leaf_wide_mfma32(LeafArgs a, const floa
 // column 8 ox - tx + 15; T sits in LDS in 8 copies shifted by c = 7 - tx
 // columns so that this start is 16-byte aligned, rows 20 dwords apart and
 // copies 648 dwords apart (= 8 mod 64), which spreads a 16-lane read over
-// distinct banks.  The q tile is [leaf][pos] with 72 halves per leaf.  MFMA
-// lane layout (16x16x32, both types): A[l%16][8(l/16)+i], B[8(l/16)+i][l%16],
-// D[4(l/16)+i][l%16].
-constexpr int kT16Row = 40, kT16Copy = 31 * 40, kT16Pitch = 1296, kQ16Leaf = 72;
+// distinct banks.  The q tile is [leaf row][leaf][pos] with 72 halves per
+// leaf and 832 per leaf row (10 leaves and 112 halves of padding): a 16-lane
+// B read covers two adjacent leaf rows of 8 leaves, and a row pitch of 416
+// dwords (32 mod 64) puts the second row's 16-byte reads on the banks the
+// first row's leave free.  MFMA lane layout (16x16x32, both types):
+// A[l%16][8(l/16)+i], B[8(l/16)+i][l%16], D[4(l/16)+i][l%16].
+constexpr int kT16Row = 40, kT16Copy = 31 * 40, kT16Pitch = 1296, kQ16Leaf = 72, kQ16RowP = 832;
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
@@ -1073,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
     typedef f4_t f4;
     constexpr int MTP = (2 * P + 15) / 16;
     __shared__ __align__(16) H st[2][8 * kT16Pitch];
-    __shared__ __align__(16) H sqh[100 * kQ16Leaf], sql[100 * kQ16Leaf];
+    __shared__ __align__(16) H sqh[10 * kQ16RowP], sql[10 * kQ16RowP];
     __shared__ double smax[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1133,7 +1136,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
             const int sg = tid + 256 * i;
             if (sg < 800) {
                 const int yy = sg / 10, jx = sg - yy * 10;
-                const int at = ((yy >> 3) * 10 + jx) * kQ16Leaf + (yy & 7) * 8;
+                const int at = (yy >> 3) * kQ16RowP + jx * kQ16Leaf + (yy & 7) * 8;
                 h8 vh, vl;
     #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -1155,7 +1158,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
         //    source rows sy = 4 ks + g, columns from 8 ox - tx + 15 in copy 7 - tx
         const int tx = lane & 7, tyb = (lane >> 3) & 1;
         const int abase = (7 - tx) * kT16Pitch + (15 - tyb + g) * kT16Row + 8;
-        const int bbase = ((ly + 1) * 10 + lx + 1) * kQ16Leaf + 8 * g;
+        const int bbase = (ly + 1) * kQ16RowP + (lx + 1) * kQ16Leaf + 8 * g;
         double acc[4][4];
     #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
@@ -1167,7 +1170,7 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
             f4 c[4];
     #pragma unroll
             for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int boff = bbase + (oy * 10 + ox) * kQ16Leaf;
+            const int boff = bbase + oy * kQ16RowP + ox * kQ16Leaf;
             const int aoff = abase + 8 * oy * kT16Row + 8 * ox;
     #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
