@@ -484,8 +484,6 @@ __global__ __launch_bounds__(256) void k_down(const double2 *__restrict__ Lm, in
 // serves target row w of every leaf (8 targets per lane).  For a fixed
 // source position all lanes need the same T values, so T rows are read with
 // scalar loads and broadcast, and the q tile sits in LDS as [pos][leaf].
-// On full tiles (p <= 10) the block also takes the tile's multipoles three
-// levels up (M2M, Sec. 5.3), the first launch of the upward pass otherwise.
 // Launch bounds of six waves per SIMD (at most 80 VGPRs: three blocks per CU).
 // ---------------------------------------------------------------------------
 // LDS layout of the 10x10-leaf q tile of the leaf kernels.  Source position
@@ -512,7 +510,6 @@ struct LeafArgs {
     const double2 *l2p;   // [64][P]
     double2 *M;           // leaf multipoles written by the FP64 leaf kernel (null: no P2M)
     const double2 *p2m;   // [P][64]
-    const double2 *m2m;   // M2M table: the FP64 leaf kernel also lifts its tile three levels (null: no)
     LevelInfo lv;
     int n, nl, L, far;
     // near set (Sec. 5.2): radius K leaves; leaves (a, b) with |a| <= kx(|b|)
@@ -548,22 +545,12 @@ __device__ __forceinline__ LeafPtrs rhs_ptrs(const LeafArgs &a)
     return p;
 }
 
-// whether k_leaf_grid<P> lifts its tile's multipoles three levels itself, in
-// the LDS of its charge tile (the M2M table and the tile's four levels fit it
-// up to p = 18): at p <= 10, where the lift's registers keep the kernel at six
-// waves per SIMD without scratch
-template <int P>
-constexpr bool leaf_lifts_tile()
-{
-    return P <= 10 && (4 * P * P + 85 * P) * 16 <= 6400 * 8;
-}
-
 template <int P>
 __global__ __launch_bounds__(512, 6) void k_leaf_grid(LeafArgs a)
 {
     const LeafPtrs pp = rhs_ptrs(a);
     if (!pp.on) return;
-    __shared__ __align__(16) double sq[6400];
+    __shared__ double sq[6400];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = a.n, nl = a.nl;
@@ -614,24 +601,11 @@ __global__ __launch_bounds__(512, 6) void k_leaf_grid(LeafArgs a)
             }
         }
     }
-    const bool lift = leaf_lifts_tile<P>() && a.m2m;   // the tile is full and lifted (below)
-    if (lift) {
-        // u first, so that its stores drain during the lift
-        const double qs = -a.qscale * kInv2Pi;
-        double *ur = pp.u + (size_t)(gLy * 8 + ty) * n + gLx * 8;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) ur[t] = qs * acc[t];
-    }
     if (pp.M) {
         // P2M: wave w computes coefficients w, w + 8, ... of the 64 leaves
         const int64_t ncell = (int64_t)nl * nl, cell = (int64_t)gLy * nl + gLx;
         double2 *Ml = pp.M + a.lv.off[a.L];
-        constexpr int KW = (P + 7) / 8;
-        double2 mk[KW];
-#pragma unroll
-        for (int i = 0; i < KW; ++i) {
-            const int k = wave + 8 * i;
-            if (k >= P) break;
+        for (int k = wave; k < P; k += 8) {
             const double2 *__restrict__ Wk = a.p2m + k * 64;
             double mx = 0.0, my = 0.0;
 #pragma unroll 8
@@ -641,38 +615,7 @@ __global__ __launch_bounds__(512, 6) void k_leaf_grid(LeafArgs a)
                 mx = fma(w.x, v, mx);
                 my = fma(w.y, v, my);
             }
-            mk[i] = make_double2(mx * a.qscale, my * a.qscale);
-            if (active) Ml[k * ncell + cell] = mk[i];
-        }
-        if constexpr (leaf_lifts_tile<P>()) {
-            if (lift) {
-                // M2M of the tile (a full 8 x 8 leaves: the host sets m2m only then)
-                // three levels up, as k_m2m_up would from the stored leaf level,
-                // in the charge tile's LDS once every wave is done reading it
-                constexpr int NA = (4 * P * P + 511) / 512;
-                double2 va[NA];
-#pragma unroll
-                for (int r = 0; r < NA; ++r) {
-                    const int t = tid + 512 * r;
-                    if (t < 4 * P * P) va[r] = a.m2m[t];
-                }
-                __syncthreads();
-                double2 *sA = reinterpret_cast<double2 *>(sq), *s0 = sA + 4 * P * P;
-                double2 *s1 = s0 + P * 64, *s2 = s1 + P * 16, *s3 = s2 + P * 4;
-#pragma unroll
-                for (int r = 0; r < NA; ++r) {
-                    const int t = tid + 512 * r;
-                    if (t < 4 * P * P) sA[t] = va[r];
-                }
-#pragma unroll
-                for (int i = 0; i < KW; ++i) {
-                    const int k = wave + 8 * i;
-                    if (k < P) s0[k * 64 + lane] = mk[i];
-                }
-                __syncthreads();
-                m2m_chain<P>(sA, s0, s1, s2, s3, pp.M, a.lv, a.L, 8, TX0, TY0);
-                return;
-            }
+            if (active) Ml[k * ncell + cell] = make_double2(mx * a.qscale, my * a.qscale);
         }
     }
     if (!active) return;
@@ -2108,7 +2051,6 @@ static LeafArgs leaf_args(fmm_plan *pl, const double *q, double qscale, double *
     a.l2p = pl->tab.l2p;
     a.M = nullptr;
     a.p2m = pl->tab.p2m;
-    a.m2m = nullptr;
     a.lv = pl->lv;
     a.n = (int)pl->n;
     a.nl = pl->nl;
@@ -2153,7 +2095,6 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
     const bool fp32 = pl->prec == FMM_FP32;
     LeafArgs a = leaf_args(pl, q, qscale, u, pl->ws.Lt, far, rh);
     if (far) a.M = pl->ws.M;
-    int m2m_from = pl->L;   // the level the upward pass starts from
     {
         StageTimer t(pl, FMM_STAGE_LEAF, s);
         dim3 gl((nl + 7) / 8, (nl + 7) / 8, nr);
@@ -2174,20 +2115,13 @@ static int grid_volume_fmm_p(fmm_plan *pl, const double *q, double qscale, doubl
                                pl->tab.p2m32);
         else if (pl->K > 1)
             launch_leaf_wide<P>(pl, gl, a, s);
-        else {
-            // full 8 x 8-leaf tiles: the leaf kernel also lifts each tile's
-            // multipoles three levels, and the upward pass starts above them
-            if (far && nl >= 8 && leaf_lifts_tile<P>()) {
-                a.m2m = pl->tab.m2m;
-                m2m_from = std::max(2, pl->L - 3);
-            }
+        else
             hipLaunchKernelGGL(k_leaf_grid<P>, gl, dim3(512), 0, s, a);
-        }
     }
     if (far) {
         {
             StageTimer t(pl, FMM_STAGE_M2M, s);
-            run_m2m_from<P>(pl, pl->ws.M, m2m_from, rh, nr, s);
+            run_m2m_from<P>(pl, pl->ws.M, pl->L, rh, nr, s);
         }
         run_m2l_l2l<P>(pl, pl->ws.M, pl->ws.Lm, pl->ws.Lt, rh, nr, s, true);
     }
