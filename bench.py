@@ -103,7 +103,7 @@ def leaf_kernel_hash():
     closing brace), so that only a change of that kernel invalidates the
     committed counter summary."""
     src = open(os.path.join(ROOT, "paper_1308_3339_amd", "csrc", "fmm_grid.hip")).read()
-    i = src.index("__global__ __launch_bounds__(512) void k_leaf_grid(")
+    i = src.rindex("\n", 0, src.index(" void k_leaf_grid(LeafArgs a)")) + 1
     j = src.index("\n}\n", i)
     return hashlib.sha256(src[i:j].encode()).hexdigest()
 

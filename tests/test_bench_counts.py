@@ -31,3 +31,12 @@ def test_leaf_pair_count_matches_oracle_lists(L):
     n, p = 8 << L, 10
     near_flops = bench.leaf_kernel_flops(n, p) - 4.0 * p * n * n
     assert near_flops == 2.0 * 64 * 64 * len(p2p)
+
+
+def test_kernel_source_hashes_find_their_kernels():
+    # the committed counter summaries are tied to these hashes: each lookup
+    # must find its kernel's declaration in the current sources
+    h = bench.leaf_kernel_hash()
+    assert len(h) == 64
+    for fname, head in bench.POINTS_HEADS.values():
+        assert len(bench.kernel_source_hash(fname, head)) == 64
