@@ -1165,33 +1165,57 @@ __global__ __launch_bounds__(256) void k_leaf_mfma16(LeafArgs a, const H *__rest
         for (int mt = 0; mt < 4; ++mt)
     #pragma unroll
             for (int i = 0; i < 4; ++i) acc[mt][i] = 0.0;
+        // leaf offsets column by column (ox), rows oy = -1, 0, 1 within: the A
+        // fragment of (oy, ks, mt) is T row shift 8 oy + 4 ks - 2 mt, so one
+        // offset row takes 6 distinct fragments and the next row shares 2 of
+        // them, which stay in registers (fh, fl: shifts 8 oy - 6 .. 8 oy + 4)
     #pragma unroll 1
-        for (int o = 0; o < 9; ++o) {
-            const int oy = o / 3 - 1, ox = o % 3 - 1;
-            f4 c[4];
+        for (int ox = -1; ox <= 1; ++ox) {
+            h8 fh[6], fl[6];
+            const int acol = abase + 8 * ox;
     #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-            const int boff = bbase + oy * kQ16RowP + ox * kQ16Leaf;
-            const int aoff = abase + 8 * oy * kT16Row + 8 * ox;
-    #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const h8 bh = *(const h8 *)&sqh[boff + 32 * ks];
-                const h8 bl = *(const h8 *)&sql[boff + 32 * ks];
-    #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    const int ai = aoff + (4 * ks - 2 * mt) * kT16Row;
-                    const h8 ah = *(const h8 *)&st[0][ai];
-                    const h8 al = *(const h8 *)&st[1][ai];
-                    if constexpr (S::kLoLo) c[mt] = S::mfma(al, bl, c[mt]);
-                    c[mt] = S::mfma(ah, bl, c[mt]);
-                    c[mt] = S::mfma(al, bh, c[mt]);
-                    c[mt] = S::mfma(ah, bh, c[mt]);
-                }
+            for (int f = 0; f < 6; ++f) {
+                fh[f] = *(const h8 *)&st[0][acol + (2 * f - 14) * kT16Row];
+                fl[f] = *(const h8 *)&st[1][acol + (2 * f - 14) * kT16Row];
             }
     #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int oyi = 0; oyi < 3; ++oyi) {
+                const int oy = oyi - 1;
+                if (oyi > 0) {
     #pragma unroll
-                for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+                    for (int f = 0; f < 2; ++f) {
+                        fh[f] = fh[f + 4];
+                        fl[f] = fl[f + 4];
+                    }
+    #pragma unroll
+                    for (int f = 2; f < 6; ++f) {
+                        const int ai = acol + (8 * oy + 2 * f - 6) * kT16Row;
+                        fh[f] = *(const h8 *)&st[0][ai];
+                        fl[f] = *(const h8 *)&st[1][ai];
+                    }
+                }
+                f4 c[4];
+    #pragma unroll
+                for (int mt = 0; mt < 4; ++mt) c[mt] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                const int boff = bbase + oy * kQ16RowP + ox * kQ16Leaf;
+    #pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const h8 bh = *(const h8 *)&sqh[boff + 32 * ks];
+                    const h8 bl = *(const h8 *)&sql[boff + 32 * ks];
+    #pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) {
+                        const h8 ah = fh[2 * ks - mt + 3], al = fl[2 * ks - mt + 3];
+                        if constexpr (S::kLoLo) c[mt] = S::mfma(al, bl, c[mt]);
+                        c[mt] = S::mfma(ah, bl, c[mt]);
+                        c[mt] = S::mfma(al, bh, c[mt]);
+                        c[mt] = S::mfma(ah, bh, c[mt]);
+                    }
+                }
+    #pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[mt][i] += (double)c[mt][i];
+            }
         }
         f4 pm[MTP];
     #pragma unroll
